@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark of the ADMM hot path on one MI355X.
+
+Workload: one plain instance with m = 4 sources and n = 262144 steps
+(1,048,576 quartics per x-step), coefficients drawn as f2 ~ U[0.1, 1],
+f1 ~ U[-1, 1], g2 ~ U[0.01, 0.1], g1 ~ U[0.8, 1.2], bounds [0, 2],
+y ~ U[0.5, 1.5], c = 0.7 sum_k g(2), rho = 1 (seed 2).  The inputs are
+uploaded to HBM before the timed region.
+
+A step is one whole ADMM iteration (7a)-(7i): the fused x/s/mu sweep and the
+finalize kernel with the z/lambda/h/p/consensus updates, with the residuals
+checked every 10 iterations.  `value` is iterations per second over exactly
+--steps iterations.  Also reported: per-kernel times from HIP events on the
+library's stream (roofline of the sweep kernel), a solve to the residual
+threshold (iterations and solves per second), the FP64 variant, and the FP64
+oracle timed on the host's cores.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ADMM iters/s & solves/s at residual 1e-4 (plain vs batched/served); p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def to_device(p, dtype):
+    import numpy as np
+    import torch
+    from paper_1903_10041_amd import workloads as W
+    dev = torch.device("cuda:0")
+    kw = {}
+    for k, v in vars(p).items():
+        if isinstance(v, np.ndarray) and k != "c":
+            kw[k] = torch.from_numpy(v).to(device=dev, dtype=dtype).contiguous()
+        else:
+            kw[k] = v
+    return W.Problem(**kw)
+
+
+def sweep_bytes(m, n, q, word):
+    """Algorithmic bytes of one sweep launch: per element 4 coefficient words
+    + x read + x write; per column y + w read + w write."""
+    E, K = m * n * q, n * q
+    return word * (6 * E + 3 * K)
+
+
+def run_gpu(args, precision_name):
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+
+    prec = admm.F32_MIXED if precision_name == "f32" else admm.F64
+    tdt = torch.float32 if precision_name == "f32" else torch.float64
+    word = 4 if precision_name == "f32" else 8
+    p = W.large_c2(n=args.n, m=args.m)
+    pd = to_device(p, tdt)
+    torch.cuda.synchronize()
+    ctx = admm.Context(0)
+
+    def fixed(iters):
+        return admm.Settings(rho=p.rho, max_iter=iters, eps_primal=0.0, eps_dual=0.0,
+                             precision=prec)
+
+    ctx.solve(pd, fixed(max(1, args.warmup)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info, _ = ctx.solve(pd, fixed(args.steps))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert info["iters"] == args.steps, info
+    wall = t1 - t0
+    res = {"iters_per_s": args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
+           "device_ms": info["device_ms"]}
+
+    prof = admm.admm_profile(ctx, pd, fixed(1), iters=args.profile_iters)
+    byts = sweep_bytes(p.m, p.n, p.q, word)
+    achieved = byts / (prof["sweep_us"] * 1e-6) / 1e9
+    res["kernel_us"] = {"sweep": prof["sweep_us"], "finalize": prof["finalize_us"],
+                        "graph_iteration": prof["graph_iter_us"]}
+    res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                       "bytes_per_launch": byts, "kernel": "k_sweep"}
+
+    if not args.skip_converge:
+        eps = 1e-4 if precision_name == "f32" else 1e-6
+        s = admm.Settings(rho=p.rho, max_iter=args.converge_max_iter, eps_primal=eps, eps_dual=eps,
+                          precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, _ = ctx.solve(pd, s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res["solve"] = {"residual": eps, "status": info["status"], "iters": info["iters"],
+                        "r": info["r"], "sigma": info["sigma"], "objective": info["objective"],
+                        "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
+    ctx.close()
+    return res
+
+
+def cpu_baseline(args):
+    import oracle
+    from paper_1903_10041_amd import workloads as W
+    p = W.large_c2(n=args.n, m=args.m)
+    nt = max(1, min(16, os.cpu_count() or 1))
+    st = oracle.init_state(p)
+    t0 = time.perf_counter()
+    st, _, _ = oracle.run(p, max_iter=3, state=st, nthreads=nt)
+    one = (time.perf_counter() - t0) / 3
+    iters = max(1, int(args.cpu_seconds / max(one, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.run(p, max_iter=iters, state=st, nthreads=nt)
+    dt = time.perf_counter() - t0
+    return {"value": iters / dt, "unit": "iters/s", "cores": nt, "kind": "oracle",
+            "sample": f"FP64 oracle, same m={p.m} n={p.n} instance, {iters} iterations "
+                      f"({dt:.1f} s) after three warm-up iterations, OpenMP x-step on {nt} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--m", type=int, default=4)
+    ap.add_argument("--profile-iters", type=int, default=400)
+    ap.add_argument("--converge-max-iter", type=int, default=200000)
+    ap.add_argument("--skip-converge", action="store_true")
+    ap.add_argument("--skip-variant", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU run would shard instances or scenarios, see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1903_10041_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    head = run_gpu(args, args.precision)
+    other = "f64" if args.precision == "f32" else "f32"
+    variant = None
+    if not args.skip_variant:
+        a2 = argparse.Namespace(**vars(args))
+        a2.steps = max(100, args.steps // 2)
+        variant = run_gpu(a2, other)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+
+    storage = {"f32": "f32 storage, f64 arithmetic", "f64": "f64"}
+    line = {
+        "metric": METRIC,
+        "value": head["iters_per_s"],
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"plain single instance m={args.m} n={args.n} q=1 rho=1, "
+                               f"{args.precision} path ({storage[args.precision]}), residual check every 10",
+                   "m": args.m, "n": args.n, "q": 1, "precision": args.precision},
+        "roofline": {k: v for k, v in head["roofline"].items()},
+        "cpu_baseline": cpu,
+        "kernel_us": head["kernel_us"],
+        "solve": head.get("solve"),
+        "variants": {other: variant} if variant else None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * admm.h - C ABI of the MI355X (gfx950) ADMM solver for robust quadratic
+ * resource allocation problems.
+ *
+ * Method: Qureshi, East and Cannon, "Parallel ADMM for robust quadratic
+ * optimal resource allocation problems" (arXiv:1903.10041).  The problem is
+ * the nominal allocation program (1) for q = 1 and the scenario program (2)
+ * for q > 1 (Sec. II), with quadratic cost and loss functions (Assumption 3):
+ *
+ *   minimise   (1/q) sum_{i,j,k} f_k^(i,j)(x_k^(i,j))
+ *   subject to sum_i x_k^(i,j) >= y_k^(j)              (demand, every j, k)
+ *              sum_k g_k^(i,j)(x_k^(i,j)) <= c^(i)     (capacity, every i, j)
+ *              x_k^(i,j) in [x_lo, x_hi]               (bounds)
+ *              x_1^(i,j) = x_1^(i)                     (first step, q > 1)
+ *
+ *   f(x) = f2 x^2 + f1 x + f0,   g(x) = g2 x^2 + g1 x + g0,   f2, g2 >= 0.
+ *
+ * It is solved by the ADMM iteration (7a)-(7i) of Appendix A: the x-step
+ * (7a) minimises one box-constrained quartic per (i, j, k) in closed form
+ * (Alg. 1, Sec. III-B); the z, x_1, h, s steps and the dual updates follow;
+ * the iteration stops when the primal and dual residuals r and sigma
+ * (defined after (7)) fall below thresholds at a check iteration (Sec. IV-B
+ * checks every 10 iterations).
+ *
+ * Conventions for every entry point:
+ *   - Return value: admm_status; 0 = OK, > 0 non-fatal, < 0 error.  No
+ *     exception or abort crosses this ABI.  admm_last_error() gives detail.
+ *   - Layout: structure of arrays, step index k fastest.  Element arrays are
+ *     [q][m][n] (index (j*m + i)*n + k), demand is [q][n], per-(i,j) scalars
+ *     are [q][m], capacities and per-source bounds are [m].
+ *   - Ownership: the caller owns every buffer it passes.  The library never
+ *     keeps a caller pointer after the call returns (submit copies its
+ *     problem).  The context owns all device memory it allocates.
+ *   - Threading: solve and solve_batch serialise on a context; submit and
+ *     poll may be called from any thread.
+ */
+#ifndef ADMM_MI355X_H
+#define ADMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct admm_context admm_context;   /* opaque; owns device memory */
+
+typedef enum {
+    ADMM_OK = 0,
+    ADMM_NOT_READY = 1,          /* poll: result not yet available */
+    ADMM_MAX_ITER = 2,           /* stopped at max_iter; outputs are valid */
+    ADMM_E_INVALID_ARG = -1,     /* see admm_last_error() */
+    ADMM_E_OUT_OF_BUDGET = -2,   /* instance can never fit the HBM budget */
+    ADMM_E_DEVICE = -3,          /* HIP runtime error */
+    ADMM_E_NUMERICAL = -4,       /* r or sigma became NaN */
+    ADMM_E_UNKNOWN_TICKET = -5,  /* poll of a ticket not issued or already returned */
+    ADMM_E_QUEUE_FULL = -6,      /* submit backpressure: retry later */
+    ADMM_E_UNSUPPORTED = -7      /* valid request outside what this build supports */
+} admm_status;
+
+typedef enum { ADMM_F64 = 0, ADMM_F32_MIXED = 1 } admm_precision;
+
+/* Box semantics of the x-step (7a).  EXACT_BOX minimises the quartic over
+ * the box, i.e. over L with the box indicator, comparing the quartic at the
+ * clamped outer roots.  PAPER_PROJECT applies Alg. 1 to the unconstrained
+ * quartic and projects its result onto the box, as (7a) is printed.  The
+ * two agree whenever the quartic is convex. */
+typedef enum { ADMM_XSTEP_EXACT_BOX = 0, ADMM_XSTEP_PAPER_PROJECT = 1 } admm_xstep;
+
+/* Order of the x-step over sources i: (7a) is stated for each i with
+ * phi containing the other sources' allocations; GAUSS_SEIDEL uses the
+ * already-updated x^(l) for l < i, JACOBI uses the previous iterate. */
+typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
+
+typedef enum { ADMM_HOST = 0, ADMM_DEVICE = 1 } admm_memspace;
+typedef enum { ADMM_BOUNDS_PER_SOURCE = 0, ADMM_BOUNDS_PER_STEP = 1 } admm_bounds_layout;
+
+/* One problem instance, program (1) (q = 1) or (2) (q > 1).
+ * mem == ADMM_HOST: every array is double, in host memory.
+ * mem == ADMM_DEVICE: arrays are device pointers of type `dtype` (double for
+ *   ADMM_F64, float for ADMM_F32_MIXED), e.g. torch tensors' data_ptr();
+ *   the capacity array c is always host double.
+ * f0 and g0 may be NULL (zero); f0 only enters the reported objective. */
+typedef struct {
+    int32_t m, n, q;                 /* sources, horizon steps, scenarios */
+    admm_memspace mem;
+    admm_precision dtype;
+    const void *f2, *f1, *f0;        /* [q][m][n] */
+    const void *g2, *g1, *g0;        /* [q][m][n] */
+    admm_bounds_layout bounds;       /* PER_SOURCE: [m]; PER_STEP: [m][n] */
+    const void *x_lo, *x_hi;
+    const void *y;                   /* [q][n] */
+    const double *c;                 /* [m], host; +INFINITY = no limit */
+} admm_problem;
+
+typedef struct {
+    double rho[4];                   /* rho_1..rho_4 of L (Appendix A), > 0 */
+    double eps_primal, eps_dual;     /* thresholds r_bar, sigma_bar (absolute) */
+    int32_t max_iter;                /* >= 0 */
+    int32_t check_every;             /* residual check cadence, default 10 */
+    admm_precision precision;        /* arithmetic of the iteration */
+    admm_xstep xstep;
+    admm_sweep sweep;
+    int32_t consensus_q1;            /* keep the rho_4 block when q == 1 (default 0) */
+    int32_t debug_branch_codes;      /* record per-element branch codes of the last x-step */
+} admm_settings;
+
+/* Iterate of (7a)-(7i), in the paper's variables, host doubles.  Any NULL
+ * member on input means the cold start: x = clamp(0), z = g(x),
+ * s = max(0, sum_i x - y), h = min(c, 1'z), x_1 = mean_j x_1^(i,j), all
+ * multipliers 0.  On input a state must have the form the iteration gives
+ * it: lambda constant in k, z - g(x) constant in k and s * mu = 0 (every
+ * exported state has it).  lambda_s and zoff_s are the exact per-(i,j)
+ * values of lambda and z - g(x); when both are given on input they are used
+ * instead of lambda and z, which makes export + import bit-exact. */
+typedef struct {
+    double *x;                       /* [q][m][n] */
+    double *z, *lambda;              /* [q][m][n] */
+    double *s, *mu;                  /* [q][n] */
+    double *h, *p, *nu;              /* [q][m] */
+    double *xbar1;                   /* [m] */
+    double *lambda_s, *zoff_s;       /* [q][m] */
+} admm_state;
+
+typedef struct {
+    int32_t status;                  /* ADMM_OK, ADMM_MAX_ITER or an error */
+    int32_t iters;                   /* iterations run */
+    double r, sigma;                 /* residuals at the last check */
+    double objective;                /* (1/q) sum f(x), f0 included */
+    int64_t branch_count[15];        /* 3*branch + clamp, last x-step; debug only */
+    double device_ms, total_ms;      /* iteration time on device; whole call */
+} admm_info;
+
+/* Defaults: rho = 1, eps = 1e-6, max_iter = 10000, check_every = 10, F64,
+ * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes. */
+void admm_default_settings(admm_settings *s);
+
+/* Create a context on HIP device `device` (the calling thread's current
+ * device is left unchanged).  hbm_budget_bytes caps the device memory the
+ * context may hold (0 = 8 GiB).  defaults may be NULL. */
+admm_status admm_create(admm_context **out, int device, size_t hbm_budget_bytes,
+                        const admm_settings *defaults);
+
+/* HIP stream (hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on
+ * which solve and solve_batch run; NULL = the default stream. */
+admm_status admm_set_stream(admm_context *ctx, void *stream);
+
+/* Solve one instance.  settings NULL = the context's defaults; warm NULL =
+ * cold start.  x_out: [q][m][n] in the problem's memspace and dtype.
+ * state_out may be NULL.  info may be NULL.  Returns ADMM_OK when converged,
+ * ADMM_MAX_ITER when max_iter was reached (outputs valid). */
+admm_status admm_solve(admm_context *ctx, const admm_problem *prob,
+                       const admm_settings *settings, const admm_state *warm,
+                       void *x_out, admm_state *state_out, admm_info *info);
+
+/* Solve `count` independent instances of different shapes in one persistent
+ * launch.  All problems share one memspace and dtype.  warm may be NULL
+ * (all cold).  x_out[b] is instance b's [q][m][n] output.  infos: [count].
+ * Returns ADMM_OK if every instance converged, ADMM_MAX_ITER if some hit
+ * max_iter, or the first error. */
+admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
+                             const admm_settings *settings, const admm_state *const *warm,
+                             void *const *x_out, admm_info *infos);
+
+/* Serving.  submit copies the problem (host memory only) and returns a
+ * ticket at once; the instance is admitted to the device when a slot and
+ * the HBM budget allow, and runs alongside the others already resident.
+ * warm_key != 0 warm-starts from the final state of the previous request
+ * with the same key (shifted to the new horizon as a receding-horizon
+ * re-solve, Alg. 2) and stores this request's final state under it. */
+admm_status admm_submit(admm_context *ctx, const admm_problem *prob,
+                        const admm_settings *settings, uint64_t warm_key,
+                        uint64_t *ticket);
+
+/* ADMM_NOT_READY until the ticket's result exists; then ADMM_OK (or
+ * ADMM_MAX_ITER / an error) exactly once, writing x_out (host doubles,
+ * [q][m][n]) and info; afterwards the ticket is unknown. */
+admm_status admm_poll(admm_context *ctx, uint64_t ticket, double *x_out, admm_info *info);
+
+/* Drop the stored warm state of a key. */
+admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key);
+
+/* Measurement hook.  Stages the problem, starts from the cold start and
+ * times each kernel of the plain path on the context's stream: a captured
+ * graph of back-to-back launches of that kernel, replayed between one HIP
+ * event pair, for about `iters` (20..100000) launches each; then whole
+ * iterations the same way.  out[4]: mean microseconds per sweep launch, per
+ * finalize launch, per iteration, and the launch count.  Thresholds are
+ * ignored.  The timed launches advance the iterate; results are not
+ * returned. */
+admm_status admm_profile(admm_context *ctx, const admm_problem *prob,
+                         const admm_settings *settings, int32_t iters, double *out);
+
+void admm_destroy(admm_context *ctx);
+const char *admm_status_string(admm_status s);
+/* Detail of the last error on this thread ("" if none). */
+const char *admm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADMM_MI355X_H */

@@ -1,0 +1,310 @@
+"""ctypes binding of the C ABI in ``include/admm.h``.
+
+Argument marshalling only: every step of the ADMM iteration runs in the HIP
+library.  Problems come either as host numpy float64 arrays
+(``ADMM_HOST``) or as torch CUDA tensors (``ADMM_DEVICE``, float64 or
+float32), whose ``data_ptr()`` is passed straight to the library.
+
+There is no CPU fallback: if ``libadmm.so`` is missing or cannot load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadmm.so")
+
+# admm_status
+OK, NOT_READY, MAX_ITER = 0, 1, 2
+E_INVALID_ARG, E_OUT_OF_BUDGET, E_DEVICE, E_NUMERICAL = -1, -2, -3, -4
+E_UNKNOWN_TICKET, E_QUEUE_FULL, E_UNSUPPORTED = -5, -6, -7
+F64, F32_MIXED = 0, 1
+XSTEP_EXACT_BOX, XSTEP_PAPER_PROJECT = 0, 1
+SWEEP_GAUSS_SEIDEL, SWEEP_JACOBI = 0, 1
+HOST, DEVICE = 0, 1
+BOUNDS_PER_SOURCE, BOUNDS_PER_STEP = 0, 1
+
+
+class AdmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"admm status {status}: {msg}")
+        self.status = status
+
+
+class admm_problem(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("q", C.c_int32),
+                ("mem", C.c_int), ("dtype", C.c_int),
+                ("f2", C.c_void_p), ("f1", C.c_void_p), ("f0", C.c_void_p),
+                ("g2", C.c_void_p), ("g1", C.c_void_p), ("g0", C.c_void_p),
+                ("bounds", C.c_int), ("x_lo", C.c_void_p), ("x_hi", C.c_void_p),
+                ("y", C.c_void_p), ("c", C.c_void_p)]
+
+
+class admm_settings(C.Structure):
+    _fields_ = [("rho", C.c_double * 4), ("eps_primal", C.c_double),
+                ("eps_dual", C.c_double), ("max_iter", C.c_int32),
+                ("check_every", C.c_int32), ("precision", C.c_int),
+                ("xstep", C.c_int), ("sweep", C.c_int), ("consensus_q1", C.c_int32),
+                ("debug_branch_codes", C.c_int32)]
+
+
+class admm_state(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in
+                ("x", "z", "lambda_", "s", "mu", "h", "p", "nu", "xbar1", "lambda_s", "zoff_s")]
+
+
+class admm_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("r", C.c_double),
+                ("sigma", C.c_double), ("objective", C.c_double),
+                ("branch_count", C.c_int64 * 15), ("device_ms", C.c_double),
+                ("total_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libadmm.so (it must have been built: no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        # torch ships its own HIP runtime; load it first so that the library
+        # binds to the same runtime instead of starting a second one.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64 = C.c_void_p, C.c_int32, C.c_uint64
+        sigs = {
+            "admm_default_settings": (None, [vp]),
+            "admm_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_size_t, vp]),
+            "admm_set_stream": (C.c_int, [vp, vp]),
+            "admm_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "admm_solve_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
+            "admm_submit": (C.c_int, [vp, vp, vp, u64, C.POINTER(u64)]),
+            "admm_poll": (C.c_int, [vp, u64, vp, vp]),
+            "admm_release_warm": (C.c_int, [vp, u64]),
+            "admm_destroy": (None, [vp]),
+            "admm_status_string": (C.c_char_p, [C.c_int]),
+            "admm_last_error": (C.c_char_p, []),
+            "admm_debug_codes": (C.c_int, [vp, vp, vp]),
+            "admm_profile": (C.c_int, [vp, vp, vp, i32, vp]),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().admm_last_error().decode()
+
+
+def _check(st: int, allow=(OK, MAX_ITER)) -> int:
+    if st not in allow:
+        raise AdmmError(st, last_error())
+    return st
+
+
+@dataclasses.dataclass
+class Settings:
+    rho: Sequence[float] = (1.0, 1.0, 1.0, 1.0)
+    eps_primal: float = 1e-6
+    eps_dual: float = 1e-6
+    max_iter: int = 10000
+    check_every: int = 10
+    precision: int = F64
+    xstep: int = XSTEP_EXACT_BOX
+    sweep: int = SWEEP_GAUSS_SEIDEL
+    consensus_q1: bool = False
+    debug_branch_codes: bool = False
+
+    def to_c(self) -> admm_settings:
+        return admm_settings((C.c_double * 4)(*[float(r) for r in self.rho]),
+                             float(self.eps_primal), float(self.eps_dual), int(self.max_iter),
+                             int(self.check_every), int(self.precision), int(self.xstep),
+                             int(self.sweep), int(bool(self.consensus_q1)),
+                             int(bool(self.debug_branch_codes)))
+
+
+def _is_torch(a) -> bool:
+    return a is not None and type(a).__module__.startswith("torch")
+
+
+class _Marshal:
+    """Builds an admm_problem from a workloads.Problem-like object and keeps
+    the arrays it points to alive."""
+
+    def __init__(self, prob):
+        self.keep = []
+        dev = _is_torch(prob.f2)
+        if dev:
+            import torch
+            dt = prob.f2.dtype
+            if dt not in (torch.float64, torch.float32):
+                raise TypeError("device arrays must be float64 or float32")
+            self.mem, self.dtype = DEVICE, (F64 if dt == torch.float64 else F32_MIXED)
+
+            def ptr(a):
+                if a is None:
+                    return None
+                if not a.is_cuda or a.dtype != dt or not a.is_contiguous():
+                    raise TypeError("device arrays must be contiguous CUDA tensors of one dtype")
+                self.keep.append(a)
+                return a.data_ptr()
+        else:
+            self.mem, self.dtype = HOST, F64
+
+            def ptr(a):
+                if a is None:
+                    return None
+                a = np.ascontiguousarray(a, dtype=np.float64)
+                self.keep.append(a)
+                return a.ctypes.data
+        xlo = prob.xlo
+        per_step = (xlo.dim() if dev else np.asarray(xlo).ndim) == 2
+        c = np.ascontiguousarray(np.asarray(prob.c, dtype=np.float64))
+        self.keep.append(c)
+        self.st = admm_problem(int(prob.m), int(prob.n), int(prob.q), self.mem, self.dtype,
+                               ptr(prob.f2), ptr(prob.f1), ptr(getattr(prob, "f0", None)),
+                               ptr(prob.g2), ptr(prob.g1), ptr(getattr(prob, "g0", None)),
+                               BOUNDS_PER_STEP if per_step else BOUNDS_PER_SOURCE,
+                               ptr(prob.xlo), ptr(prob.xhi), ptr(prob.y), c.ctypes.data)
+        self.device = dev
+
+
+STATE_KEYS = ("x", "z", "lambda_", "s", "mu", "h", "p", "nu", "xbar1", "lambda_s", "zoff_s")
+
+
+def _state_shapes(m, n, q):
+    return {"x": (q, m, n), "z": (q, m, n), "lambda_": (q, m, n), "s": (q, n), "mu": (q, n),
+            "h": (q, m), "p": (q, m), "nu": (q, m), "xbar1": (m,), "lambda_s": (q, m),
+            "zoff_s": (q, m)}
+
+
+def _state_struct(d: Optional[dict], keep: list):
+    if d is None:
+        return None
+    vals = []
+    for k in STATE_KEYS:
+        a = d.get(k, d.get("lam") if k == "lambda_" else None)
+        if a is None:
+            vals.append(None)
+            continue
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        vals.append(a.ctypes.data)
+    return admm_state(*vals)
+
+
+def info_dict(inf: admm_info) -> dict:
+    return {"status": inf.status, "iters": inf.iters, "r": inf.r, "sigma": inf.sigma,
+            "objective": inf.objective, "branch_count": np.array(list(inf.branch_count)),
+            "device_ms": inf.device_ms, "total_ms": inf.total_ms}
+
+
+class Context:
+    """One admm_context on a HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0,
+                 defaults: Optional[Settings] = None):
+        L = lib()
+        h = C.c_void_p()
+        d = defaults.to_c() if defaults else None
+        _check(L.admm_create(C.byref(h), int(device), int(hbm_budget_bytes),
+                             C.byref(d) if d is not None else None), allow=(OK,))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().admm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_handle: Optional[int]):
+        _check(lib().admm_set_stream(self.h, stream_handle), allow=(OK,))
+
+    def solve(self, prob, settings: Optional[Settings] = None, warm: Optional[dict] = None,
+              want_state: bool = False, x_out=None, want_codes: bool = False):
+        """admm_solve.  Returns (x, info dict, state dict or None)."""
+        mp = _Marshal(prob)
+        keep: list = []
+        s = settings.to_c() if settings else None
+        m, n, q = prob.m, prob.n, prob.q
+        if x_out is None:
+            if mp.device:
+                import torch
+                x_out = torch.empty((q, m, n), dtype=prob.f2.dtype, device=prob.f2.device)
+            else:
+                x_out = np.empty((q, m, n))
+        xptr = x_out.data_ptr() if mp.device else x_out.ctypes.data
+        wst = _state_struct(warm, keep)
+        st_out = None
+        st_c = None
+        if want_state:
+            st_out = {k: np.empty(shp) for k, shp in _state_shapes(m, n, q).items()}
+            st_c = _state_struct(st_out, [])
+            # write into the dict's own arrays
+            st_c = admm_state(*[st_out[k].ctypes.data for k in STATE_KEYS])
+        inf = admm_info()
+        if mp.device:
+            import torch
+            self.set_stream(torch.cuda.current_stream(prob.f2.device).cuda_stream)
+        st = lib().admm_solve(self.h, C.byref(mp.st), C.byref(s) if s is not None else None,
+                              C.byref(wst) if wst is not None else None, xptr,
+                              C.byref(st_c) if st_c is not None else None, C.byref(inf))
+        _check(st)
+        out = info_dict(inf)
+        if want_codes:
+            codes = np.empty((q, m, n), dtype=np.uint8)
+            _check(lib().admm_debug_codes(self.h, C.byref(mp.st), codes.ctypes.data), allow=(OK,))
+            out["codes"] = codes
+        if st_out is not None:
+            st_out["lam"] = st_out["lambda_"]
+        return x_out, out, st_out
+
+
+def _profile(ctx, prob, settings, iters):
+    mp = _Marshal(prob)
+    s = settings.to_c() if settings else None
+    out = (C.c_double * 4)()
+    if mp.device:
+        import torch
+        ctx.set_stream(torch.cuda.current_stream(prob.f2.device).cuda_stream)
+    _check(lib().admm_profile(ctx.h, C.byref(mp.st), C.byref(s) if s is not None else None,
+                              int(iters), out), allow=(OK,))
+    return {"sweep_us": out[0], "finalize_us": out[1], "graph_iter_us": out[2], "iters": int(out[3])}
+
+
+def admm_profile(ctx: "Context", prob, settings: Optional[Settings] = None, iters: int = 200) -> dict:
+    """Per-kernel timing of the plain path (HIP events around each launch)."""
+    return _profile(ctx, prob, settings, iters)
+
+
+def admm_create(device: int = 0, hbm_budget_bytes: int = 0, defaults: Optional[Settings] = None) -> Context:
+    return Context(device, hbm_budget_bytes, defaults)
+
+
+def admm_solve(ctx: Context, prob, settings: Optional[Settings] = None, warm=None, want_state=False):
+    return ctx.solve(prob, settings, warm, want_state)
+
+
+def admm_destroy(ctx: Context):
+    ctx.close()

@@ -1,0 +1,78 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// ADMM library.  Not part of the public ABI (include/admm.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace admm {
+
+constexpr int kBlock = 256;          // threads per block (4 wave64s)
+constexpr int kWaves = kBlock / 64;
+constexpr int kPad = 64;             // n is padded to a multiple of this
+
+// Device-resident control block of one solve (one instance).
+struct Ctrl {
+    int32_t t;          // iterations completed
+    int32_t status;     // -1 running, 0 converged, 2 max_iter, -4 numerical
+    int32_t done;       // 1 once status is final: kernels become no-ops
+    int32_t bad_input;  // set by the pack kernel when validation fails
+    double r, sigma;    // residuals at the last check iteration
+    double objective;
+    double pad_[3];
+};
+
+// Branch classes of the x-step (code = 3 * branch + clamp state).
+enum { BR_QUAD = 0, BR_CARDANO = 1, BR_TRIPLE = 2, BR_TRIG_LO = 3, BR_TRIG_HI = 4 };
+enum { CL_INTERIOR = 0, CL_LO = 1, CL_HI = 2 };
+
+// Everything a kernel of one plain solve needs, passed by value.
+// Element arrays are [q][m][n_pad], column arrays [q][n_pad], per-(i,j)
+// scalars [q][m] (index j*m + i).  `coef` packs (f2, f1, g2, g1) per element.
+struct SolveParams {
+    int32_t m, n, q, n_pad;
+    int32_t nblk;           // sweep blocks per scenario
+    int32_t group;          // finalize: lanes cooperating on one (i,j) pair
+    int32_t check_every, max_iter;
+    int32_t xstep_project, jacobi, consensus, want_codes;
+    double rho1, rho2, rho3, rho4, inv_q, eps_p, eps_d;
+    const void *coef;       // vec4 of T
+    const void *g0;         // T or null
+    const void *f0;         // T or null (objective only)
+    const void *y;          // T
+    const void *blo, *bhi;  // T [m][n_pad] per-step bounds, or null
+    const double *slo, *shi;// [m] per-source bounds (used when blo is null)
+    const double *cap;      // [m]
+    void *x;                // T
+    void *w;                // T: s - mu (s = max(w,0), mu = max(-w,0))
+    uint8_t *codes;         // [q][m][n_pad] or null
+    double *lam, *zoff, *h, *p, *nu, *x1;   // [q][m]
+    double *xbar1;          // [m]
+    double *part;           // block partials
+    double *pair_r, *pair_s;// [q][m] check scratch
+    Ctrl *ctrl;
+};
+
+// Partials layout (doubles): g-sum [q][nblk][m], then dg-max, dg-min (same
+// shape), then per-block residual maxima [q][nblk][2].
+inline size_t part_doubles(int m, int q, int nblk) {
+    return (size_t)q * nblk * (3 * (size_t)m + 2);
+}
+
+// Launchers (admm_kernels.hip).  All are asynchronous on `s`.
+// dtype: 0 = double, 1 = float (storage of element/column arrays).
+hipError_t launch_pack(const SolveParams &P, int dtype, int src_dtype,
+                       const void *f2, const void *f1, const void *g2, const void *g1,
+                       const void *g0, const void *f0, const void *y,
+                       const void *blo, const void *bhi, void *g0_dst, void *f0_dst,
+                       void *y_dst, void *blo_dst, void *bhi_dst, hipStream_t s);
+hipError_t launch_cold_init(const SolveParams &P, int dtype, hipStream_t s);
+hipError_t launch_iteration(const SolveParams &P, int dtype, hipStream_t s);
+hipError_t launch_sweep(const SolveParams &P, int dtype, hipStream_t s);
+hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
+hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
+hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
+hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,
+                         const void *w_src, hipStream_t s);
+int max_m_supported();
+
+}  // namespace admm

@@ -1,0 +1,701 @@
+// Host runtime and C ABI of the ADMM library (see include/admm.h).
+//
+// A context owns a workspace of device buffers, capped by its HBM budget,
+// reused across solves.  A plain solve packs the problem into the kernels'
+// padded structure-of-arrays layout, starts the iteration from the cold
+// start or a warm state, then replays a captured HIP graph holding a chunk
+// of iterations until the device-side stop flag is set.  The flag is read
+// from pinned host memory once per chunk, with one chunk kept in flight.
+#include "admm.h"
+#include "admm_internal.hpp"
+#include "admm_host.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+using namespace admm;
+
+namespace admm {
+
+thread_local std::string g_last_error;
+
+admm_status fail(admm_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+}
+
+admm_status Arena::ensure(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (b.bytes >= bytes) return ADMM_OK;
+    if (used - b.bytes + bytes > budget)
+        return fail(ADMM_E_OUT_OF_BUDGET, "device workspace of " + std::to_string(bytes) +
+                                              " bytes exceeds the context's HBM budget");
+    if (b.p) { (void)hipFree(b.p); used -= b.bytes; b.p = nullptr; b.bytes = 0; }
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+        b.p = nullptr;
+        return fail(ADMM_E_DEVICE, "hipMalloc failed");
+    }
+    b.bytes = bytes;
+    used += bytes;
+    return ADMM_OK;
+}
+
+void Arena::release(DevBuf &b) {
+    if (b.p) { (void)hipFree(b.p); used -= b.bytes; }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+}  // namespace admm
+
+// ------------------------------------------------------------- validation
+
+static bool finite_or_null(const double *a, size_t n) {
+    if (!a) return true;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+namespace admm {
+
+admm_status validate_settings(const admm_settings *s) {
+    for (int r = 0; r < 4; ++r)
+        if (!(s->rho[r] > 0.0) || !std::isfinite(s->rho[r]))
+            return fail(ADMM_E_INVALID_ARG, "rho_1..rho_4 must be finite and > 0");
+    if (!(s->eps_primal >= 0.0) || !(s->eps_dual >= 0.0))
+        return fail(ADMM_E_INVALID_ARG, "eps_primal and eps_dual must be >= 0");
+    if (s->max_iter < 0) return fail(ADMM_E_INVALID_ARG, "max_iter must be >= 0");
+    if (s->check_every < 1) return fail(ADMM_E_INVALID_ARG, "check_every must be >= 1");
+    if (s->precision != ADMM_F64 && s->precision != ADMM_F32_MIXED)
+        return fail(ADMM_E_INVALID_ARG, "unknown precision");
+    if (s->xstep != ADMM_XSTEP_EXACT_BOX && s->xstep != ADMM_XSTEP_PAPER_PROJECT)
+        return fail(ADMM_E_INVALID_ARG, "unknown xstep");
+    if (s->sweep != ADMM_SWEEP_GAUSS_SEIDEL && s->sweep != ADMM_SWEEP_JACOBI)
+        return fail(ADMM_E_INVALID_ARG, "unknown sweep");
+    return ADMM_OK;
+}
+
+admm_status validate_problem_shape(const admm_problem *p) {
+    if (!p) return fail(ADMM_E_INVALID_ARG, "problem is NULL");
+    if (p->m < 1 || p->n < 1 || p->q < 1) return fail(ADMM_E_INVALID_ARG, "m, n and q must be >= 1");
+    if (p->m > max_m_supported())
+        return fail(ADMM_E_UNSUPPORTED, "m > " + std::to_string(max_m_supported()) + " sources is not supported");
+    if ((int64_t)p->m * p->n * p->q > (int64_t)1 << 40) return fail(ADMM_E_INVALID_ARG, "problem too large");
+    if (!p->f2 || !p->f1 || !p->g2 || !p->g1 || !p->x_lo || !p->x_hi || !p->y || !p->c)
+        return fail(ADMM_E_INVALID_ARG, "f2, f1, g2, g1, x_lo, x_hi, y and c are required");
+    if (p->mem != ADMM_HOST && p->mem != ADMM_DEVICE) return fail(ADMM_E_INVALID_ARG, "unknown memspace");
+    if (p->mem == ADMM_DEVICE && p->dtype != ADMM_F64 && p->dtype != ADMM_F32_MIXED)
+        return fail(ADMM_E_INVALID_ARG, "unknown dtype");
+    if (p->bounds != ADMM_BOUNDS_PER_SOURCE && p->bounds != ADMM_BOUNDS_PER_STEP)
+        return fail(ADMM_E_INVALID_ARG, "unknown bounds layout");
+    for (int i = 0; i < p->m; ++i)
+        if (std::isnan(p->c[i]) || p->c[i] == -INFINITY)
+            return fail(ADMM_E_INVALID_ARG, "capacities must be numbers or +inf");
+    if (p->mem == ADMM_HOST) {
+        const size_t E = (size_t)p->m * p->n * p->q;
+        const double *f2 = (const double *)p->f2, *g2 = (const double *)p->g2;
+        if (!finite_or_null(f2, E) || !finite_or_null((const double *)p->f1, E) ||
+            !finite_or_null(g2, E) || !finite_or_null((const double *)p->g1, E) ||
+            !finite_or_null((const double *)p->g0, E) || !finite_or_null((const double *)p->f0, E) ||
+            !finite_or_null((const double *)p->y, (size_t)p->q * p->n))
+            return fail(ADMM_E_INVALID_ARG, "coefficients and demand must be finite");
+        for (size_t e = 0; e < E; ++e)
+            if (f2[e] < 0.0 || g2[e] < 0.0)
+                return fail(ADMM_E_INVALID_ARG, "f2 and g2 must be >= 0 (convexity, Assumption 1)");
+        const size_t NB = p->bounds == ADMM_BOUNDS_PER_STEP ? (size_t)p->m * p->n : (size_t)p->m;
+        const double *lo = (const double *)p->x_lo, *hi = (const double *)p->x_hi;
+        for (size_t e = 0; e < NB; ++e)
+            if (!std::isfinite(lo[e]) || !std::isfinite(hi[e]) || lo[e] > hi[e])
+                return fail(ADMM_E_INVALID_ARG, "bounds must be finite with x_lo <= x_hi");
+    }
+    return ADMM_OK;
+}
+
+}  // namespace admm
+
+// ------------------------------------------------------------ the context
+
+extern "C" void admm_default_settings(admm_settings *s) {
+    std::memset(s, 0, sizeof *s);
+    for (int r = 0; r < 4; ++r) s->rho[r] = 1.0;
+    s->eps_primal = 1e-6;
+    s->eps_dual = 1e-6;
+    s->max_iter = 10000;
+    s->check_every = 10;
+    s->precision = ADMM_F64;
+    s->xstep = ADMM_XSTEP_EXACT_BOX;
+    s->sweep = ADMM_SWEEP_GAUSS_SEIDEL;
+}
+
+extern "C" admm_status admm_create(admm_context **out, int device, size_t budget,
+                                   const admm_settings *defaults) {
+    if (!out) return fail(ADMM_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(ADMM_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(ADMM_E_INVALID_ARG, "device index out of range");
+    admm_settings s;
+    if (defaults) s = *defaults;
+    else admm_default_settings(&s);
+    admm_status st = validate_settings(&s);
+    if (st != ADMM_OK) return st;
+    admm_context *ctx = new admm_context();
+    ctx->device = device;
+    ctx->arena.budget = budget ? budget : (size_t)8 << 30;
+    ctx->defaults = s;
+    DeviceGuard g(device);
+    if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hctrl, 2 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return fail(ADMM_E_DEVICE, "stream/event/pinned allocation failed");
+    }
+    *out = ctx;
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_set_stream(admm_context *ctx, void *stream) {
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    ctx->user = (hipStream_t)stream;
+    return ADMM_OK;
+}
+
+extern "C" void admm_destroy(admm_context *ctx) {
+    if (!ctx) return;
+    serve_shutdown(ctx);
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->own);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (DevBuf *b : ctx->ws.all()) ctx->arena.release(*b);
+    batch_release(ctx);
+    if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
+    (void)hipEventDestroy(ctx->join);
+    (void)hipEventDestroy(ctx->ev0);
+    (void)hipEventDestroy(ctx->ev1);
+    (void)hipStreamDestroy(ctx->own);
+    delete ctx;
+}
+
+extern "C" const char *admm_status_string(admm_status s) {
+    switch (s) {
+    case ADMM_OK: return "ok";
+    case ADMM_NOT_READY: return "not ready";
+    case ADMM_MAX_ITER: return "max_iter reached";
+    case ADMM_E_INVALID_ARG: return "invalid argument";
+    case ADMM_E_OUT_OF_BUDGET: return "out of HBM budget";
+    case ADMM_E_DEVICE: return "device error";
+    case ADMM_E_NUMERICAL: return "numerical failure (NaN residual)";
+    case ADMM_E_UNKNOWN_TICKET: return "unknown ticket";
+    case ADMM_E_QUEUE_FULL: return "queue full";
+    case ADMM_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *admm_last_error(void) { return g_last_error.c_str(); }
+
+// --------------------------------------------------------- plain solve
+
+namespace admm {
+
+#define HIPCHK(x)                                                                   \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(ADMM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
+int finalize_group(int m, int q, int nblk) {
+    int G = pow2_floor(std::max(1, kBlock / (m * q)));
+    if (G > 64) G = 64;
+    while (G > 1 && G / 2 >= nblk) G /= 2;
+    return G;
+}
+
+// Layout and buffers of one solve; fills P.
+admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settings *s, SolveParams &P,
+                    int &dtype) {
+    Workspace &W = ctx->ws;
+    Arena &A = ctx->arena;
+    dtype = s->precision == ADMM_F64 ? 0 : 1;
+    const size_t T = dtype == 0 ? 8 : 4;
+    const int m = pr->m, n = pr->n, q = pr->q;
+    const int n_pad = (n + kPad - 1) / kPad * kPad;
+    const int nblk = (n + kBlock - 1) / kBlock;
+    const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
+    std::memset(&P, 0, sizeof P);
+    P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk;
+    P.group = finalize_group(m, q, nblk);
+    P.check_every = s->check_every;
+    P.max_iter = s->max_iter;
+    P.xstep_project = s->xstep == ADMM_XSTEP_PAPER_PROJECT;
+    P.jacobi = s->sweep == ADMM_SWEEP_JACOBI;
+    P.consensus = (q > 1) || s->consensus_q1;
+    P.want_codes = s->debug_branch_codes ? 1 : 0;
+    P.rho1 = s->rho[0]; P.rho2 = s->rho[1]; P.rho3 = s->rho[2]; P.rho4 = s->rho[3];
+    P.inv_q = 1.0 / q;
+    P.eps_p = s->eps_primal;
+    P.eps_d = s->eps_dual;
+    admm_status st;
+#define ENS(buf, bytes) if ((st = A.ensure(buf, bytes)) != ADMM_OK) return st
+    ENS(W.coef, E * 4 * T);
+    ENS(W.x, E * T);
+    ENS(W.y, K * T);
+    ENS(W.w, K * T);
+    ENS(W.scal, (7 * M + m + 3 * (size_t)m) * sizeof(double) + 2 * M * sizeof(double));
+    ENS(W.part, part_doubles(m, q, nblk) * sizeof(double));
+    ENS(W.ctrl, sizeof(Ctrl));
+    ENS(W.obj, 1024 * sizeof(double));
+    if (pr->g0) ENS(W.g0, E * T);
+    if (pr->f0) ENS(W.f0, E * T);
+    if (pr->bounds == ADMM_BOUNDS_PER_STEP) { ENS(W.blo, (size_t)m * n_pad * T); ENS(W.bhi, (size_t)m * n_pad * T); }
+    if (P.want_codes) ENS(W.codes, E);
+#undef ENS
+    double *sc = (double *)W.scal.p;
+    P.lam = sc; P.zoff = sc + M; P.h = sc + 2 * M; P.p = sc + 3 * M; P.nu = sc + 4 * M;
+    P.x1 = sc + 5 * M; P.pair_r = sc + 6 * M; P.pair_s = sc + 7 * M;
+    P.xbar1 = sc + 8 * M; P.slo = sc + 8 * M + m; P.shi = sc + 8 * M + 2 * m; P.cap = sc + 8 * M + 3 * m;
+    P.coef = W.coef.p; P.x = W.x.p; P.y = W.y.p; P.w = W.w.p;
+    P.g0 = pr->g0 ? W.g0.p : nullptr;
+    P.f0 = pr->f0 ? W.f0.p : nullptr;
+    P.blo = pr->bounds == ADMM_BOUNDS_PER_STEP ? W.blo.p : nullptr;
+    P.bhi = pr->bounds == ADMM_BOUNDS_PER_STEP ? W.bhi.p : nullptr;
+    P.codes = P.want_codes ? (uint8_t *)W.codes.p : nullptr;
+    P.part = (double *)W.part.p;
+    P.ctrl = (Ctrl *)W.ctrl.p;
+    return ADMM_OK;
+}
+
+// Pack the problem into the workspace (validating it on the device too).
+admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
+                          hipStream_t s) {
+    const int m = pr->m, n = pr->n, q = pr->q;
+    const size_t E = (size_t)q * m * n;
+    std::vector<double> slo(m), shi(m);
+    const int src_dtype = pr->mem == ADMM_HOST ? 0 : (pr->dtype == ADMM_F64 ? 0 : 1);
+    const size_t ST = src_dtype == 0 ? 8 : 4;
+    if (pr->bounds == ADMM_BOUNDS_PER_SOURCE) {
+        if (pr->mem == ADMM_HOST) {
+            std::memcpy(slo.data(), pr->x_lo, m * sizeof(double));
+            std::memcpy(shi.data(), pr->x_hi, m * sizeof(double));
+        } else {
+            std::vector<char> a(m * ST), b(m * ST);
+            HIPCHK(hipMemcpy(a.data(), pr->x_lo, m * ST, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(b.data(), pr->x_hi, m * ST, hipMemcpyDeviceToHost));
+            for (int i = 0; i < m; ++i) {
+                slo[i] = ST == 8 ? ((double *)a.data())[i] : ((float *)a.data())[i];
+                shi[i] = ST == 8 ? ((double *)b.data())[i] : ((float *)b.data())[i];
+            }
+            for (int i = 0; i < m; ++i)
+                if (!std::isfinite(slo[i]) || !std::isfinite(shi[i]) || slo[i] > shi[i])
+                    return fail(ADMM_E_INVALID_ARG, "bounds must be finite with x_lo <= x_hi");
+        }
+        if (dtype == 1)
+            for (int i = 0; i < m; ++i) { slo[i] = (double)(float)slo[i]; shi[i] = (double)(float)shi[i]; }
+    } else {
+        std::fill(slo.begin(), slo.end(), 0.0);
+        std::fill(shi.begin(), shi.end(), 0.0);
+    }
+    std::vector<double> hb(3 * (size_t)m);
+    std::memcpy(hb.data(), slo.data(), m * sizeof(double));
+    std::memcpy(hb.data() + m, shi.data(), m * sizeof(double));
+    std::memcpy(hb.data() + 2 * m, pr->c, m * sizeof(double));
+    HIPCHK(hipMemcpyAsync((void *)P.slo, hb.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s));
+
+    const void *f2 = pr->f2, *f1 = pr->f1, *g2 = pr->g2, *g1 = pr->g1, *g0 = pr->g0, *f0 = pr->f0;
+    const void *y = pr->y, *blo = nullptr, *bhi = nullptr;
+    if (pr->bounds == ADMM_BOUNDS_PER_STEP) { blo = pr->x_lo; bhi = pr->x_hi; }
+    if (pr->mem == ADMM_HOST) {
+        // upload into staging first (double)
+        size_t need = 4 * E + (g0 ? E : 0) + (f0 ? E : 0) + (size_t)q * n +
+                      (blo ? 2 * (size_t)m * n : 0);
+        admm_status st = ctx->arena.ensure(ctx->ws.staging, need * sizeof(double));
+        if (st != ADMM_OK) return st;
+        double *d = (double *)ctx->ws.staging.p;
+        auto up = [&](const void *src, size_t cnt) -> const void * {
+            if (!src) return nullptr;
+            const void *dst = d;
+            (void)hipMemcpyAsync(d, src, cnt * sizeof(double), hipMemcpyHostToDevice, s);
+            d += cnt;
+            return dst;
+        };
+        f2 = up(pr->f2, E); f1 = up(pr->f1, E); g2 = up(pr->g2, E); g1 = up(pr->g1, E);
+        g0 = up(pr->g0, E); f0 = up(pr->f0, E); y = up(pr->y, (size_t)q * n);
+        if (blo) { blo = up(pr->x_lo, (size_t)m * n); bhi = up(pr->x_hi, (size_t)m * n); }
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(launch_pack(P, dtype, src_dtype, f2, f1, g2, g1, g0, f0, y, blo, bhi, (void *)P.g0,
+                       (void *)P.f0, (void *)P.y, (void *)P.blo, (void *)P.bhi, s));
+    HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->hctrl->bad_input)
+        return fail(ADMM_E_INVALID_ARG,
+                    "problem arrays must be finite, with f2, g2 >= 0 (Assumption 1) and x_lo <= x_hi");
+    return ADMM_OK;
+}
+
+// Warm start from paper variables (host doubles).
+admm_status load_warm(admm_context *ctx, const admm_problem *pr, const admm_state *ws, const SolveParams &P,
+                      int dtype, hipStream_t s) {
+    const int m = pr->m, n = pr->n, q = pr->q;
+    const size_t E = (size_t)q * m * n, K = (size_t)q * n, M = (size_t)q * m;
+    if (!ws->x || !ws->s || !ws->mu || !ws->h || !ws->p || !ws->nu || !ws->xbar1 ||
+        !((ws->lambda_s && ws->zoff_s) || (ws->z && ws->lambda)))
+        return fail(ADMM_E_INVALID_ARG, "warm state: x, s, mu, h, p, nu, xbar1 and either "
+                                        "(lambda_s, zoff_s) or (z, lambda) are required");
+    std::vector<double> w(K), lam(M), zoff(M);
+    for (size_t c = 0; c < K; ++c) {
+        const double a = ws->s[c], b = ws->mu[c];
+        const double sc = 1e-12 * (1.0 + std::fabs(a) + std::fabs(b));
+        if (!(a >= -sc) || !(b >= -sc) || std::min(a, b) > sc)
+            return fail(ADMM_E_INVALID_ARG, "warm state: s and mu must be >= 0 with s * mu = 0");
+        w[c] = a - b;
+    }
+    if (ws->lambda_s && ws->zoff_s) {
+        std::memcpy(lam.data(), ws->lambda_s, M * sizeof(double));
+        std::memcpy(zoff.data(), ws->zoff_s, M * sizeof(double));
+    } else {
+        // need g(x) on the host: coefficients from the caller (host) or the packed copy
+        std::vector<double> g2(E), g1(E), g0(E, 0.0);
+        if (pr->mem == ADMM_HOST) {
+            std::memcpy(g2.data(), pr->g2, E * sizeof(double));
+            std::memcpy(g1.data(), pr->g1, E * sizeof(double));
+            if (pr->g0) std::memcpy(g0.data(), pr->g0, E * sizeof(double));
+        } else {
+            const size_t ST = pr->dtype == ADMM_F64 ? 8 : 4;
+            std::vector<char> a(E * ST), b(E * ST), c(pr->g0 ? E * ST : 0);
+            HIPCHK(hipMemcpy(a.data(), pr->g2, E * ST, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(b.data(), pr->g1, E * ST, hipMemcpyDeviceToHost));
+            if (pr->g0) HIPCHK(hipMemcpy(c.data(), pr->g0, E * ST, hipMemcpyDeviceToHost));
+            for (size_t e = 0; e < E; ++e) {
+                g2[e] = ST == 8 ? ((double *)a.data())[e] : ((float *)a.data())[e];
+                g1[e] = ST == 8 ? ((double *)b.data())[e] : ((float *)b.data())[e];
+                if (pr->g0) g0[e] = ST == 8 ? ((double *)c.data())[e] : ((float *)c.data())[e];
+            }
+        }
+        for (size_t pi = 0; pi < M; ++pi) {
+            const size_t base = pi * n;
+            double lmax = 0.0, zmax = 0.0, sc = 1.0;
+            const double l0 = ws->lambda[base];
+            const double x0 = ws->x[base];
+            const double zo0 = ws->z[base] - ((g2[base] * x0 + g1[base]) * x0 + g0[base]);
+            for (int k = 0; k < n; ++k) {
+                const double xk = ws->x[base + k];
+                const double gk = (g2[base + k] * xk + g1[base + k]) * xk + g0[base + k];
+                lmax = std::max(lmax, std::fabs(ws->lambda[base + k] - l0));
+                zmax = std::max(zmax, std::fabs((ws->z[base + k] - gk) - zo0));
+                sc = std::max(sc, std::fabs(gk) + std::fabs(ws->z[base + k]) + std::fabs(ws->lambda[base + k]));
+            }
+            if (lmax > 1e-9 * sc || zmax > 1e-9 * sc)
+                return fail(ADMM_E_INVALID_ARG, "warm state: lambda and z - g(x) must be constant in k "
+                                                "(the form every ADMM iterate has)");
+            lam[pi] = l0;
+            zoff[pi] = zo0;
+        }
+    }
+    // staging: x (E) then w (K)
+    admm_status st = ctx->arena.ensure(ctx->ws.staging, (E + K) * sizeof(double));
+    if (st != ADMM_OK) return st;
+    double *d = (double *)ctx->ws.staging.p;
+    HIPCHK(hipMemcpyAsync(d, ws->x, E * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d + E, w.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_load_x(P, dtype, d, 0, d + E, s));
+    HIPCHK(hipMemcpyAsync(P.lam, lam.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(P.zoff, zoff.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(P.h, ws->h, M * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(P.p, ws->p, M * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(P.nu, ws->nu, M * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(P.xbar1, ws->xbar1, m * sizeof(double), hipMemcpyHostToDevice, s));
+    Ctrl c0;
+    std::memset(&c0, 0, sizeof c0);
+    c0.status = P.max_iter > 0 ? -1 : 2;
+    c0.done = P.max_iter > 0 ? 0 : 1;
+    c0.r = INFINITY;
+    c0.sigma = INFINITY;
+    *ctx->hctrl = c0;
+    HIPCHK(hipMemcpyAsync(P.ctrl, ctx->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return ADMM_OK;
+}
+
+static int chunk_for(int check_every) {
+    int c = check_every;
+    while (c < 40) c += check_every;
+    return c;
+}
+
+// Run the iteration to the device stop flag with a captured graph per chunk.
+admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms) {
+    const int chunk = chunk_for(P.check_every);
+    const bool reuse = ctx->gexec && ctx->gdtype == dtype && ctx->gchunk == chunk &&
+                       std::memcmp(&ctx->gparams, &P, sizeof P) == 0;
+    if (!reuse) {
+        if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        for (int c = 0; c < chunk; ++c) {
+            hipError_t e = launch_iteration(P, dtype, s);
+            if (e != hipSuccess) {
+                hipGraph_t junk;
+                (void)hipStreamEndCapture(s, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                return fail(ADMM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+            }
+        }
+        HIPCHK(hipStreamEndCapture(s, &g));
+        hipError_t e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) { ctx->gexec = nullptr; return fail(ADMM_E_DEVICE, "graph instantiate failed"); }
+        ctx->gparams = P;
+        ctx->gdtype = dtype;
+        ctx->gchunk = chunk;
+    }
+    const long max_chunks = (P.max_iter + chunk - 1) / chunk;
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    // Two chunks in flight: after queuing chunk c (and a copy of the control
+    // block behind it), wait for the copy queued behind chunk c-1.
+    Ctrl *hc = ctx->hctrl;
+    hipEvent_t flag_ev[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreateWithFlags(&flag_ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&flag_ev[1], hipEventDisableTiming));
+    auto cleanup = [&]() { (void)hipEventDestroy(flag_ev[0]); (void)hipEventDestroy(flag_ev[1]); };
+    long launched = 0;
+    bool done = P.max_iter == 0;
+    while (!done && launched < max_chunks) {
+        const int slot = (int)(launched & 1);
+        if (hipGraphLaunch(ctx->gexec, s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "graph launch failed"); }
+        (void)hipMemcpyAsync(&hc[slot], P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+        (void)hipEventRecord(flag_ev[slot], s);
+        ++launched;
+        int wait_slot = -1;
+        if (launched == max_chunks) wait_slot = slot;            // last one: wait for it
+        else if (launched >= 2) wait_slot = slot ^ 1;            // the previous chunk
+        if (wait_slot >= 0) {
+            if (hipEventSynchronize(flag_ev[wait_slot]) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "event sync failed"); }
+            done = hc[wait_slot].done != 0;
+        }
+    }
+    (void)hipEventRecord(ctx->ev1, s);
+    if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "stream sync failed"); }
+    cleanup();
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (dev_ms) *dev_ms = ms;
+    return ADMM_OK;
+}
+
+// Expand the device state into the paper's variables.
+admm_status export_state(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
+                         admm_state *out, hipStream_t s) {
+    const int m = pr->m, n = pr->n, q = pr->q, n_pad = P.n_pad;
+    const size_t E = (size_t)q * m * n, Ep = (size_t)q * m * n_pad, K = (size_t)q * n, M = (size_t)q * m;
+    const size_t T = dtype == 0 ? 8 : 4;
+    std::vector<char> xb(Ep * T), wb((size_t)q * n_pad * T), cb(Ep * 4 * T), g0b(P.g0 ? Ep * T : 0);
+    std::vector<double> sc(8 * M + m);
+    HIPCHK(hipMemcpyAsync(xb.data(), P.x, Ep * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(wb.data(), P.w, (size_t)q * n_pad * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(cb.data(), P.coef, Ep * 4 * T, hipMemcpyDeviceToHost, s));
+    if (P.g0) HIPCHK(hipMemcpyAsync(g0b.data(), P.g0, Ep * T, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(sc.data(), P.lam, (8 * M + m) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    auto rd = [&](const std::vector<char> &b, size_t i) -> double {
+        return T == 8 ? ((const double *)b.data())[i] : (double)((const float *)b.data())[i];
+    };
+    const double *lam = sc.data(), *zoff = lam + M, *h = lam + 2 * M, *p = lam + 3 * M, *nu = lam + 4 * M;
+    const double *xbar1 = lam + 8 * M;
+    for (size_t r = 0; r < M; ++r)
+        for (int k = 0; k < n; ++k) {
+            const size_t e = r * n + k, ep = r * n_pad + k;
+            const double x = rd(xb, ep);
+            if (out->x) out->x[e] = x;
+            const double g2 = rd(cb, 4 * ep + 2), g1 = rd(cb, 4 * ep + 3);
+            const double g0 = P.g0 ? rd(g0b, ep) : 0.0;
+            if (out->z) out->z[e] = (g2 * x + g1) * x + g0 + zoff[r];
+            if (out->lambda) out->lambda[e] = lam[r];
+        }
+    for (int j = 0; j < q; ++j)
+        for (int k = 0; k < n; ++k) {
+            const double w = rd(wb, (size_t)j * n_pad + k);
+            if (out->s) out->s[(size_t)j * n + k] = std::max(w, 0.0);
+            if (out->mu) out->mu[(size_t)j * n + k] = std::max(-w, 0.0);
+        }
+    (void)K;
+    (void)E;
+    if (out->h) std::memcpy(out->h, h, M * sizeof(double));
+    if (out->p) std::memcpy(out->p, p, M * sizeof(double));
+    if (out->nu) std::memcpy(out->nu, nu, M * sizeof(double));
+    if (out->xbar1) std::memcpy(out->xbar1, xbar1, m * sizeof(double));
+    if (out->lambda_s) std::memcpy(out->lambda_s, lam, M * sizeof(double));
+    if (out->zoff_s) std::memcpy(out->zoff_s, zoff, M * sizeof(double));
+    return ADMM_OK;
+}
+
+}  // namespace admm
+
+extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, const admm_settings *settings,
+                                  const admm_state *warm, void *x_out, admm_state *state_out, admm_info *info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    if (!x_out) return fail(ADMM_E_INVALID_ARG, "x_out is NULL");
+    admm_settings S = settings ? *settings : ctx->defaults;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    if ((st = validate_problem_shape(pr)) != ADMM_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->own;
+    // order after the caller's stream (device inputs may be produced there)
+    HIPCHK(hipEventRecord(ctx->join, ctx->user));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    SolveParams P;
+    int dtype = 0;
+    if ((st = prepare(ctx, pr, &S, P, dtype)) != ADMM_OK) return st;
+    if ((st = stage_problem(ctx, pr, P, dtype, s)) != ADMM_OK) return st;
+    if (warm && warm->x) {
+        if ((st = load_warm(ctx, pr, warm, P, dtype, s)) != ADMM_OK) return st;
+    } else {
+        HIPCHK(launch_cold_init(P, dtype, s));
+    }
+    double dev_ms = 0.0;
+    if ((st = iterate(ctx, P, dtype, s, &dev_ms)) != ADMM_OK) return st;
+    HIPCHK(launch_objective(P, dtype, (double *)ctx->ws.obj.p, s));
+    HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    // x out
+    const size_t E = (size_t)pr->q * pr->m * pr->n;
+    if (pr->mem == ADMM_DEVICE) {
+        HIPCHK(launch_unpack_x(P, dtype, x_out, pr->dtype == ADMM_F64 ? 0 : 1, s));
+    } else {
+        if ((st = ctx->arena.ensure(ctx->ws.staging, E * sizeof(double))) != ADMM_OK) return st;
+        HIPCHK(launch_unpack_x(P, dtype, ctx->ws.staging.p, 0, s));
+        HIPCHK(hipMemcpyAsync(x_out, ctx->ws.staging.p, E * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    const Ctrl c = *ctx->hctrl;
+    if (state_out && (st = export_state(ctx, pr, P, dtype, state_out, s)) != ADMM_OK) return st;
+    admm_info inf;
+    std::memset(&inf, 0, sizeof inf);
+    inf.status = c.status == 0 ? ADMM_OK : (c.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
+    inf.iters = c.t;
+    inf.r = c.r;
+    inf.sigma = c.sigma;
+    inf.objective = c.objective;
+    inf.device_ms = dev_ms;
+    if (P.want_codes) {
+        const size_t Ep = (size_t)pr->q * pr->m * P.n_pad;
+        std::vector<uint8_t> codes(Ep);
+        HIPCHK(hipMemcpy(codes.data(), P.codes, Ep, hipMemcpyDeviceToHost));
+        for (size_t r = 0; r < (size_t)pr->q * pr->m; ++r)
+            for (int k = 0; k < pr->n; ++k) {
+                const uint8_t cd = codes[r * P.n_pad + k];
+                if (cd < 15) inf.branch_count[cd]++;
+            }
+    }
+    HIPCHK(hipEventRecord(ctx->join, s));
+    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    inf.total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (info) *info = inf;
+    if (inf.status == ADMM_E_NUMERICAL) return fail(ADMM_E_NUMERICAL, "residual became NaN");
+    return (admm_status)inf.status;
+}
+
+// Branch codes of the last x-step, [q][m][n] (debug_branch_codes solves).
+extern "C" admm_status admm_debug_codes(admm_context *ctx, const admm_problem *pr, uint8_t *out) {
+    if (!ctx || !pr || !out) return fail(ADMM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!ctx->ws.codes.p) return fail(ADMM_E_INVALID_ARG, "no branch codes recorded");
+    const int n_pad = (pr->n + kPad - 1) / kPad * kPad;
+    const size_t rows = (size_t)pr->q * pr->m;
+    std::vector<uint8_t> codes(rows * n_pad);
+    if (codes.size() > ctx->ws.codes.bytes) return fail(ADMM_E_INVALID_ARG, "problem does not match the recorded codes");
+    HIPCHK(hipMemcpy(codes.data(), ctx->ws.codes.p, codes.size(), hipMemcpyDeviceToHost));
+    for (size_t r = 0; r < rows; ++r) std::memcpy(out + r * pr->n, codes.data() + r * n_pad, pr->n);
+    return ADMM_OK;
+}
+
+// Kernel timing: each kernel of the plain path timed on its own, as a
+// captured graph of back-to-back launches of that kernel between one HIP
+// event pair (so launch gaps, not per-launch event overhead, are included),
+// then whole iterations through the captured iteration graph.
+static admm_status time_graph(admm_context *ctx, hipStream_t s, int reps, int per_graph,
+                              const std::function<void()> &enqueue, double *us_per_launch) {
+    hipGraph_t gr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < per_graph; ++c) enqueue();
+    HIPCHK(hipStreamEndCapture(s, &gr));
+    hipGraphExec_t gx;
+    hipError_t e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return fail(ADMM_E_DEVICE, "graph instantiate failed");
+    (void)hipGraphLaunch(gx, s);   // warm
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    for (int r = 0; r < reps; ++r) (void)hipGraphLaunch(gx, s);
+    HIPCHK(hipEventRecord(ctx->ev1, s));
+    e = hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(gx);
+    if (e != hipSuccess) return fail(ADMM_E_DEVICE, hipGetErrorString(e));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    *us_per_launch = 1000.0 * ms / ((double)reps * per_graph);
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, const admm_settings *settings,
+                                    int32_t iters, double *out) {
+    if (!ctx || !out) return fail(ADMM_E_INVALID_ARG, "NULL argument");
+    if (iters < 20 || iters > 100000) return fail(ADMM_E_INVALID_ARG, "iters must be in [20, 100000]");
+    admm_settings S = settings ? *settings : ctx->defaults;
+    S.max_iter = 1 << 30;
+    S.eps_primal = 0.0;
+    S.eps_dual = 0.0;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    if ((st = validate_problem_shape(pr)) != ADMM_OK) return st;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->own;
+    HIPCHK(hipEventRecord(ctx->join, ctx->user));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    SolveParams P;
+    int dtype = 0;
+    if ((st = prepare(ctx, pr, &S, P, dtype)) != ADMM_OK) return st;
+    if ((st = stage_problem(ctx, pr, P, dtype, s)) != ADMM_OK) return st;
+    HIPCHK(launch_cold_init(P, dtype, s));
+    const int per = 20, reps = std::max(1, iters / per);
+    double sw = 0, fi = 0, it = 0;
+    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, s); }, &sw)) != ADMM_OK) return st;
+    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, s); }, &fi)) != ADMM_OK) return st;
+    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, s); }, &it)) != ADMM_OK) return st;
+    out[0] = sw;
+    out[1] = fi;
+    out[2] = it;
+    out[3] = (double)reps * per;
+    HIPCHK(hipEventRecord(ctx->join, s));
+    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    return ADMM_OK;
+}
