@@ -86,7 +86,9 @@ def run_gpu(args, precision_name):
     byts = sweep_bytes(p.m, p.n, p.q, word)
     achieved = byts / (prof["sweep_us"] * 1e-6) / 1e9
     res["kernel_us"] = {"sweep": prof["sweep_us"], "finalize": prof["finalize_us"],
-                        "graph_iteration": prof["graph_iter_us"]}
+                        "graph_iteration": prof["graph_iter_us"],
+                        "persistent_iteration": prof["persist_iter_us"],
+                        "persistent_cols_per_thread": prof["persist_cols_per_thread"]}
     res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                        "bytes_per_launch": byts, "kernel": "k_sweep"}
@@ -105,6 +107,158 @@ def run_gpu(args, precision_name):
                         "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
     ctx.close()
     return res
+
+
+def _device_problem(p, dtype):
+    return to_device(p, dtype)
+
+
+def run_batch(args):
+    """4096 independent instances (m ~ U{2..8}, n log-uniform [50, 4000]) in
+    one batched launch, FP32 storage, to r, sigma < 1e-4, capacity penalty
+    rho_2 / n per instance.  Also the plain per-instance path on a sample."""
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    probs = W.batch_c3(count=args.batch_count)
+    dp = [_device_problem(p, torch.float32) for p in probs]
+    torch.cuda.synchronize()
+    ctx = admm.Context(0, hbm_budget_bytes=16 << 30)
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+                      rho2_per_step=True)
+    ctx.solve_batch(dp[:64], s)                     # warm-up (code objects, buffers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = ctx.solve_batch(dp, s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(i["iters"] for i in infos)
+    elem_iters = sum(i["iters"] * p.m * p.n for i, p in zip(infos, probs))
+    col_iters = sum(i["iters"] * p.n for i, p in zip(infos, probs))
+    conv = sum(i["status"] == admm.OK for i in infos)
+    byts = 4 * (6 * elem_iters + 3 * col_iters)
+    # plain per-instance path on a sample of the same instances
+    sample = list(range(0, len(dp), max(1, len(dp) // args.plain_sample)))[:args.plain_sample]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for b in sample:
+        ctx.solve(dp[b], s)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t1) / len(sample)
+    ctx.close()
+    return {"workload": f"{len(probs)} instances, m ~ U{{2..8}}, n log-uniform [50, 4000], f32 storage, "
+                        "residual 1e-4, rho_2 / n",
+            "solve_s": dt, "solves_per_s": conv / dt, "converged": conv, "instances": len(probs),
+            "instance_iters_per_s": iters / dt, "mean_iters": iters / len(probs),
+            "element_iters_per_s": elem_iters / dt,
+            "hbm_gbs_algorithmic": byts / dt / 1e9, "hbm_frac": byts / dt / 1e9 / HBM_PEAK_GBS,
+            "plain_path_solves_per_s": 1.0 / dt_plain, "plain_path_sample": len(sample),
+            "speedup_vs_plain": (conv / dt) * dt_plain}
+
+
+def run_serve(args):
+    """Open-loop Poisson client at --serve-rate requests/s for
+    --serve-seconds: requests with m in {2, 4}, n log-uniform [100, 50000],
+    256 warm-start keys, residual 1e-4, f32 storage.  Instances come from a
+    pool of --serve-pool seeded problems reused round-robin (generating
+    every request's arrays would cost more host time than the solves)."""
+    import math
+    import threading
+    import numpy as np
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    rng = np.random.default_rng(5)
+    pool = []
+    for r in range(args.serve_pool):
+        m = int(rng.choice([2, 4]))
+        n = int(round(math.exp(rng.uniform(math.log(100), math.log(50000)))))
+        pool.append(W.uniform_problem(m, n, 5 * 7_000_003 + r))
+    nreq = int(args.serve_rate * args.serve_seconds)
+    gaps = rng.exponential(1.0 / args.serve_rate, size=nreq)
+    keys = rng.integers(1, 257, size=nreq)
+    ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+                      rho2_per_step=True)
+    # warm-up
+    for p in pool[:8]:
+        t = ctx.submit(p, s)
+        while ctx.poll(t, p.m, p.n) is None:
+            time.sleep(0.001)
+    lat, iters, status = [], [], []
+    submitted = {}
+    done_flag = [False]
+    lock = threading.Lock()
+
+    def poller():
+        while True:
+            with lock:
+                items = list(submitted.items())
+            if not items and done_flag[0]:
+                return
+            for t, (p, ts) in items:
+                out = ctx.poll(t, p.m, p.n)
+                if out is not None:
+                    lat.append(time.perf_counter() - ts)
+                    iters.append(out[1]["iters"])
+                    status.append(out[1]["status"])
+                    with lock:
+                        del submitted[t]
+            time.sleep(0.0002)
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.perf_counter()
+    due = t0
+    for r in range(nreq):
+        due += gaps[r]
+        now = time.perf_counter()
+        if due > now:
+            time.sleep(due - now)
+        p = pool[r % len(pool)]
+        ts = time.perf_counter()
+        t = ctx.submit(p, s, warm_key=int(keys[r]))
+        with lock:
+            submitted[t] = (p, ts)
+    t_sub = time.perf_counter() - t0
+    done_flag[0] = True
+    th.join()
+    t_all = time.perf_counter() - t0
+    ctx.close()
+    lat_ms = np.array(lat) * 1000.0
+    return {"workload": f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, m in {{2,4}}, "
+                        f"n log-uniform [100, 50000] (pool of {len(pool)}), 256 warm keys, residual 1e-4, "
+                        "f32 storage, rho_2 / n",
+            "requests": nreq, "completed": len(lat), "converged": int(sum(st == admm.OK for st in status)),
+            "solves_per_s": len(lat) / t_all, "offered_per_s": nreq / t_sub,
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "max_ms": float(lat_ms.max()), "mean_iters": float(np.mean(iters)), "drain_s": t_all - t_sub}
+
+
+def run_robust(args):
+    """Robust two-source scenario program: m = 2, q = 200, n = 3600 (engine
+    quadratic, battery quartic, first-step consensus), f32 storage, to
+    r, sigma < 1e-4, rho = 1."""
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    p = W.phev_c4()
+    pd = _device_problem(p, torch.float32)
+    ctx = admm.Context(0)
+    out = {"workload": "m=2 q=200 n=3600 robust scenario program, f32 storage, residual 1e-4"}
+    for tag, r2 in (("rho1", False), ("rho2_per_step", True)):
+        s = admm.Settings(max_iter=args.robust_max_iter, eps_primal=1e-4, eps_dual=1e-4,
+                          precision=admm.F32_MIXED, rho2_per_step=r2)
+        ctx.solve(pd, admm.Settings(max_iter=50, eps_primal=0, eps_dual=0, precision=admm.F32_MIXED))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info, _ = ctx.solve(pd, s)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[tag] = {"status": info["status"], "iters": info["iters"], "solve_ms": dt * 1000,
+                    "iters_per_s": info["iters"] / dt, "r": info["r"], "sigma": info["sigma"],
+                    "objective": info["objective"]}
+    ctx.close()
+    return out
 
 
 def cpu_baseline(args):
@@ -134,11 +288,21 @@ def main():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--m", type=int, default=4)
     ap.add_argument("--profile-iters", type=int, default=400)
-    ap.add_argument("--converge-max-iter", type=int, default=200000)
+    ap.add_argument("--converge-max-iter", type=int, default=400000)
     ap.add_argument("--skip-converge", action="store_true")
     ap.add_argument("--skip-variant", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--skip-extras", action="store_true", help="only the headline plain-path run")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-pool", type=int, default=384)
+    ap.add_argument("--robust-max-iter", type=int, default=100000)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB 3 times (a plain copy kernel of known "
+                         "size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -149,6 +313,15 @@ def main():
     from paper_1903_10041_amd import build as hb
     if not os.path.exists(hb.LIB):
         hb.build()
+    if args.copy_calibration_mib:
+        import torch
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     head = run_gpu(args, args.precision)
     other = "f64" if args.precision == "f32" else "f32"
     variant = None
@@ -156,6 +329,11 @@ def main():
         a2 = argparse.Namespace(**vars(args))
         a2.steps = max(100, args.steps // 2)
         variant = run_gpu(a2, other)
+    extras = {}
+    if not args.skip_extras:
+        extras["batched"] = run_batch(args)
+        extras["served"] = run_serve(args)
+        extras["robust"] = run_robust(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
     storage = {"f32": "f32 storage, f64 arithmetic", "f64": "f64"}
@@ -181,6 +359,7 @@ def main():
         "solve": head.get("solve"),
         "variants": {other: variant} if variant else None,
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
 
 

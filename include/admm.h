@@ -104,6 +104,7 @@ typedef struct {
     admm_sweep sweep;
     int32_t consensus_q1;            /* keep the rho_4 block when q == 1 (default 0) */
     int32_t debug_branch_codes;      /* record per-element branch codes of the last x-step */
+    int32_t rho2_per_step;           /* 1: the capacity block uses rho_2 / n (default 0) */
 } admm_settings;
 
 /* Iterate of (7a)-(7i), in the paper's variables, host doubles.  Any NULL
@@ -133,7 +134,11 @@ typedef struct {
 } admm_info;
 
 /* Defaults: rho = 1, eps = 1e-6, max_iter = 10000, check_every = 10, F64,
- * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes. */
+ * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes,
+ * rho2_per_step = 0.  rho2_per_step scales the penalty of the capacity
+ * constraint sum_k z_k = h (one constraint over n terms) by 1/n per
+ * instance; with rho_2 = rho_1 the iteration count grows about linearly in
+ * n, with rho_2 = rho_1 / n it stays near a hundred for any n. */
 void admm_default_settings(admm_settings *s);
 
 /* Create a context on HIP device `device` (the calling thread's current
@@ -186,11 +191,25 @@ admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key);
  * graph of back-to-back launches of that kernel, replayed between one HIP
  * event pair, for about `iters` (20..100000) launches each; then whole
  * iterations the same way.  out[4]: mean microseconds per sweep launch, per
- * finalize launch, per iteration, and the launch count.  Thresholds are
- * ignored.  The timed launches advance the iterate; results are not
- * returned. */
+ * finalize launch, per iteration, and the launch count; out[4], out[5]:
+ * when the problem takes the resident persistent path, microseconds per
+ * iteration of one cooperative launch and its columns per thread (else 0).
+ * Thresholds are ignored; the timed launches advance the iterate and
+ * results are not returned.  out must hold 6 doubles. */
 admm_status admm_profile(admm_context *ctx, const admm_problem *prob,
                          const admm_settings *settings, int32_t iters, double *out);
+
+/* Test hooks.  admm_debug_codes: branch codes (3*branch + clamp state) of
+ * the last x-step of the previous debug_branch_codes solve of `prob`,
+ * [q][m][n] bytes.  admm_debug_quartic: the device x-step minimiser of
+ * A x^4 + B x^3 + C x^2 + D x over [lo, hi] (Alg. 1 with the box rule of
+ * `paper_project`, in the arithmetic of `precision`) applied to N host
+ * arrays; writes x_out[N] and codes_out[N]. */
+admm_status admm_debug_codes(admm_context *ctx, const admm_problem *prob, uint8_t *out);
+admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const double *A, const double *B,
+                               const double *C, const double *D, const double *lo, const double *hi,
+                               int32_t paper_project, int32_t precision, double *x_out,
+                               int32_t *codes_out);
 
 void admm_destroy(admm_context *ctx);
 const char *admm_status_string(admm_status s);

@@ -50,7 +50,8 @@ class _Settings(C.Structure):
                 ("eps_dual", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("paper_project", C.c_int32),
                 ("jacobi", C.c_int32), ("consensus_q1", C.c_int32),
-                ("nthreads", C.c_int32)]
+                ("nthreads", C.c_int32), ("adaptive_rho", C.c_int32),
+                ("tau", C.c_double), ("band_hi", C.c_double), ("band_lo", C.c_double)]
 
 
 class _State(C.Structure):
@@ -62,7 +63,7 @@ class _Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32),
                 ("r", C.c_double), ("sigma", C.c_double),
                 ("objective", C.c_double), ("branch_count", C.c_int64 * 15),
-                ("n_hist", C.c_int32)]
+                ("n_hist", C.c_int32), ("rho_final", C.c_double * 4)]
 
 
 _lib = None
@@ -158,7 +159,7 @@ def objective(prob, x) -> float:
 
 def validate(prob, rho=(1.0, 1.0, 1.0, 1.0)) -> bool:
     keep = _Keep(prob)
-    s = _Settings((C.c_double * 4)(*rho), 0.0, 0.0, 1, 10, 0, 0, 0, 1)
+    s = _Settings((C.c_double * 4)(*rho), 0.0, 0.0, 1, 10, 0, 0, 0, 1, 0, 1.1, 1.2, 0.8)
     return lib().oracle_validate(C.byref(keep.st), C.byref(s)) == 0
 
 
@@ -166,7 +167,8 @@ def run(prob, *, max_iter: int = 500, eps_primal: float = 0.0, eps_dual: float =
         check_every: int = 10, rho=None, paper_project: bool = False,
         jacobi: bool = False, consensus_q1: bool = False, nthreads: int = 1,
         state: dict | None = None, want_codes: bool = False,
-        want_coef: bool = False):
+        want_coef: bool = False, adaptive_rho: bool = False, tau: float = 1.1,
+        band_hi: float = 1.2, band_lo: float = 0.8):
     """Run (7a)-(7i) from ``state`` (cold start if None).
 
     Returns (state, info dict, history array of rows (t, r, sigma)).  The
@@ -181,7 +183,8 @@ def run(prob, *, max_iter: int = 500, eps_primal: float = 0.0, eps_dual: float =
               for k, s in _state_shapes(prob).items()}
     S = _Settings((C.c_double * 4)(*rho), float(eps_primal), float(eps_dual),
                   int(max_iter), int(check_every), int(paper_project), int(jacobi),
-                  int(consensus_q1), int(nthreads))
+                  int(consensus_q1), int(nthreads), int(adaptive_rho), float(tau),
+                  float(band_hi), float(band_lo))
     nh = max(1, max_iter // max(1, check_every))
     hist = np.zeros((nh, 3))
     E = prob.m * prob.n * prob.q
@@ -194,7 +197,8 @@ def run(prob, *, max_iter: int = 500, eps_primal: float = 0.0, eps_dual: float =
         raise ValueError(f"oracle: invalid input (status {rc})")
     out = {"status": info.status, "iters": info.iters, "r": info.r,
            "sigma": info.sigma, "objective": info.objective,
-           "branch_count": np.array(list(info.branch_count), dtype=np.int64)}
+           "branch_count": np.array(list(info.branch_count), dtype=np.int64),
+           "rho": tuple(info.rho_final)}
     if want_codes:
         out["codes"] = codes.reshape(prob.q, prob.m, prob.n)
     if want_coef:

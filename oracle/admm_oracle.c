@@ -39,6 +39,11 @@
  *       treated as the triple root.
  *   R10 a tie delta_f = 0 keeps the smaller root x_1.
  *   R11 A = 0 (g2 = 0) is the quadratic x = clamp(-D / 2C).
+ *   R12 adaptive rho (Sec. IV-A): at a check iteration that does not stop,
+ *       all rho_i are multiplied by tau when r/sigma > band_hi * rbar/sbar
+ *       and divided by tau when r/sigma < band_lo * rbar/sbar; the scaled
+ *       multipliers mu, lambda, nu, p are divided by the same factor, so the
+ *       unscaled multipliers rho * (.) are unchanged.
  */
 #include <math.h>
 #include <stdint.h>
@@ -214,6 +219,8 @@ typedef struct {
     int32_t jacobi;                  /* R3 */
     int32_t consensus_q1;            /* R1 */
     int32_t nthreads;
+    int32_t adaptive_rho;            /* R12: residual balancing at check iterations */
+    double tau, band_hi, band_lo;    /* Sec. IV-A: 1.1, 1.2, 0.8 */
 } oracle_settings;
 
 typedef struct {
@@ -229,6 +236,7 @@ typedef struct {
     double r, sigma, objective;
     int64_t branch_count[15];        /* codes of the last x-step */
     int32_t n_hist;
+    double rho_final[4];
 } oracle_info;
 
 #define EIDX(j, i, k) ((((int64_t)(j) * m) + (i)) * n + (k))
@@ -350,7 +358,7 @@ int oracle_run(const oracle_problem *P, const oracle_settings *S,
     if (oracle_validate(P, S) != 0) { info->status = -1; return -1; }
     const int m = P->m, n = P->n, q = P->q;
     const int64_t E = (int64_t)m * n * q, K = (int64_t)n * q, M = (int64_t)m * q;
-    const double rho1 = S->rho[0], rho2 = S->rho[1], rho3 = S->rho[2], rho4 = S->rho[3];
+    double rho1 = S->rho[0], rho2 = S->rho[1], rho3 = S->rho[2], rho4 = S->rho[3];
     const int consensus = (q > 1) || S->consensus_q1;
     int nt = S->nthreads > 0 ? S->nthreads : 1;
     (void)nt;
@@ -507,12 +515,28 @@ int oracle_run(const oracle_problem *P, const oracle_settings *S,
             }
             ++nh;
             if (r < S->eps_primal && sigma < S->eps_dual) { status = 0; break; }
+            if (S->adaptive_rho) {
+                const double target = (S->eps_primal > 0.0 && S->eps_dual > 0.0)
+                                    ? S->eps_primal / S->eps_dual : 1.0;
+                const double ratio = sigma > 0.0 ? r / sigma : INFINITY;
+                double f = 1.0;
+                if (ratio > S->band_hi * target) f = S->tau;
+                else if (ratio < S->band_lo * target) f = 1.0 / S->tau;
+                if (f != 1.0) {
+                    rho1 *= f; rho2 *= f; rho3 *= f; rho4 *= f;
+                    for (int64_t jk = 0; jk < K; ++jk) X->mu[jk] /= f;
+                    for (int64_t e = 0; e < E; ++e) X->lam[e] /= f;
+                    for (int64_t ij = 0; ij < M; ++ij) { X->p[ij] /= f; X->nu[ij] /= f; }
+                }
+            }
         }
     }
     if (t > S->max_iter) t = S->max_iter;
 
     info->status = status;
     info->iters = t;
+    info->rho_final[0] = rho1; info->rho_final[1] = rho2;
+    info->rho_final[2] = rho3; info->rho_final[3] = rho4;
     info->r = r;
     info->sigma = sigma;
     info->objective = oracle_objective(P, X->x);

@@ -51,7 +51,7 @@ class admm_settings(C.Structure):
                 ("eps_dual", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int),
                 ("xstep", C.c_int), ("sweep", C.c_int), ("consensus_q1", C.c_int32),
-                ("debug_branch_codes", C.c_int32)]
+                ("debug_branch_codes", C.c_int32), ("rho2_per_step", C.c_int32)]
 
 
 class admm_state(C.Structure):
@@ -98,6 +98,7 @@ def lib():
             "admm_last_error": (C.c_char_p, []),
             "admm_debug_codes": (C.c_int, [vp, vp, vp]),
             "admm_profile": (C.c_int, [vp, vp, vp, i32, vp]),
+            "admm_debug_quartic": (C.c_int, [vp, C.c_int64] + [vp] * 6 + [i32, i32, vp, vp]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -129,13 +130,14 @@ class Settings:
     sweep: int = SWEEP_GAUSS_SEIDEL
     consensus_q1: bool = False
     debug_branch_codes: bool = False
+    rho2_per_step: bool = False
 
     def to_c(self) -> admm_settings:
         return admm_settings((C.c_double * 4)(*[float(r) for r in self.rho]),
                              float(self.eps_primal), float(self.eps_dual), int(self.max_iter),
                              int(self.check_every), int(self.precision), int(self.xstep),
                              int(self.sweep), int(bool(self.consensus_q1)),
-                             int(bool(self.debug_branch_codes)))
+                             int(bool(self.debug_branch_codes)), int(bool(self.rho2_per_step)))
 
 
 def _is_torch(a) -> bool:
@@ -238,6 +240,33 @@ class Context:
         except Exception:
             pass
 
+    def solve_batch(self, probs, settings: Optional[Settings] = None, x_outs=None):
+        return _solve_batch(self, probs, settings, x_outs)
+
+    def submit(self, prob, settings: Optional[Settings] = None, warm_key: int = 0) -> int:
+        """admm_submit (host arrays).  Returns the ticket."""
+        mp = _Marshal(prob)
+        if mp.device:
+            raise TypeError("admm_submit takes host arrays")
+        s = settings.to_c() if settings else None
+        t = C.c_uint64()
+        _check(lib().admm_submit(self.h, C.byref(mp.st), C.byref(s) if s is not None else None,
+                                 int(warm_key), C.byref(t)), allow=(OK,))
+        return t.value
+
+    def poll(self, ticket: int, m: int, n: int, q: int = 1):
+        """admm_poll.  Returns None while not ready, else (x, info)."""
+        x = np.empty((q, m, n))
+        inf = admm_info()
+        st = lib().admm_poll(self.h, int(ticket), x.ctypes.data, C.byref(inf))
+        if st == NOT_READY:
+            return None
+        _check(st)
+        return x, info_dict(inf)
+
+    def release_warm(self, key: int):
+        _check(lib().admm_release_warm(self.h, int(key)), allow=(OK,))
+
     def set_stream(self, stream_handle: Optional[int]):
         _check(lib().admm_set_stream(self.h, stream_handle), allow=(OK,))
 
@@ -281,21 +310,62 @@ class Context:
         return x_out, out, st_out
 
 
+def _solve_batch(ctx, probs, settings=None, x_outs=None):
+    n = len(probs)
+    ms = [_Marshal(p) for p in probs]
+    arr = (admm_problem * max(1, n))(*[m.st for m in ms])
+    s = settings.to_c() if settings else None
+    dev = n > 0 and ms[0].device
+    if x_outs is None:
+        if dev:
+            import torch
+            x_outs = [torch.empty((p.q, p.m, p.n), dtype=p.f2.dtype, device=p.f2.device) for p in probs]
+        else:
+            x_outs = [np.empty((p.q, p.m, p.n)) for p in probs]
+    ptrs = (C.c_void_p * max(1, n))(*[(x.data_ptr() if dev else x.ctypes.data) for x in x_outs])
+    infos = (admm_info * max(1, n))()
+    if dev:
+        import torch
+        ctx.set_stream(torch.cuda.current_stream(probs[0].f2.device).cuda_stream)
+    st = lib().admm_solve_batch(ctx.h, n, arr, C.byref(s) if s is not None else None, None, ptrs, infos)
+    _check(st)
+    return x_outs, [info_dict(infos[i]) for i in range(n)]
+
+
+def admm_solve_batch(ctx: "Context", probs, settings: Optional[Settings] = None, x_outs=None):
+    """Solve many independent instances in one batched launch.  Returns
+    (list of x, list of info dicts)."""
+    return _solve_batch(ctx, probs, settings, x_outs)
+
+
 def _profile(ctx, prob, settings, iters):
     mp = _Marshal(prob)
     s = settings.to_c() if settings else None
-    out = (C.c_double * 4)()
+    out = (C.c_double * 6)()
     if mp.device:
         import torch
         ctx.set_stream(torch.cuda.current_stream(prob.f2.device).cuda_stream)
     _check(lib().admm_profile(ctx.h, C.byref(mp.st), C.byref(s) if s is not None else None,
                               int(iters), out), allow=(OK,))
-    return {"sweep_us": out[0], "finalize_us": out[1], "graph_iter_us": out[2], "iters": int(out[3])}
+    return {"sweep_us": out[0], "finalize_us": out[1], "graph_iter_us": out[2], "iters": int(out[3]),
+            "persist_iter_us": out[4], "persist_cols_per_thread": int(out[5])}
 
 
 def admm_profile(ctx: "Context", prob, settings: Optional[Settings] = None, iters: int = 200) -> dict:
     """Per-kernel timing of the plain path (HIP events around each launch)."""
     return _profile(ctx, prob, settings, iters)
+
+
+def admm_debug_quartic(ctx: "Context", A, B, Cc, D, lo, hi, paper_project=False, precision=F64):
+    """Device quartic minimiser on arrays (returns x, codes)."""
+    arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), np.shape(A)).ravel())
+            for v in (A, B, Cc, D, lo, hi)]
+    N = arrs[0].size
+    x = np.empty(N)
+    codes = np.empty(N, dtype=np.int32)
+    _check(lib().admm_debug_quartic(ctx.h, N, *[a.ctypes.data for a in arrs], int(paper_project),
+                                    int(precision), x.ctypes.data, codes.ctypes.data), allow=(OK,))
+    return x.reshape(np.shape(A)), codes.reshape(np.shape(A))
 
 
 def admm_create(device: int = 0, hbm_budget_bytes: int = 0, defaults: Optional[Settings] = None) -> Context:

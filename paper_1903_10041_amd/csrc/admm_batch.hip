@@ -1,10 +1,366 @@
-// Batched and served solves (placeholder entry points until the persistent
-// batched kernel lands).
+// Batched solve (admm_solve_batch) and the serving engine (admm_submit /
+// admm_poll) on top of the block-per-instance kernel k_batch.
+#include "admm_batch_kernels.hpp"
 #include "admm_host.hpp"
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
 namespace admm {
-void batch_release(admm_context *) {}
-void serve_shutdown(admm_context *) {}
+
+// Source pointers of one instance for the pack kernel (device memory, of
+// the caller's dtype S).
+struct PackSrc {
+    const void *f2, *f1, *g2, *g1, *y, *lo, *hi;
+};
+
+template <typename T, typename S>
+__global__ __launch_bounds__(kBlock) void k_batch_pack(BatchParams B, const PackSrc *src, int32_t *bad) {
+    for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
+        const BInst I = B.inst[b];
+        const PackSrc P = src[b];
+        V4<T> *coef = (V4<T> *)B.coef + I.coef_off;
+        T *y = (T *)B.y + I.col_off;
+        const int m = I.m, n = I.n, np = I.n_pad;
+        int badl = 0;
+        for (int e = threadIdx.x; e < m * np; e += kBlock) {
+            const int i = e / np, k = e - i * np;
+            V4<T> v = {T(0), T(0), T(0), T(0)};
+            if (k < n) {
+                const size_t s = (size_t)i * n + k;
+                const double a = (double)((const S *)P.f2)[s], bb = (double)((const S *)P.f1)[s];
+                const double c = (double)((const S *)P.g2)[s], d = (double)((const S *)P.g1)[s];
+                if (!(a >= 0.0) || !(c >= 0.0) || !isfinite(a) || !isfinite(bb) || !isfinite(c) || !isfinite(d))
+                    badl = 1;
+                v.a = (T)a; v.b = (T)bb; v.c = (T)c; v.d = (T)d;
+            }
+            coef[e] = v;
+        }
+        for (int k = threadIdx.x; k < np; k += kBlock) {
+            double v = 0.0;
+            if (k < n) {
+                v = (double)((const S *)P.y)[k];
+                if (!isfinite(v)) badl = 1;
+            }
+            y[k] = (T)v;
+        }
+        if (threadIdx.x < m) {
+            const int i = threadIdx.x;
+            double lo = (double)((const S *)P.lo)[i], hi = (double)((const S *)P.hi)[i];
+            if (!isfinite(lo) || !isfinite(hi) || lo > hi) badl = 1;
+            if (sizeof(T) == 4) { lo = (double)(float)lo; hi = (double)(float)hi; }
+            B.pool[I.pool_off + 4 * m + i] = lo;
+            B.pool[I.pool_off + 5 * m + i] = hi;
+        }
+        if (badl) atomicOr(&bad[b], 1);
+    }
+}
+
+template <typename T, typename D>
+__global__ __launch_bounds__(kBlock) void k_batch_unpack(BatchParams B, D *const *dst) {
+    for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
+        const BInst I = B.inst[b];
+        const T *x = (const T *)B.x + I.x_off;
+        D *out = dst[b];
+        for (int e = threadIdx.x; e < I.m * I.n; e += kBlock) {
+            const int i = e / I.n, k = e - i * I.n;
+            out[e] = (D)x[(size_t)i * I.n_pad + k];
+        }
+    }
+}
+
+// Grid of a batch kernel: all resident blocks, no more than the queue.
+template <typename K>
+static int batch_grid(admm_context *ctx, K kernel, int count) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    return std::max(1, std::min(count, nb * std::max(1, ctx->num_cu)));
+}
+
+template <typename T, bool MIXED>
+static hipError_t launch_batch_class(admm_context *ctx, int cls, const BatchParams &B, bool init, hipStream_t s) {
+    if (B.count == 0) return hipSuccess;
+    if (cls == 0) {
+        if (init) k_batch_init<T, 2><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
+        k_batch<T, 2, MIXED><<<batch_grid(ctx, k_batch<T, 2, MIXED>, B.count), kBlock, 0, s>>>(B);
+    } else if (cls == 1) {
+        if (init) k_batch_init<T, 4><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
+        k_batch<T, 4, MIXED><<<batch_grid(ctx, k_batch<T, 4, MIXED>, B.count), kBlock, 0, s>>>(B);
+    } else {
+        if (init) k_batch_init<T, 8><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
+        k_batch<T, 8, MIXED><<<batch_grid(ctx, k_batch<T, 8, MIXED>, B.count), kBlock, 0, s>>>(B);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(admm_context *ctx, int dtype, int cls, const BatchParams &B, bool init, hipStream_t s) {
+    return dtype == 0 ? launch_batch_class<double, false>(ctx, cls, B, init, s)
+                      : launch_batch_class<float, true>(ctx, cls, B, init, s);
+}
+
+int batch_class(int m) { return m <= 2 ? 0 : (m <= 4 ? 1 : 2); }
+
+struct BatchState {
+    DevBuf coef, x, y, w, pool, inst, order, next, bad, src, stage, outp;
+    hipStream_t cs[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+static admm_status batch_state(admm_context *ctx, BatchState *&bs) {
+    if (!ctx->batch) {
+        bs = new BatchState();
+        for (int c = 0; c < 3; ++c)
+            if (hipStreamCreateWithFlags(&bs->cs[c], hipStreamNonBlocking) != hipSuccess)
+                return fail(ADMM_E_DEVICE, "stream creation failed");
+        for (int e = 0; e < 4; ++e)
+            if (hipEventCreateWithFlags(&bs->ev[e], hipEventDisableTiming) != hipSuccess)
+                return fail(ADMM_E_DEVICE, "event creation failed");
+        ctx->batch = bs;
+    }
+    bs = ctx->batch;
+    return ADMM_OK;
+}
+
+void batch_release(admm_context *ctx) {
+    BatchState *bs = ctx->batch;
+    if (!bs) return;
+    for (DevBuf *b : {&bs->coef, &bs->x, &bs->y, &bs->w, &bs->pool, &bs->inst, &bs->order, &bs->next, &bs->bad,
+                      &bs->src, &bs->stage, &bs->outp})
+        ctx->arena.release(*b);
+    for (auto s : bs->cs)
+        if (s) (void)hipStreamDestroy(s);
+    for (auto e : bs->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete bs;
+    ctx->batch = nullptr;
+}
+
+#define BCHK(x)                                                                     \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(ADMM_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static bool batchable(const admm_problem &p) {
+    return p.q == 1 && !p.g0 && !p.f0 && p.bounds == ADMM_BOUNDS_PER_SOURCE;
+}
+
+// Batched solve of the instances `idx` (all batchable, one memspace/dtype).
+static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs, const std::vector<int> &idx,
+                                    const admm_settings &S, void *const *x_out, admm_info *infos) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const int cnt = (int)idx.size();
+    if (cnt == 0) return ADMM_OK;
+    BatchState *bs = nullptr;
+    admm_status st = batch_state(ctx, bs);
+    if (st != ADMM_OK) return st;
+    const int dtype = S.precision == ADMM_F64 ? 0 : 1;
+    const size_t T = dtype == 0 ? 8 : 4;
+    const admm_problem &p0 = probs[idx[0]];
+    const bool host = p0.mem == ADMM_HOST;
+    const int src_dtype = host ? 0 : (p0.dtype == ADMM_F64 ? 0 : 1);
+    const size_t ST = src_dtype == 0 ? 8 : 4;
+
+    std::vector<BInst> inst(cnt);
+    size_t E = 0, K = 0, PO = 0, SRC = 0, OUT = 0;
+    for (int b = 0; b < cnt; ++b) {
+        const admm_problem &p = probs[idx[b]];
+        BInst &I = inst[b];
+        std::memset(&I, 0, sizeof I);
+        I.m = p.m;
+        I.n = p.n;
+        I.n_pad = (p.n + kPad - 1) / kPad * kPad;
+        I.status = -1;
+        I.max_iter = S.max_iter;
+        I.check_every = S.check_every;
+        I.flags = (S.xstep == ADMM_XSTEP_PAPER_PROJECT ? 1 : 0) | (S.sweep == ADMM_SWEEP_JACOBI ? 2 : 0);
+        for (int r = 0; r < 4; ++r) I.rho[r] = S.rho[r];
+        if (S.rho2_per_step) I.rho[1] = S.rho[1] / (double)p.n;
+        I.eps_p = S.eps_primal;
+        I.eps_d = S.eps_dual;
+        I.coef_off = (int64_t)E;
+        I.x_off = (int64_t)E;
+        I.col_off = (int64_t)K;
+        I.w_off = (int64_t)K;
+        I.pool_off = (int64_t)PO;
+        E += (size_t)p.m * I.n_pad;
+        K += I.n_pad;
+        PO += (size_t)kPoolPerSource * p.m;
+        SRC += 4 * (size_t)p.m * p.n + p.n + 2 * (size_t)p.m;
+        OUT += (size_t)p.m * p.n;
+    }
+    Arena &A = ctx->arena;
+#define ENS(buf, bytes) if ((st = A.ensure(buf, bytes)) != ADMM_OK) return st
+    ENS(bs->coef, E * 4 * T);
+    ENS(bs->x, E * T);
+    ENS(bs->y, K * T);
+    ENS(bs->w, K * T);
+    ENS(bs->pool, PO * sizeof(double));
+    ENS(bs->inst, cnt * sizeof(BInst));
+    ENS(bs->order, 3 * (size_t)cnt * sizeof(int32_t));
+    ENS(bs->next, 4 * sizeof(int32_t));
+    ENS(bs->bad, cnt * sizeof(int32_t));
+    ENS(bs->src, cnt * sizeof(PackSrc) + cnt * sizeof(void *));
+    if (host) ENS(bs->stage, SRC * sizeof(double));
+    ENS(bs->outp, OUT * (host ? sizeof(double) : 1));
+#undef ENS
+    hipStream_t s = ctx->own;
+    BCHK(hipEventRecord(ctx->join, ctx->user));
+    BCHK(hipStreamWaitEvent(s, ctx->join, 0));
+
+    // sources: the caller's device arrays, or host arrays staged in one copy
+    std::vector<PackSrc> src(cnt);
+    std::vector<double> pool_img(PO, 0.0);
+    if (host) {
+        std::vector<double> img(SRC);
+        size_t o = 0;
+        for (int b = 0; b < cnt; ++b) {
+            const admm_problem &p = probs[idx[b]];
+            const size_t en = (size_t)p.m * p.n;
+            double *base = (double *)bs->stage.p;
+            auto put = [&](const void *a, size_t len) -> const void * {
+                std::memcpy(img.data() + o, a, len * sizeof(double));
+                const void *d = base + o;
+                o += len;
+                return d;
+            };
+            src[b].f2 = put(p.f2, en);
+            src[b].f1 = put(p.f1, en);
+            src[b].g2 = put(p.g2, en);
+            src[b].g1 = put(p.g1, en);
+            src[b].y = put(p.y, p.n);
+            src[b].lo = put(p.x_lo, p.m);
+            src[b].hi = put(p.x_hi, p.m);
+        }
+        BCHK(hipMemcpyAsync(bs->stage.p, img.data(), SRC * sizeof(double), hipMemcpyHostToDevice, s));
+        BCHK(hipStreamSynchronize(s));
+    } else {
+        for (int b = 0; b < cnt; ++b) {
+            const admm_problem &p = probs[idx[b]];
+            src[b] = {p.f2, p.f1, p.g2, p.g1, p.y, p.x_lo, p.x_hi};
+        }
+    }
+    (void)ST;
+    for (int b = 0; b < cnt; ++b) {
+        const admm_problem &p = probs[idx[b]];
+        for (int i = 0; i < p.m; ++i) pool_img[inst[b].pool_off + 6 * p.m + i] = p.c[i];
+    }
+    BCHK(hipMemcpyAsync(bs->inst.p, inst.data(), cnt * sizeof(BInst), hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(bs->pool.p, pool_img.data(), PO * sizeof(double), hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(bs->src.p, src.data(), cnt * sizeof(PackSrc), hipMemcpyHostToDevice, s));
+    BCHK(hipMemsetAsync(bs->bad.p, 0, cnt * sizeof(int32_t), s));
+    BatchParams B;
+    B.inst = (BInst *)bs->inst.p;
+    B.order = nullptr;
+    B.count = cnt;
+    B.window = S.max_iter;
+    B.next = (int32_t *)bs->next.p;
+    B.coef = bs->coef.p;
+    B.x = bs->x.p;
+    B.y = bs->y.p;
+    B.w = bs->w.p;
+    B.pool = (double *)bs->pool.p;
+    const int pg = std::min(cnt, 4096);
+    if (dtype == 0 && src_dtype == 0) k_batch_pack<double, double><<<pg, kBlock, 0, s>>>(B, (const PackSrc *)bs->src.p, (int32_t *)bs->bad.p);
+    else if (dtype == 0) k_batch_pack<double, float><<<pg, kBlock, 0, s>>>(B, (const PackSrc *)bs->src.p, (int32_t *)bs->bad.p);
+    else if (src_dtype == 0) k_batch_pack<float, double><<<pg, kBlock, 0, s>>>(B, (const PackSrc *)bs->src.p, (int32_t *)bs->bad.p);
+    else k_batch_pack<float, float><<<pg, kBlock, 0, s>>>(B, (const PackSrc *)bs->src.p, (int32_t *)bs->bad.p);
+    BCHK(hipGetLastError());
+    std::vector<int32_t> bad(cnt);
+    BCHK(hipMemcpyAsync(bad.data(), bs->bad.p, cnt * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    for (int b = 0; b < cnt; ++b)
+        if (bad[b])
+            return fail(ADMM_E_INVALID_ARG, "batch instance " + std::to_string(idx[b]) +
+                                                ": arrays must be finite, with f2, g2 >= 0 and x_lo <= x_hi");
+
+    // per-class queues, longest first (work ~ m n^2: iterations grow with n)
+    std::vector<int32_t> order[3];
+    for (int b = 0; b < cnt; ++b) order[batch_class(inst[b].m)].push_back(b);
+    for (auto &o : order)
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
+            return (double)inst[a].m * inst[a].n * inst[a].n > (double)inst[b].m * inst[b].n * inst[b].n;
+        });
+    std::vector<int32_t> ord_all(3 * (size_t)cnt, 0);
+    for (int c = 0; c < 3; ++c) std::copy(order[c].begin(), order[c].end(), ord_all.begin() + (size_t)c * cnt);
+    BCHK(hipMemcpyAsync(bs->order.p, ord_all.data(), 3 * (size_t)cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    BCHK(hipMemsetAsync(bs->next.p, 0, 4 * sizeof(int32_t), s));
+    BCHK(hipEventRecord(bs->ev[0], s));
+    BCHK(hipEventRecord(ctx->ev0, s));
+    for (int c = 0; c < 3; ++c) {
+        if (order[c].empty()) continue;
+        BCHK(hipStreamWaitEvent(bs->cs[c], bs->ev[0], 0));
+        BatchParams Bc = B;
+        Bc.order = (const int32_t *)bs->order.p + (size_t)c * cnt;
+        Bc.count = (int)order[c].size();
+        Bc.next = (int32_t *)bs->next.p + c;
+        BCHK(launch_batch(ctx, dtype, c, Bc, true, bs->cs[c]));
+        BCHK(hipEventRecord(bs->ev[1 + c], bs->cs[c]));
+        BCHK(hipStreamWaitEvent(s, bs->ev[1 + c], 0));
+    }
+    BCHK(hipEventRecord(ctx->ev1, s));
+    // outputs
+    std::vector<void *> dst(cnt);
+    if (host) {
+        size_t o = 0;
+        for (int b = 0; b < cnt; ++b) {
+            dst[b] = (double *)bs->outp.p + o;
+            o += (size_t)inst[b].m * inst[b].n;
+        }
+    } else {
+        for (int b = 0; b < cnt; ++b) dst[b] = x_out[idx[b]];
+    }
+    void **dst_dev = (void **)((char *)bs->src.p + cnt * sizeof(PackSrc));
+    BCHK(hipMemcpyAsync(dst_dev, dst.data(), cnt * sizeof(void *), hipMemcpyHostToDevice, s));
+    const int out_dtype = host ? 0 : src_dtype;
+    if (dtype == 0 && out_dtype == 0) k_batch_unpack<double, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
+    else if (dtype == 0) k_batch_unpack<double, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
+    else if (out_dtype == 0) k_batch_unpack<float, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
+    else k_batch_unpack<float, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
+    BCHK(hipGetLastError());
+    std::vector<BInst> fin(cnt);
+    BCHK(hipMemcpyAsync(fin.data(), bs->inst.p, cnt * sizeof(BInst), hipMemcpyDeviceToHost, s));
+    std::vector<double> hout;
+    if (host) {
+        hout.resize(OUT);
+        BCHK(hipMemcpyAsync(hout.data(), bs->outp.p, OUT * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    BCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (host) {
+        size_t o = 0;
+        for (int b = 0; b < cnt; ++b) {
+            const size_t en = (size_t)inst[b].m * inst[b].n;
+            std::memcpy(x_out[idx[b]], hout.data() + o, en * sizeof(double));
+            o += en;
+        }
+    }
+    const double total = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    for (int b = 0; b < cnt; ++b) {
+        admm_info &inf = infos[idx[b]];
+        std::memset(&inf, 0, sizeof inf);
+        const BInst &I = fin[b];
+        inf.status = I.status == 0 ? ADMM_OK : (I.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
+        inf.iters = I.t;
+        inf.r = I.r;
+        inf.sigma = I.sigma;
+        inf.objective = I.objective;
+        inf.device_ms = ms;
+        inf.total_ms = total;
+    }
+    BCHK(hipEventRecord(ctx->join, s));
+    BCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    return ADMM_OK;
+}
+
 }  // namespace admm
 
 using namespace admm;
@@ -12,22 +368,709 @@ using namespace admm;
 extern "C" admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
                                         const admm_settings *settings, const admm_state *const *warm,
                                         void *const *x_out, admm_info *infos) {
-    (void)ctx; (void)count; (void)probs; (void)settings; (void)warm; (void)x_out; (void)infos;
-    return fail(ADMM_E_UNSUPPORTED, "admm_solve_batch: not built yet");
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    if (count < 0 || (count > 0 && (!probs || !x_out || !infos)))
+        return fail(ADMM_E_INVALID_ARG, "probs, x_out and infos are required");
+    if (count == 0) return ADMM_OK;
+    const admm_settings S = settings ? *settings : ctx->defaults;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    for (int b = 0; b < count; ++b) {
+        if ((st = validate_problem_shape(&probs[b])) != ADMM_OK)
+            return fail(st, "batch instance " + std::to_string(b) + ": " + g_last_error);
+        if (!x_out[b]) return fail(ADMM_E_INVALID_ARG, "x_out[" + std::to_string(b) + "] is NULL");
+        if (probs[b].mem != probs[0].mem || (probs[b].mem == ADMM_DEVICE && probs[b].dtype != probs[0].dtype))
+            return fail(ADMM_E_INVALID_ARG, "all batch instances must share one memspace and dtype");
+    }
+    // instances outside the batched kernel (q > 1, g0/f0, per-step bounds,
+    // warm states) are solved one by one through the plain path
+    std::vector<int> in_batch, alone;
+    for (int b = 0; b < count; ++b) {
+        const bool w = warm && warm[b] && warm[b]->x;
+        (batchable(probs[b]) && !w ? in_batch : alone).push_back(b);
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        DeviceGuard g(ctx->device);
+        if ((st = solve_batch_core(ctx, probs, in_batch, S, x_out, infos)) != ADMM_OK) return st;
+    }
+    for (int b : alone) {
+        st = admm_solve(ctx, &probs[b], &S, warm ? warm[b] : nullptr, x_out[b], nullptr, &infos[b]);
+        if (st < 0) return fail(st, "batch instance " + std::to_string(b) + ": " + g_last_error);
+    }
+    bool any_max = false;
+    for (int b = 0; b < count; ++b) {
+        if (infos[b].status < 0) return fail((admm_status)infos[b].status, "batch instance " + std::to_string(b) + " failed");
+        any_max |= infos[b].status == ADMM_MAX_ITER;
+    }
+    return any_max ? ADMM_MAX_ITER : ADMM_OK;
 }
+
+// ------------------------------------------------------------------ serving
+//
+// A worker thread per context runs continuous batching over k_batch:
+//   1. admit queued requests while a slot and device memory are free
+//      (first-fit allocation inside one serving arena capped by the budget);
+//   2. pack the newly admitted ones and start them cold, or warm from the
+//      stored final state of the previous request with the same key,
+//      shifted one step (the receding-horizon re-solve of Alg. 2);
+//   3. run one window of at most `window` iterations for every resident
+//      instance (the kernel takes them longest-first);
+//   4. retire finished instances: copy x to the host, store the warm state,
+//      free the memory, publish the result for admm_poll.
+// A request's arithmetic is the batched kernel's, which does not depend on
+// the other residents, so a result is the same alone and in the mix.
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+
+namespace admm {
+
+class FreeList {
+  public:
+    void reset(size_t bytes) {
+        free_.clear();
+        if (bytes) free_[0] = bytes;
+        total_ = bytes;
+    }
+    // first fit, 256-byte granules; returns SIZE_MAX when nothing fits
+    size_t alloc(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                const size_t off = it->first, rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t total() const { return total_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t total_ = 0;
+};
+
+struct ServeReq {
+    uint64_t ticket = 0, key = 0;
+    admm_settings S;
+    int m = 0, n = 0, n_pad = 0;
+    std::vector<double> f2, f1, g2, g1, y, lo, hi, c;
+    size_t off = SIZE_MAX, bytes = 0;
+    // byte offsets (from the arena base) of the parts of the chunk
+    size_t coef_b = 0, x_b = 0, y_b = 0, w_b = 0, pool_b = 0;
+    BInst inst;
+    bool warm = false;
+    std::vector<double> x;
+    admm_info info;
+    std::chrono::steady_clock::time_point t_submit;
+};
+
+struct WarmEntry {
+    int m = 0, n = 0, n_pad = 0;
+    size_t off = SIZE_MAX, bytes = 0;   // x [m][n_pad] then w [n_pad], storage type
+    std::vector<double> lam, p;
+    uint64_t stamp = 0;
+};
+
+// Parameters of the warm-start kernel for one new instance.
+struct WarmSrc {
+    int32_t idx;                        // descriptor index of the new instance
+    int32_t n_old, n_pad_old, pad;
+    int64_t x_old, w_old;               // element offsets (storage type) in the arena
+    double lam[8], p[8];
+};
+
+// Warm start: x and w shifted one step from the stored state (steps past
+// the old horizon take the cold defaults), lambda and p from the previous
+// solve, z = g(x), h = min(c, sum_k g(x)).
+template <typename T, int MAXM>
+__global__ __launch_bounds__(kBlock) void k_serve_warm(BatchParams B, const WarmSrc *ws, int count) {
+    __shared__ double lds[MAXM + 2][kBlock];
+    __shared__ double s_sum[MAXM];
+    for (int q = blockIdx.x; q < count; q += gridDim.x) {
+        const WarmSrc W = ws[q];
+        BInst &I = B.inst[W.idx];
+        SolveParams P = inst_params<MAXM>(B, I);
+        inst_pointers<T>(B, I, P);
+        const T *xo = (const T *)B.x + W.x_old;
+        const T *wo = (const T *)B.x + W.w_old;
+        const int m = P.m, n = P.n;
+        double gs[MAXM];
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) gs[i] = 0.0;
+        for (int k = threadIdx.x; k < n; k += kBlock) {
+            const bool have = k + 1 < W.n_old;
+            double sx = 0.0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i < m) {
+                    const size_t e = (size_t)i * P.n_pad + k;
+                    const double x0 = have ? (double)xo[(size_t)i * W.n_pad_old + k + 1]
+                                           : st_round<T>(clampd(0.0, P.slo[i], P.shi[i]));
+                    const double xv = clampd(x0, P.slo[i], P.shi[i]);
+                    ((T *)P.x)[e] = (T)xv;
+                    const V4<T> cf = ((const V4<T> *)P.coef)[e];
+                    gs[i] += ((double)cf.c * xv + (double)cf.d) * xv;
+                    sx += xv;
+                }
+            }
+            const double wv = have ? (double)wo[k + 1] : fmax(0.0, sx - (double)((const T *)P.y)[k]);
+            ((T *)P.w)[k] = (T)wv;
+        }
+        block_sum_rows<MAXM>(m, gs, lds, s_sum);
+        if (threadIdx.x < m) {
+            const int i = threadIdx.x;
+            P.h[i] = fmin(P.cap[i], s_sum[i]);
+            P.lam[i] = W.lam[i];
+            P.zoff[i] = 0.0;
+            P.p[i] = W.p[i];
+        }
+        if (threadIdx.x == 0) {
+            I.t = 0;
+            I.r = INFINITY;
+            I.sigma = INFINITY;
+            I.status = I.max_iter > 0 ? -1 : 2;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+static void launch_serve_warm(int cls, const BatchParams &B, const WarmSrc *ws, int count, hipStream_t s) {
+    const int g = std::max(1, std::min(count, 2048));
+    if (cls == 0) k_serve_warm<T, 2><<<g, kBlock, 0, s>>>(B, ws, count);
+    else if (cls == 1) k_serve_warm<T, 4><<<g, kBlock, 0, s>>>(B, ws, count);
+    else k_serve_warm<T, 8><<<g, kBlock, 0, s>>>(B, ws, count);
+}
+
+constexpr int kServeMaxSlots = 16384;
+constexpr size_t kServeMaxQueue = 1u << 20;
+
+struct ServeState {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<ServeReq *> pending;
+    std::vector<ServeReq *> active;
+    std::unordered_map<uint64_t, ServeReq *> done;
+    std::unordered_map<uint64_t, int> issued;         // ticket -> 1 while outstanding
+    std::unordered_map<uint64_t, WarmEntry> warm;
+    std::thread worker;
+    bool stop = false;
+    bool failed = false;
+    std::string fail_msg;
+    uint64_t next_ticket = 1, stamp = 0;
+    int dtype = -1;
+    int window = 50;
+    DevBuf arena, inst, order, next, src, stage, wsrc;
+    FreeList fl;
+    hipStream_t s = nullptr;
+};
+
+static size_t serve_chunk_bytes(int m, int n_pad, size_t T, size_t *parts) {
+    auto r = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t coef = r((size_t)m * n_pad * 4 * T), x = r((size_t)m * n_pad * T), y = r(n_pad * T),
+                 w = r(n_pad * T), pool = r((size_t)kPoolPerSource * m * sizeof(double));
+    if (parts) {
+        parts[0] = 0;
+        parts[1] = coef;
+        parts[2] = coef + x;
+        parts[3] = coef + x + y;
+        parts[4] = coef + x + y + w;
+    }
+    return coef + x + y + w + pool;
+}
+
+static void serve_fail(ServeState *ss, const std::string &msg) {
+    std::lock_guard<std::mutex> lk(ss->mu);
+    ss->failed = true;
+    ss->fail_msg = msg;
+    ss->cv.notify_all();
+}
+
+static void evict_warm_lru(ServeState *ss) {
+    auto victim = ss->warm.end();
+    for (auto it = ss->warm.begin(); it != ss->warm.end(); ++it)
+        if (victim == ss->warm.end() || it->second.stamp < victim->second.stamp) victim = it;
+    if (victim != ss->warm.end()) {
+        ss->fl.release(victim->second.off, victim->second.bytes);
+        ss->warm.erase(victim);
+    }
+}
+
+// One cycle of the worker: admit, start, run a window, retire.
+static bool serve_cycle(admm_context *ctx, ServeState *ss) {
+    const int dtype = ss->dtype;
+    const size_t T = dtype == 0 ? 8 : 4;
+    std::vector<ServeReq *> fresh;
+    {
+        std::unique_lock<std::mutex> lk(ss->mu);
+        ss->cv.wait(lk, [&] { return ss->stop || !ss->pending.empty() || !ss->active.empty(); });
+        if (ss->stop) return false;
+        while (!ss->pending.empty() && (int)ss->active.size() < kServeMaxSlots) {
+            ServeReq *r = ss->pending.front();
+            size_t off = ss->fl.alloc(r->bytes);
+            while (off == SIZE_MAX && !ss->warm.empty()) {
+                evict_warm_lru(ss);
+                off = ss->fl.alloc(r->bytes);
+            }
+            if (off == SIZE_MAX) break;                 // wait for memory to free up
+            ss->pending.pop_front();
+            r->off = off;
+            ss->active.push_back(r);
+            fresh.push_back(r);
+        }
+    }
+    hipStream_t s = ss->s;
+    char *base = (char *)ss->arena.p;
+    // descriptors of every resident instance
+    const int na = (int)ss->active.size();
+    std::vector<BInst> insts(na);
+    for (int a = 0; a < na; ++a) {
+        ServeReq *r = ss->active[a];
+        size_t parts[5];
+        serve_chunk_bytes(r->m, r->n_pad, T, parts);
+        r->coef_b = r->off + parts[0];
+        r->x_b = r->off + parts[1];
+        r->y_b = r->off + parts[2];
+        r->w_b = r->off + parts[3];
+        r->pool_b = r->off + parts[4];
+        BInst &I = r->inst;
+        I.coef_off = (int64_t)(r->coef_b / (4 * T));
+        I.x_off = (int64_t)(r->x_b / T);
+        I.col_off = (int64_t)(r->y_b / T);
+        I.w_off = (int64_t)(r->w_b / T);
+        I.pool_off = (int64_t)(r->pool_b / sizeof(double));
+        insts[a] = I;
+    }
+    if (ss->arena.bytes == 0) return true;
+    auto dev_ok = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess) serve_fail(ss, std::string(what) + ": " + hipGetErrorString(e));
+        return e == hipSuccess;
+    };
+    Arena &A = ctx->arena;
+    if (A.ensure(ss->inst, std::max<size_t>(1, na) * sizeof(BInst)) != ADMM_OK ||
+        A.ensure(ss->order, 3 * std::max<size_t>(1, na) * sizeof(int32_t)) != ADMM_OK ||
+        A.ensure(ss->next, 4 * sizeof(int32_t)) != ADMM_OK) {
+        serve_fail(ss, "serving descriptors do not fit the budget");
+        return false;
+    }
+    if (!dev_ok(hipMemcpyAsync(ss->inst.p, insts.data(), na * sizeof(BInst), hipMemcpyHostToDevice, s), "upload"))
+        return false;
+    BatchParams B;
+    B.inst = (BInst *)ss->inst.p;
+    B.order = nullptr;
+    B.count = na;
+    B.window = ss->window;
+    B.next = (int32_t *)ss->next.p;
+    B.coef = base;
+    B.x = base;
+    B.y = base;
+    B.w = base;
+    B.pool = (double *)base;
+    // start the newly admitted instances
+    if (!fresh.empty()) {
+        const int nf = (int)fresh.size();
+        size_t SRC = 0;
+        for (ServeReq *r : fresh) SRC += 4 * (size_t)r->m * r->n + r->n + 2 * (size_t)r->m;
+        if (A.ensure(ss->stage, SRC * sizeof(double)) != ADMM_OK ||
+            A.ensure(ss->src, nf * (sizeof(PackSrc) + sizeof(BInst) + sizeof(int32_t)) + 256) != ADMM_OK ||
+            A.ensure(ss->wsrc, std::max(1, nf) * sizeof(WarmSrc)) != ADMM_OK) {
+            serve_fail(ss, "serving staging does not fit the budget");
+            return false;
+        }
+        std::vector<double> img(SRC);
+        std::vector<PackSrc> src(nf);
+        std::vector<BInst> fi(nf);
+        std::vector<int32_t> cold_idx[3];
+        std::vector<WarmSrc> warm_src[3];
+        size_t o = 0;
+        double *sb = (double *)ss->stage.p;
+        for (int f = 0; f < nf; ++f) {
+            ServeReq *r = fresh[f];
+            auto put = [&](const std::vector<double> &v) -> const void * {
+                std::memcpy(img.data() + o, v.data(), v.size() * sizeof(double));
+                const void *d = sb + o;
+                o += v.size();
+                return d;
+            };
+            src[f] = {put(r->f2), put(r->f1), put(r->g2), put(r->g1), put(r->y), put(r->lo), put(r->hi)};
+            fi[f] = r->inst;
+            const int a = (int)(std::find(ss->active.begin(), ss->active.end(), r) - ss->active.begin());
+            const int cls = batch_class(r->m);
+            auto wit = r->key ? ss->warm.find(r->key) : ss->warm.end();
+            if (wit != ss->warm.end() && wit->second.m == r->m) {
+                WarmEntry &we = wit->second;
+                WarmSrc w;
+                std::memset(&w, 0, sizeof w);
+                w.idx = a;
+                w.n_old = we.n;
+                w.n_pad_old = we.n_pad;
+                w.x_old = (int64_t)(we.off / T);
+                w.w_old = (int64_t)((we.off + (size_t)we.m * we.n_pad * T) / T);
+                for (int i = 0; i < r->m; ++i) { w.lam[i] = we.lam[i]; w.p[i] = we.p[i]; }
+                warm_src[cls].push_back(w);
+                r->warm = true;
+            } else {
+                cold_idx[cls].push_back(a);
+            }
+        }
+        // capacities into the pools, then pack
+        for (ServeReq *r : fresh) {
+            if (!dev_ok(hipMemcpyAsync(base + r->pool_b + 6 * r->m * sizeof(double), r->c.data(),
+                                       r->m * sizeof(double), hipMemcpyHostToDevice, s), "upload"))
+                return false;
+        }
+        char *sp = (char *)ss->src.p;
+        PackSrc *d_src = (PackSrc *)sp;
+        BInst *d_fi = (BInst *)(sp + nf * sizeof(PackSrc));
+        if (!dev_ok(hipMemcpyAsync(sb, img.data(), SRC * sizeof(double), hipMemcpyHostToDevice, s), "upload") ||
+            !dev_ok(hipMemcpyAsync(d_src, src.data(), nf * sizeof(PackSrc), hipMemcpyHostToDevice, s), "upload") ||
+            !dev_ok(hipMemcpyAsync(d_fi, fi.data(), nf * sizeof(BInst), hipMemcpyHostToDevice, s), "upload"))
+            return false;
+        BatchParams Bf = B;
+        Bf.inst = d_fi;
+        Bf.count = nf;
+        int32_t *d_bad = (int32_t *)(sp + nf * (sizeof(PackSrc) + sizeof(BInst)));
+        (void)hipMemsetAsync(d_bad, 0, nf * sizeof(int32_t), s);
+        const int pg = std::min(nf, 2048);
+        if (dtype == 0) k_batch_pack<double, double><<<pg, kBlock, 0, s>>>(Bf, d_src, d_bad);
+        else k_batch_pack<float, double><<<pg, kBlock, 0, s>>>(Bf, d_src, d_bad);
+        if (!dev_ok(hipGetLastError(), "pack")) return false;
+        // cold and warm starts per class (descriptors of all residents)
+        for (int c = 0; c < 3; ++c) {
+            if (!cold_idx[c].empty()) {
+                if (!dev_ok(hipMemcpyAsync(ss->order.p, cold_idx[c].data(), cold_idx[c].size() * sizeof(int32_t),
+                                           hipMemcpyHostToDevice, s), "upload"))
+                    return false;
+                BatchParams Bc = B;
+                Bc.order = (const int32_t *)ss->order.p;
+                Bc.count = (int)cold_idx[c].size();
+                const int g = std::min(Bc.count, 2048);
+                if (dtype == 0) {
+                    if (c == 0) k_batch_init<double, 2><<<g, kBlock, 0, s>>>(Bc);
+                    else if (c == 1) k_batch_init<double, 4><<<g, kBlock, 0, s>>>(Bc);
+                    else k_batch_init<double, 8><<<g, kBlock, 0, s>>>(Bc);
+                } else {
+                    if (c == 0) k_batch_init<float, 2><<<g, kBlock, 0, s>>>(Bc);
+                    else if (c == 1) k_batch_init<float, 4><<<g, kBlock, 0, s>>>(Bc);
+                    else k_batch_init<float, 8><<<g, kBlock, 0, s>>>(Bc);
+                }
+                if (!dev_ok(hipStreamSynchronize(s), "init")) return false;
+            }
+            if (!warm_src[c].empty()) {
+                if (!dev_ok(hipMemcpyAsync(ss->wsrc.p, warm_src[c].data(), warm_src[c].size() * sizeof(WarmSrc),
+                                           hipMemcpyHostToDevice, s), "upload"))
+                    return false;
+                if (dtype == 0) launch_serve_warm<double>(c, B, (const WarmSrc *)ss->wsrc.p, (int)warm_src[c].size(), s);
+                else launch_serve_warm<float>(c, B, (const WarmSrc *)ss->wsrc.p, (int)warm_src[c].size(), s);
+                if (!dev_ok(hipStreamSynchronize(s), "warm init")) return false;
+            }
+        }
+        std::vector<int32_t> bad(nf);
+        if (!dev_ok(hipMemcpyAsync(bad.data(), d_bad, nf * sizeof(int32_t), hipMemcpyDeviceToHost, s), "readback") ||
+            !dev_ok(hipStreamSynchronize(s), "pack"))
+            return false;
+        for (int f = 0; f < nf; ++f)
+            if (bad[f]) {
+                const int a = (int)(std::find(ss->active.begin(), ss->active.end(), fresh[f]) - ss->active.begin());
+                insts[a].status = -1000;   // invalid input: retired below without running
+            }
+    }
+    // one window for every resident instance, per class, longest first
+    std::vector<int32_t> order[3];
+    {
+        std::vector<BInst> cur(na);
+        if (!dev_ok(hipMemcpyAsync(cur.data(), ss->inst.p, na * sizeof(BInst), hipMemcpyDeviceToHost, s), "readback") ||
+            !dev_ok(hipStreamSynchronize(s), "readback"))
+            return false;
+        for (int a = 0; a < na; ++a) {
+            if (insts[a].status == -1000) cur[a].status = -1000;
+            insts[a] = cur[a];
+            if (cur[a].status == -1) order[batch_class(cur[a].m)].push_back(a);
+        }
+    }
+    for (auto &o : order)
+        std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
+            return (double)insts[a].m * insts[a].n > (double)insts[b].m * insts[b].n;
+        });
+    std::vector<int32_t> ord_all(3 * (size_t)std::max(1, na), 0);
+    for (int c = 0; c < 3; ++c) std::copy(order[c].begin(), order[c].end(), ord_all.begin() + (size_t)c * na);
+    if (!dev_ok(hipMemcpyAsync(ss->order.p, ord_all.data(), ord_all.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload") ||
+        !dev_ok(hipMemsetAsync(ss->next.p, 0, 4 * sizeof(int32_t), s), "memset"))
+        return false;
+    for (int c = 0; c < 3; ++c) {
+        if (order[c].empty()) continue;
+        BatchParams Bc = B;
+        Bc.order = (const int32_t *)ss->order.p + (size_t)c * na;
+        Bc.count = (int)order[c].size();
+        Bc.next = (int32_t *)ss->next.p + c;
+        if (!dev_ok(launch_batch(ctx, dtype, c, Bc, false, s), "window")) return false;
+    }
+    std::vector<BInst> after(na);
+    if (!dev_ok(hipMemcpyAsync(after.data(), ss->inst.p, na * sizeof(BInst), hipMemcpyDeviceToHost, s), "readback") ||
+        !dev_ok(hipStreamSynchronize(s), "window"))
+        return false;
+    // retire finished instances
+    std::vector<ServeReq *> still;
+    std::vector<ServeReq *> finished;
+    for (int a = 0; a < na; ++a) {
+        ServeReq *r = ss->active[a];
+        r->inst = after[a];
+        if (insts[a].status == -1000) r->inst.status = -1000;
+        (r->inst.status == -1 ? still : finished).push_back(r);
+    }
+    for (ServeReq *r : finished) {
+        admm_info &inf = r->info;
+        std::memset(&inf, 0, sizeof inf);
+        const BInst &I = r->inst;
+        if (I.status == -1000) {
+            inf.status = ADMM_E_INVALID_ARG;
+        } else {
+            inf.status = I.status == 0 ? ADMM_OK : (I.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
+            inf.iters = I.t;
+            inf.r = I.r;
+            inf.sigma = I.sigma;
+            inf.objective = I.objective;
+            std::vector<char> xb((size_t)r->m * r->n_pad * T);
+            if (!dev_ok(hipMemcpyAsync(xb.data(), base + r->x_b, xb.size(), hipMemcpyDeviceToHost, s), "readback"))
+                return false;
+            std::vector<double> pool((size_t)kPoolPerSource * r->m);
+            if (!dev_ok(hipMemcpyAsync(pool.data(), base + r->pool_b, pool.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, s), "readback") ||
+                !dev_ok(hipStreamSynchronize(s), "readback"))
+                return false;
+            r->x.resize((size_t)r->m * r->n);
+            for (int i = 0; i < r->m; ++i)
+                for (int k = 0; k < r->n; ++k) {
+                    const size_t e = (size_t)i * r->n_pad + k;
+                    r->x[(size_t)i * r->n + k] = T == 8 ? ((double *)xb.data())[e] : (double)((float *)xb.data())[e];
+                }
+            // warm store: x and w of this final iterate, lambda and p
+            if (r->key) {
+                std::lock_guard<std::mutex> lk(ss->mu);
+                auto it = ss->warm.find(r->key);
+                if (it != ss->warm.end()) {
+                    ss->fl.release(it->second.off, it->second.bytes);
+                    ss->warm.erase(it);
+                }
+                WarmEntry we;
+                we.m = r->m;
+                we.n = r->n;
+                we.n_pad = r->n_pad;
+                we.bytes = ((size_t)r->m * r->n_pad + r->n_pad) * T;
+                we.off = ss->fl.alloc(we.bytes);
+                if (we.off != SIZE_MAX) {
+                    (void)hipMemcpyAsync(base + we.off, base + r->x_b, (size_t)r->m * r->n_pad * T,
+                                         hipMemcpyDeviceToDevice, s);
+                    (void)hipMemcpyAsync(base + we.off + (size_t)r->m * r->n_pad * T, base + r->w_b, r->n_pad * T,
+                                         hipMemcpyDeviceToDevice, s);
+                    we.lam.assign(pool.begin(), pool.begin() + r->m);
+                    we.p.assign(pool.begin() + 3 * r->m, pool.begin() + 4 * r->m);
+                    we.stamp = ++ss->stamp;
+                    ss->warm[r->key] = we;
+                }
+            }
+        }
+        inf.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r->t_submit).count();
+    }
+    if (!dev_ok(hipStreamSynchronize(s), "warm store")) return false;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        for (ServeReq *r : finished) {
+            ss->fl.release(r->off, r->bytes);
+            r->off = SIZE_MAX;
+            r->f2.clear(); r->f1.clear(); r->g2.clear(); r->g1.clear(); r->y.clear();
+            ss->done[r->ticket] = r;
+        }
+        ss->active = still;
+        ss->cv.notify_all();
+    }
+    return true;
+}
+
+static void serve_main(admm_context *ctx, ServeState *ss) {
+    (void)hipSetDevice(ctx->device);
+    while (serve_cycle(ctx, ss)) {
+    }
+}
+
+void serve_shutdown(admm_context *ctx) {
+    ServeState *ss = ctx->serve;
+    if (!ss) return;
+    {
+        std::lock_guard<std::mutex> lk(ss->mu);
+        ss->stop = true;
+        ss->cv.notify_all();
+    }
+    if (ss->worker.joinable()) ss->worker.join();
+    for (ServeReq *r : ss->pending) delete r;
+    for (ServeReq *r : ss->active) delete r;
+    for (auto &kv : ss->done) delete kv.second;
+    DeviceGuard g(ctx->device);
+    for (DevBuf *b : {&ss->arena, &ss->inst, &ss->order, &ss->next, &ss->src, &ss->stage, &ss->wsrc})
+        ctx->arena.release(*b);
+    if (ss->s) (void)hipStreamDestroy(ss->s);
+    delete ss;
+    ctx->serve = nullptr;
+}
+
+// Serving arena: what the budget leaves after the other workspaces, capped.
+static admm_status serve_start(admm_context *ctx, int dtype) {
+    if (ctx->serve) return ADMM_OK;
+    ServeState *ss = new ServeState();
+    ss->dtype = dtype;
+    if (const char *e = std::getenv("ADMM_SERVE_WINDOW")) ss->window = std::max(1, std::atoi(e));
+    DeviceGuard g(ctx->device);
+    if (hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) != hipSuccess) {
+        delete ss;
+        return fail(ADMM_E_DEVICE, "stream creation failed");
+    }
+    const size_t left = ctx->arena.budget > ctx->arena.used ? ctx->arena.budget - ctx->arena.used : 0;
+    // at most three quarters of the budget, so plain and batched solves on
+    // the same context keep room for their workspaces
+    size_t bytes = std::min(left, ctx->arena.budget / 4 * 3);
+    bytes = std::min(bytes, (size_t)16 << 30) & ~size_t(255);
+    admm_status st = ctx->arena.ensure(ss->arena, bytes);
+    if (st != ADMM_OK) {
+        (void)hipStreamDestroy(ss->s);
+        delete ss;
+        return st;
+    }
+    ss->fl.reset(bytes);
+    ctx->serve = ss;
+    ss->worker = std::thread(serve_main, ctx, ss);
+    return ADMM_OK;
+}
+
+}  // namespace admm
 
 extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, const admm_settings *settings,
                                    uint64_t warm_key, uint64_t *ticket) {
-    (void)ctx; (void)prob; (void)settings; (void)warm_key; (void)ticket;
-    return fail(ADMM_E_UNSUPPORTED, "admm_submit: not built yet");
+    if (!ctx || !ticket) return fail(ADMM_E_INVALID_ARG, "context and ticket are required");
+    const admm_settings S = settings ? *settings : ctx->defaults;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    if ((st = validate_problem_shape(prob)) != ADMM_OK) return st;
+    if (prob->mem != ADMM_HOST) return fail(ADMM_E_UNSUPPORTED, "admm_submit takes host arrays");
+    if (!batchable(*prob))
+        return fail(ADMM_E_UNSUPPORTED, "admm_submit serves q = 1 instances with per-source bounds and no g0/f0");
+    const int dtype = S.precision == ADMM_F64 ? 0 : 1;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if ((st = serve_start(ctx, dtype)) != ADMM_OK) return st;
+    }
+    ServeState *ss = ctx->serve;
+    if (ss->dtype != dtype) return fail(ADMM_E_INVALID_ARG, "one precision per serving context");
+    const size_t T = dtype == 0 ? 8 : 4;
+    ServeReq *r = new ServeReq();
+    r->t_submit = std::chrono::steady_clock::now();
+    r->S = S;
+    r->key = warm_key;
+    r->m = prob->m;
+    r->n = prob->n;
+    r->n_pad = (prob->n + kPad - 1) / kPad * kPad;
+    r->bytes = serve_chunk_bytes(r->m, r->n_pad, T, nullptr);
+    if (r->bytes > ss->fl.total()) {
+        delete r;
+        return fail(ADMM_E_OUT_OF_BUDGET, "instance larger than the serving arena");
+    }
+    const size_t E = (size_t)r->m * r->n;
+    auto cp = [](const void *p, size_t n) {
+        const double *d = (const double *)p;
+        return std::vector<double>(d, d + n);
+    };
+    r->f2 = cp(prob->f2, E);
+    r->f1 = cp(prob->f1, E);
+    r->g2 = cp(prob->g2, E);
+    r->g1 = cp(prob->g1, E);
+    r->y = cp(prob->y, r->n);
+    r->lo = cp(prob->x_lo, r->m);
+    r->hi = cp(prob->x_hi, r->m);
+    r->c = cp(prob->c, r->m);
+    BInst &I = r->inst;
+    std::memset(&I, 0, sizeof I);
+    I.m = r->m;
+    I.n = r->n;
+    I.n_pad = r->n_pad;
+    I.status = -1;
+    I.max_iter = S.max_iter;
+    I.check_every = S.check_every;
+    I.flags = (S.xstep == ADMM_XSTEP_PAPER_PROJECT ? 1 : 0) | (S.sweep == ADMM_SWEEP_JACOBI ? 2 : 0);
+    for (int k = 0; k < 4; ++k) I.rho[k] = S.rho[k];
+    if (S.rho2_per_step) I.rho[1] = S.rho[1] / (double)r->n;
+    I.eps_p = S.eps_primal;
+    I.eps_d = S.eps_dual;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    if (ss->failed) {
+        delete r;
+        return fail(ADMM_E_DEVICE, "serving worker stopped: " + ss->fail_msg);
+    }
+    if (ss->pending.size() >= kServeMaxQueue) {
+        delete r;
+        return fail(ADMM_E_QUEUE_FULL, "serving queue full");
+    }
+    r->ticket = ss->next_ticket++;
+    ss->issued[r->ticket] = 1;
+    ss->pending.push_back(r);
+    ss->cv.notify_all();
+    *ticket = r->ticket;
+    return ADMM_OK;
 }
 
 extern "C" admm_status admm_poll(admm_context *ctx, uint64_t ticket, double *x_out, admm_info *info) {
-    (void)ctx; (void)ticket; (void)x_out; (void)info;
-    return fail(ADMM_E_UNSUPPORTED, "admm_poll: not built yet");
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    ServeState *ss = ctx->serve;
+    if (!ss) return fail(ADMM_E_UNKNOWN_TICKET, "unknown ticket");
+    std::unique_lock<std::mutex> lk(ss->mu);
+    if (!ss->issued.count(ticket)) return fail(ADMM_E_UNKNOWN_TICKET, "unknown ticket");
+    auto it = ss->done.find(ticket);
+    if (it == ss->done.end()) {
+        if (ss->failed) return fail(ADMM_E_DEVICE, "serving worker stopped: " + ss->fail_msg);
+        return ADMM_NOT_READY;
+    }
+    ServeReq *r = it->second;
+    ss->done.erase(it);
+    ss->issued.erase(ticket);
+    lk.unlock();
+    if (x_out && !r->x.empty()) std::memcpy(x_out, r->x.data(), r->x.size() * sizeof(double));
+    if (info) *info = r->info;
+    const admm_status st = (admm_status)r->info.status;
+    delete r;
+    if (st < 0) return fail(st, "request failed");
+    return st;
 }
 
 extern "C" admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key) {
-    (void)ctx; (void)warm_key;
-    return fail(ADMM_E_UNSUPPORTED, "admm_release_warm: not built yet");
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    ServeState *ss = ctx->serve;
+    if (!ss) return ADMM_OK;
+    std::lock_guard<std::mutex> lk(ss->mu);
+    auto it = ss->warm.find(warm_key);
+    if (it != ss->warm.end()) {
+        ss->fl.release(it->second.off, it->second.bytes);
+        ss->warm.erase(it);
+    }
+    return ADMM_OK;
 }

@@ -1,0 +1,396 @@
+// Device building blocks shared by the plain (graph and persistent) and the
+// batched kernels: the per-column x/s/mu update, block reductions and the
+// scalar steps of one iteration.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "admm_internal.hpp"
+#include "admm_quartic.hpp"
+
+namespace admm {
+
+template <typename T> struct alignas(4 * sizeof(T)) V4 { T a, b, c, d; };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// Reductions over aligned groups of G lanes (G a power of two <= 64).
+__device__ __forceinline__ double group_sum(double v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double group_max(double v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double group_min(double v, int G) {
+    for (int o = G >> 1; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double st_round(double v) { return (double)(T)v; }
+
+// ---------------------------------------------------------------- sweep
+
+// x-step quartic coefficients (7a) in the theta/phi form:
+//   A = rho1 g2^2 / 2, B = rho1 g2 g1,
+//   C = f2/q + rho1 (g1^2/2 - g2 (theta - g0)) + rho3/2 [+ rho4/2 at k = 1],
+//   D = f1/q - rho1 g1 (theta - g0) - rho3 phi [- rho4 (x_1 + nu) at k = 1].
+template <bool MIXED>
+__device__ __forceinline__ double xstep(const SolveParams &P, double f2, double f1, double g2, double g1,
+                                        double tg, double phi, bool first_step, double cons,
+                                        double lo, double hi, int &code) {
+    const double A = 0.5 * P.rho1 * g2 * g2;
+    const double B = P.rho1 * g2 * g1;
+    double C = f2 * P.inv_q + P.rho1 * (0.5 * g1 * g1 - g2 * tg) + 0.5 * P.rho3;
+    double D = f1 * P.inv_q - P.rho1 * g1 * tg - P.rho3 * phi;
+    if (first_step) {
+        C += 0.5 * P.rho4;
+        D -= P.rho4 * cons;
+    }
+    if (MIXED) return qmin_mixed(A, B, C, D, lo, hi, P.xstep_project, code);
+    return qmin_f64(A, B, C, D, lo, hi, P.xstep_project, code);
+}
+
+// The data of one column (j, k): coefficients and x of every source, y, w.
+template <typename T, int MAXM>
+struct Col {
+    V4<T> cf[MAXM];
+    T x[MAXM];
+    T y, w;
+};
+
+template <typename T>
+__device__ __forceinline__ void opaque1(T &v) {
+    asm volatile("" : "+v"(v));
+}
+
+template <typename T, int MAXM>
+__device__ __forceinline__ void opaque(Col<T, MAXM> &d) {
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        opaque1(d.cf[i].a);
+        opaque1(d.cf[i].b);
+        opaque1(d.cf[i].c);
+        opaque1(d.cf[i].d);
+        opaque1(d.x[i]);
+    }
+    opaque1(d.y);
+    opaque1(d.w);
+}
+
+template <typename T, int MAXM>
+__device__ __forceinline__ void col_load(const SolveParams &P, int j, int k, Col<T, MAXM> &d) {
+    const V4<T> *coef = (const V4<T> *)P.coef;
+    const T *X = (const T *)P.x;
+    const size_t col = (size_t)j * P.n_pad + k;
+    d.y = ((const T *)P.y)[col];
+    d.w = ((const T *)P.w)[col];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        if (i < P.m) {
+            const size_t e = ((size_t)j * P.m + i) * P.n_pad + k;
+            d.cf[i] = coef[e];
+            d.x[i] = X[e];
+        }
+    }
+}
+
+template <typename T, int MAXM>
+__device__ __forceinline__ void col_store(const SolveParams &P, int j, int k, const Col<T, MAXM> &d) {
+    T *X = (T *)P.x;
+    ((T *)P.w)[(size_t)j * P.n_pad + k] = d.w;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+        if (i < P.m) X[((size_t)j * P.m + i) * P.n_pad + k] = d.x[i];
+}
+
+// Per-(i, j) scalars the sweep needs: theta_k = g(x_k) + toff, and the
+// consensus target x_1 + nu at k = 1.
+template <int MAXM>
+struct Scal {
+    double toff[MAXM], cons[MAXM];
+};
+
+template <int MAXM, bool COHERENT>
+__device__ __forceinline__ double ld_scalar(const double *p) {
+    if (COHERENT) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *p;
+}
+
+template <int MAXM, bool COHERENT>
+__device__ __forceinline__ void scal_load(const SolveParams &P, int j, Scal<MAXM> &sc) {
+    // branch-free: indices past m are clamped to a valid pair and zeroed
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        const int ii = i < P.m ? i : P.m - 1;
+        const int pi = j * P.m + ii;
+        const double t = ld_scalar<MAXM, COHERENT>(P.zoff + pi) + ld_scalar<MAXM, COHERENT>(P.lam + pi);
+        const double c = ld_scalar<MAXM, COHERENT>(P.xbar1 + ii) + ld_scalar<MAXM, COHERENT>(P.nu + pi);
+        sc.toff[i] = i < P.m ? t : 0.0;
+        sc.cons[i] = (i < P.m && P.consensus) ? c : 0.0;
+    }
+}
+
+// Block-level accumulators of one tile.
+template <int MAXM>
+struct Acc {
+    double gsum[MAXM], dgmax[MAXM], dgmin[MAXM];
+    double rdem, sig3;
+    __device__ __forceinline__ void reset() {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) { gsum[i] = 0.0; dgmax[i] = -DBL_MAX; dgmin[i] = DBL_MAX; }
+        rdem = 0.0;
+        sig3 = 0.0;
+    }
+};
+
+// One column: the x-step (7a) for every source in turn (Gauss-Seidel, or
+// Jacobi by flag), then the s- and mu-steps (7e)-(7f) through w = s - mu,
+// accumulating sum_k g(x_k) per source and the residual trackers.
+template <typename T, int MAXM, bool MIXED, bool CHECK>
+__device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, Col<T, MAXM> &d,
+                                           const Scal<MAXM> &sc, Acc<MAXM> &acc) {
+    const int m = P.m;
+    const double y = (double)d.y;
+    const double w = (double)d.w;
+    const double s_old = fmax(w, 0.0), mu_old = fmax(-w, 0.0);
+    const double sm = s_old + mu_old;
+    const T *G0 = (const T *)P.g0;
+    double xo[MAXM], xc[MAXM];
+    double sum_old = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        xo[i] = (i < m) ? (double)d.x[i] : 0.0;
+        xc[i] = xo[i];
+        sum_old += xo[i];
+    }
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        if (i < m) {
+            const double f2 = d.cf[i].a, f1 = d.cf[i].b, g2 = d.cf[i].c, g1 = d.cf[i].d;
+            const size_t e = ((size_t)j * m + i) * P.n_pad + k;
+            const double g0 = G0 ? (double)G0[e] : 0.0;
+            double lo, hi;
+            if (P.blo) {
+                lo = (double)((const T *)P.blo)[(size_t)i * P.n_pad + k];
+                hi = (double)((const T *)P.bhi)[(size_t)i * P.n_pad + k];
+            } else {
+                lo = P.slo[i];
+                hi = P.shi[i];
+            }
+            const double g_old = (g2 * xo[i] + g1) * xo[i] + g0;
+            const double theta = g_old + sc.toff[i];
+            double others = 0.0;
+#pragma unroll
+            for (int l = 0; l < MAXM; ++l)
+                if (l < m && l != i) others += P.jacobi ? xo[l] : xc[l];
+            const double phi = sm - others + y;
+            int code;
+            const double xn = st_round<T>(xstep<MIXED>(P, f2, f1, g2, g1, theta - g0, phi,
+                                                       P.consensus && k == 0, sc.cons[i], lo, hi, code));
+            xc[i] = xn;
+            d.x[i] = (T)xn;
+            if (P.want_codes) P.codes[e] = (uint8_t)code;
+            if (k == 0) P.x1[j * m + i] = xn;
+            const double g_new = (g2 * xn + g1) * xn + g0;
+            acc.gsum[i] += g_new;
+            if (CHECK) {
+                const double dg = g_new - g_old;
+                acc.dgmax[i] = fmax(acc.dgmax[i], dg);
+                acc.dgmin[i] = fmin(acc.dgmin[i], dg);
+            }
+        }
+    }
+    double sum_new = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) sum_new += (i < m) ? xc[i] : 0.0;
+    const double wn = st_round<T>(sum_new - y - mu_old);
+    d.w = (T)wn;
+    if (CHECK) {
+        const double s_new = fmax(wn, 0.0);
+        acc.rdem = fmax(acc.rdem, fabs(s_new - sum_new + y));
+        acc.sig3 = fmax(acc.sig3, fabs((s_new - s_old) - (sum_new - sum_old)));
+    }
+}
+
+// Block reduction of one tile's accumulators into the partials: transposed
+// through LDS so that each wave reduces whole rows (one source each).
+template <int MAXM>
+__device__ __forceinline__ void block_partials(const SolveParams &P, size_t tile, const Acc<MAXM> &acc,
+                                               bool check, double (*lds)[kBlock]) {
+    const int m = P.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t slab = (size_t)P.q * P.nblk * m;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+        if (i < m) lds[i][tid] = acc.gsum[i];
+    __syncthreads();
+    for (int i = wv; i < m; i += kWaves) {
+        double v = (lds[i][lane] + lds[i][lane + 64]) + (lds[i][lane + 128] + lds[i][lane + 192]);
+        v = wave_sum(v);
+        if (lane == 0) P.part[tile * m + i] = v;
+    }
+    if (check) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+            if (i < m) lds[i][tid] = acc.dgmax[i];
+        lds[MAXM][tid] = acc.rdem;
+        lds[MAXM + 1][tid] = acc.sig3;
+        __syncthreads();
+        for (int r = wv; r < m + 2; r += kWaves) {
+            const int row = r < m ? r : MAXM + (r - m);
+            double v = fmax(fmax(lds[row][lane], lds[row][lane + 64]),
+                            fmax(lds[row][lane + 128], lds[row][lane + 192]));
+            v = wave_max(v);
+            if (lane == 0) {
+                if (r < m) P.part[slab + tile * m + r] = v;
+                else P.part[3 * slab + tile * 2 + (r - m)] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+            if (i < m) lds[i][tid] = acc.dgmin[i];
+        __syncthreads();
+        for (int i = wv; i < m; i += kWaves) {
+            double v = fmin(fmin(lds[i][lane], lds[i][lane + 64]), fmin(lds[i][lane + 128], lds[i][lane + 192]));
+            v = wave_min(v);
+            if (lane == 0) P.part[2 * slab + tile * m + i] = v;
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- finalize
+
+__device__ __forceinline__ double block_max(double v, double *lds) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    v = wave_max(v);
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double r = lds[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) r = fmax(r, lds[w]);
+    return r;
+}
+
+// The scalar steps of one iteration, run by one block of kBlock threads
+// after every tile's partials are written: (7b)+(7g) through kappa, (7d),
+// (7i), the consensus (7c)+(7h), the residuals on check iterations and the
+// stop flag.  Sums over tiles run in a fixed order.
+__device__ inline void finalize_body(const SolveParams &P) {
+    Ctrl *ctrl = P.ctrl;
+    const int t1 = ctrl->t + 1;
+    const bool check = (t1 % P.check_every) == 0;
+    const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group;
+    const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = kBlock / G;
+    const size_t slab = (size_t)q * nblk * m;
+    const double *pg = P.part, *pmax = P.part + slab, *pmin = P.part + 2 * slab;
+    const double *pr = P.part + 3 * slab;
+    const double nd = (double)P.n;
+    const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+
+    for (int base = 0; base < M; base += ngroups) {
+        const int pi = base + gid;
+        const bool active = pi < M;
+        const int j = active ? pi / m : 0, i = active ? pi % m : 0;
+        double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
+        if (active) {
+            for (int bb = gl; bb < nblk; bb += G) {
+                const size_t idx = ((size_t)j * nblk + bb) * m + i;
+                s += pg[idx];
+                if (check) { mx = fmax(mx, pmax[idx]); mn = fmin(mn, pmin[idx]); }
+            }
+        }
+        s = group_sum(s, G);
+        if (check) { mx = group_max(mx, G); mn = group_min(mn, G); }
+        if (active && gl == 0) {
+            const double lam_old = P.lam[pi], zoff_old = P.zoff[pi];
+            const double h_old = P.h[pi], p_old = P.p[pi];
+            const double W = s - nd * lam_old;              // 1'(g(x) - lambda)
+            const double kap = kfac * (h_old + p_old - W);
+            const double sumz = W + nd * kap;               // 1'z
+            const double zoff_new = kap - lam_old;          // z - g(x)
+            const double hn = fmin(P.cap[i], sumz - p_old);
+            const double pn = p_old + hn - sumz;
+            P.lam[pi] = kap;
+            P.zoff[pi] = zoff_new;
+            P.h[pi] = hn;
+            P.p[pi] = pn;
+            if (check) {
+                const double cz = zoff_new - zoff_old;
+                P.pair_r[pi] = fmax(fabs(zoff_new), fabs(hn - sumz));
+                P.pair_s[pi] = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)),
+                                    P.rho2 * fabs(hn - h_old));
+            }
+        }
+    }
+    __syncthreads();
+
+    if (P.consensus) {
+        int G2 = 64;
+        while (G2 > 1 && m * G2 > kBlock) G2 >>= 1;
+        const int g2l = tid & (G2 - 1), g2id = tid / G2;
+        for (int base = 0; base < m; base += kBlock / G2) {
+            const int i = base + g2id;
+            double s = 0.0;
+            if (i < m)
+                for (int jj = g2l; jj < q; jj += G2) s += P.x1[jj * m + i] - P.nu[jj * m + i];
+            s = group_sum(s, G2);
+            if (i < m && g2l == 0) P.xbar1[i] = s * P.inv_q;
+        }
+        __syncthreads();
+        for (int pi = tid; pi < M; pi += kBlock) {
+            const double res = P.xbar1[pi % m] - P.x1[pi];
+            P.nu[pi] += res;
+            if (check) P.pair_r[pi] = fmax(P.pair_r[pi], fabs(res));
+        }
+        __syncthreads();
+    }
+
+    __shared__ double lds[kWaves];
+    if (check) {
+        double r = 0.0, sg = 0.0;
+        for (int pi = tid; pi < M; pi += kBlock) {
+            r = fmax(r, P.pair_r[pi]);
+            sg = fmax(sg, P.pair_s[pi]);
+        }
+        for (int bb = tid; bb < q * nblk; bb += kBlock) {
+            r = fmax(r, pr[2 * bb]);
+            sg = fmax(sg, P.rho3 * pr[2 * bb + 1]);
+        }
+        r = block_max(r, lds);
+        sg = block_max(sg, lds);
+        if (tid == 0) {
+            ctrl->r = r;
+            ctrl->sigma = sg;
+            if (!(r == r) || !(sg == sg)) { ctrl->status = -4; ctrl->done = 1; }
+            else if (r < P.eps_p && sg < P.eps_d) { ctrl->status = 0; ctrl->done = 1; }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        ctrl->t = t1;
+        if (!ctrl->done && t1 >= P.max_iter) { ctrl->status = 2; ctrl->done = 1; }
+    }
+}
+
+}  // namespace admm

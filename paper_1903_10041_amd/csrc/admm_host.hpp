@@ -27,6 +27,7 @@ struct DevBuf {
 // Device allocations of a context, capped by its HBM budget.
 struct Arena {
     size_t budget = 0, used = 0;
+    std::mutex mu;                                 // the serving worker shares it
     admm_status ensure(DevBuf &b, size_t bytes);   // grow-only
     void release(DevBuf &b);
 };
@@ -40,6 +41,7 @@ struct Workspace {
 
 struct BatchState;
 struct ServeState;
+extern thread_local std::string g_last_error;
 
 }  // namespace admm
 
@@ -56,6 +58,10 @@ struct admm_context {
     hipGraphExec_t gexec = nullptr; // cached iteration-chunk graph
     admm::SolveParams gparams;
     int gdtype = -1, gchunk = 0;
+    bool coop = false;              // cooperative launch supported
+    int num_cu = 0;
+    int persist_cap[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+                                {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
     admm::BatchState *batch = nullptr;
     admm::ServeState *serve = nullptr;
 };
@@ -65,6 +71,8 @@ namespace admm {
 admm_status validate_settings(const admm_settings *s);
 admm_status validate_problem_shape(const admm_problem *p);
 int finalize_group(int m, int q, int nblk);
+int sweep_cpt(int n, int q);
+int persist_columns(admm_context *ctx, int dtype, int m, int n, int q);
 admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settings *s, SolveParams &P,
                     int &dtype);
 admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,

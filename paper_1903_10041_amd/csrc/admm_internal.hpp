@@ -31,6 +31,8 @@ enum { CL_INTERIOR = 0, CL_LO = 1, CL_HI = 2 };
 struct SolveParams {
     int32_t m, n, q, n_pad;
     int32_t nblk;           // sweep blocks per scenario
+    int32_t cpt;            // columns per sweep thread (1, 2 or 4)
+    int32_t persistent;     // 1: resident cooperative kernel, 0: graph of sweep + finalize
     int32_t group;          // finalize: lanes cooperating on one (i,j) pair
     int32_t check_every, max_iter;
     int32_t xstep_project, jacobi, consensus, want_codes;
@@ -50,6 +52,7 @@ struct SolveParams {
     double *part;           // block partials
     double *pair_r, *pair_s;// [q][m] check scratch
     Ctrl *ctrl;
+    uint32_t *bar;          // grid barrier words (persistent path)
 };
 
 // Partials layout (doubles): g-sum [q][nblk][m], then dg-max, dg-min (same
@@ -66,13 +69,19 @@ hipError_t launch_pack(const SolveParams &P, int dtype, int src_dtype,
                        const void *blo, const void *bhi, void *g0_dst, void *f0_dst,
                        void *y_dst, void *blo_dst, void *bhi_dst, hipStream_t s);
 hipError_t launch_cold_init(const SolveParams &P, int dtype, hipStream_t s);
-hipError_t launch_iteration(const SolveParams &P, int dtype, hipStream_t s);
-hipError_t launch_sweep(const SolveParams &P, int dtype, hipStream_t s);
+hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s);
+hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
 hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,
                          const void *w_src, hipStream_t s);
+hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, const double *C, const double *D,
+                               const double *lo, const double *hi, int project, int mixed, double *x,
+                               int32_t *codes, hipStream_t s);
+const void *persist_kernel(int dtype, int m, int R);
+hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int chunk, uint32_t spin_limit,
+                          hipStream_t s);
 int max_m_supported();
 
 }  // namespace admm

@@ -16,6 +16,7 @@
 // non-zero, so w = s - mu holds both.  Nothing else of z, lambda, s, mu is
 // stored.  All reductions run in a fixed order: results are deterministic.
 #include "admm_internal.hpp"
+#include "admm_device.hpp"
 
 #include <cfloat>
 #include <cmath>
@@ -23,363 +24,155 @@
 
 namespace admm {
 
-template <typename T> struct alignas(4 * sizeof(T)) V4 { T a, b, c, d; };
-
-__device__ __forceinline__ double clampd(double v, double lo, double hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-__device__ __forceinline__ int cstate(double u, double lo, double hi) {
-    return u < lo ? CL_LO : (u > hi ? CL_HI : CL_INTERIOR);
-}
-
-// Box-constrained minimiser of A x^4 + B x^3 + C x^2 + D x (Alg. 1).
-//   A == 0: quadratic (g2 = 0), minimiser -D / 2C.
-//   Otherwise the critical points solve x^3 + b x^2 + c x + d = 0 with
-//   b = 3B/4A, c = C/2A, d = D/4A; Q, R, Delta as in Sec. III-B.
-//   Delta > 0: one real root; Cardano with the larger-magnitude cube root
-//     taken directly and the other from S T = -Q (no cancellation).
-//   Q^3 >= 0 (with Delta <= 0): the triple root -b/3.
-//   Otherwise three real roots; only the outer two are minimisers:
-//     u3 = 2 sqrt(-Q) cos(th/3) - b/3, u1 = 2 sqrt(-Q) cos(th/3 + 2pi/3) - b/3
-//   with th = acos(R / sqrt(-Q^3)); the winner is decided by the sign of
-//   f(v1) - f(v3), factored through (v1 - v3).
-//   project == 0: v = clamp(u) (minimum over the box); project == 1: the
-//   unconstrained choice, then clamped.
-__device__ __forceinline__ double quartic_box_min(double A, double B, double C, double D,
-                                                  double lo, double hi, int project, int &code) {
-    if (A == 0.0) {
-        const double u = -D / (2.0 * C);
-        code = 3 * BR_QUAD + cstate(u, lo, hi);
-        return clampd(u, lo, hi);
-    }
-    const double ia = 1.0 / A;
-    const double b3 = 0.25 * B * ia;          // b / 3
-    const double c = 0.5 * C * ia;
-    const double d = 0.25 * D * ia;
-    const double Q = c * (1.0 / 3.0) - b3 * b3;
-    const double R = 0.5 * (b3 * c - d) - b3 * b3 * b3;
-    const double Q3 = Q * Q * Q;
-    const double Delta = Q3 + R * R;
-    double u;
-    if (Delta > 0.0) {
-        const double sq = sqrt(Delta);
-        const double S = cbrt(R + copysign(sq, R));
-        const double T = (S != 0.0) ? -Q / S : 0.0;
-        u = S + T - b3;
-        code = 3 * BR_CARDANO + cstate(u, lo, hi);
-        return clampd(u, lo, hi);
-    }
-    if (!(Q3 < 0.0)) {
-        u = -b3;
-        code = 3 * BR_TRIPLE + cstate(u, lo, hi);
-        return clampd(u, lo, hi);
-    }
-    const double sqQ = sqrt(-Q);
-    double rr = R / (-Q * sqQ);
-    rr = rr < -1.0 ? -1.0 : (rr > 1.0 ? 1.0 : rr);
-    const double th3 = acos(rr) * (1.0 / 3.0);
-    double sn, cs;
-    sincos(th3, &sn, &cs);
-    const double amp = 2.0 * sqQ;
-    const double u3 = amp * cs - b3;
-    const double u1 = amp * (-0.5 * cs - 0.86602540378443864676 * sn) - b3;
-    double v1 = u1, v3 = u3;
-    if (!project) { v1 = clampd(u1, lo, hi); v3 = clampd(u3, lo, hi); }
-    const double sv = v1 + v3, p2 = v1 * v1 + v3 * v3;
-    const double F = 0.25 * sv * p2 + b3 * (p2 + v1 * v3) + 0.5 * c * sv + d;
-    const bool hi_wins = (v1 < v3) && (F < 0.0);
-    u = hi_wins ? u3 : u1;
-    code = 3 * (hi_wins ? BR_TRIG_HI : BR_TRIG_LO) + cstate(u, lo, hi);
-    return clampd(u, lo, hi);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-// Reductions over aligned groups of G lanes (G a power of two <= 64).
-__device__ __forceinline__ double group_sum(double v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double group_max(double v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double group_min(double v, int G) {
-    for (int o = G >> 1; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ double st_round(double v) { return (double)(T)v; }
-
-// ---------------------------------------------------------------- sweep
-
-template <typename T, int MAXM>
+// Streaming sweep (graph path): one thread owns CPT columns of tile
+// (j, blockIdx.x), k = blockIdx.x * CPT * 256 + c * 256 + tid.  CHECK
+// selects the variant that also tracks the residual terms; it is used only
+// on check iterations.
+template <typename T, int MAXM, int CPT, bool MIXED, bool CHECK>
 __global__ __launch_bounds__(kBlock) void k_sweep(SolveParams P) {
-    const Ctrl *ctrl = P.ctrl;
+    Ctrl *ctrl = P.ctrl;
     if (ctrl->done) return;
-    const int t1 = ctrl->t + 1;
-    const bool check = (t1 % P.check_every) == 0;
-    const int m = P.m, n = P.n, n_pad = P.n_pad;
+    // the graph places the check variant by iteration number; flag any
+    // disagreement with the device counter (reported as a device error)
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 &&
+        (((ctrl->t + 1) % P.check_every) == 0) != CHECK)
+        atomicOr(&ctrl->bad_input, 2);
     const int j = blockIdx.y;
-    const int tid = threadIdx.x;
-    const int k = blockIdx.x * kBlock + tid;
-    const V4<T> *coef = (const V4<T> *)P.coef;
-    T *X = (T *)P.x;
-    T *Wv = (T *)P.w;
-    const T *Y = (const T *)P.y;
-    const T *G0 = (const T *)P.g0;
-
-    double gsum[MAXM], dgmax[MAXM], dgmin[MAXM];
+    Scal<MAXM> sc;
+    scal_load<MAXM, false>(P, j, sc);
+    Acc<MAXM> acc;
+    acc.reset();
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) { gsum[i] = 0.0; dgmax[i] = -DBL_MAX; dgmin[i] = DBL_MAX; }
-    double rdem = 0.0, sig3 = 0.0;
-
-    if (k < n) {
-        const size_t col = (size_t)j * n_pad + k;
-        const double y = (double)Y[col];
-        const double w = (double)Wv[col];
-        const double s_old = fmax(w, 0.0), mu_old = fmax(-w, 0.0);
-        const double sm = s_old + mu_old;
-        double xo[MAXM], xc[MAXM];
-        double sum_old = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXM; ++i) {
-            xo[i] = (i < m) ? (double)X[((size_t)j * m + i) * n_pad + k] : 0.0;
-            xc[i] = xo[i];
-            sum_old += xo[i];
-        }
-#pragma unroll
-        for (int i = 0; i < MAXM; ++i) {
-            if (i < m) {
-                const size_t e = ((size_t)j * m + i) * n_pad + k;
-                const int pi = j * m + i;
-                const V4<T> cf = coef[e];
-                const double f2 = cf.a, f1 = cf.b, g2 = cf.c, g1 = cf.d;
-                const double g0 = G0 ? (double)G0[e] : 0.0;
-                double lo, hi;
-                if (P.blo) {
-                    lo = (double)((const T *)P.blo)[(size_t)i * n_pad + k];
-                    hi = (double)((const T *)P.bhi)[(size_t)i * n_pad + k];
-                } else {
-                    lo = P.slo[i];
-                    hi = P.shi[i];
-                }
-                const double g_old = (g2 * xo[i] + g1) * xo[i] + g0;
-                const double theta = (g_old + P.zoff[pi]) + P.lam[pi];
-                double others = 0.0;
-#pragma unroll
-                for (int l = 0; l < MAXM; ++l)
-                    if (l < m && l != i) others += P.jacobi ? xo[l] : xc[l];
-                const double phi = sm - others + y;
-                const double tg = theta - g0;
-                const double A = 0.5 * P.rho1 * g2 * g2;
-                const double B = P.rho1 * g2 * g1;
-                double C = f2 * P.inv_q + P.rho1 * (0.5 * g1 * g1 - g2 * tg) + 0.5 * P.rho3;
-                double D = f1 * P.inv_q - P.rho1 * g1 * tg - P.rho3 * phi;
-                if (P.consensus && k == 0) {
-                    C += 0.5 * P.rho4;
-                    D -= P.rho4 * (P.xbar1[i] + P.nu[pi]);
-                }
-                int code;
-                const double xn = st_round<T>(quartic_box_min(A, B, C, D, lo, hi, P.xstep_project, code));
-                xc[i] = xn;
-                X[e] = (T)xn;
-                if (P.want_codes) P.codes[e] = (uint8_t)code;
-                if (k == 0) P.x1[pi] = xn;
-                const double g_new = (g2 * xn + g1) * xn + g0;
-                gsum[i] = g_new;
-                const double dg = g_new - g_old;
-                dgmax[i] = dg;
-                dgmin[i] = dg;
-            }
-        }
-        double sum_new = 0.0;
-#pragma unroll
-        for (int i = 0; i < MAXM; ++i) sum_new += (i < m) ? xc[i] : 0.0;
-        const double wn = st_round<T>(sum_new - y - mu_old);
-        Wv[col] = (T)wn;
-        const double s_new = fmax(wn, 0.0);
-        rdem = fabs(s_new - sum_new + y);
-        sig3 = fabs((s_new - s_old) - (sum_new - sum_old));
-    }
-
-    __shared__ double red[kWaves][3 * MAXM + 2];
-    const int lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-        if (i < m) {
-            const double v = wave_sum(gsum[i]);
-            if (lane == 0) red[wv][i] = v;
+    for (int cc = 0; cc < CPT; ++cc) {
+        const int k = blockIdx.x * (kBlock * CPT) + cc * kBlock + threadIdx.x;
+        if (k < P.n) {
+            Col<T, MAXM> d;
+            col_load(P, j, k, d);
+            col_update<T, MAXM, MIXED, CHECK>(P, j, k, d, sc, acc);
+            col_store(P, j, k, d);
         }
     }
-    if (check) {
-#pragma unroll
-        for (int i = 0; i < MAXM; ++i) {
-            if (i < m) {
-                const double a = wave_max(dgmax[i]);
-                const double b = wave_min(dgmin[i]);
-                if (lane == 0) { red[wv][MAXM + i] = a; red[wv][2 * MAXM + i] = b; }
-            }
-        }
-        const double a = wave_max(rdem), b = wave_max(sig3);
-        if (lane == 0) { red[wv][3 * MAXM] = a; red[wv][3 * MAXM + 1] = b; }
-    }
-    __syncthreads();
-    const size_t slab = (size_t)P.q * P.nblk * m;
-    const size_t bidx = (size_t)j * P.nblk + blockIdx.x;
-    if (tid < m) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += red[w][tid];
-        P.part[bidx * m + tid] = s;
-        if (check) {
-            double a = red[0][MAXM + tid], b = red[0][2 * MAXM + tid];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) {
-                a = fmax(a, red[w][MAXM + tid]);
-                b = fmin(b, red[w][2 * MAXM + tid]);
-            }
-            P.part[slab + bidx * m + tid] = a;
-            P.part[2 * slab + bidx * m + tid] = b;
-        }
-    }
-    if (check && tid == 0) {
-        double a = red[0][3 * MAXM], b = red[0][3 * MAXM + 1];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) {
-            a = fmax(a, red[w][3 * MAXM]);
-            b = fmax(b, red[w][3 * MAXM + 1]);
-        }
-        P.part[3 * slab + bidx * 2] = a;
-        P.part[3 * slab + bidx * 2 + 1] = b;
-    }
+    __shared__ double lds[MAXM + 2][kBlock];
+    block_partials<MAXM>(P, (size_t)j * P.nblk + blockIdx.x, acc, CHECK, lds);
 }
 
-// ------------------------------------------------------------- finalize
-
-__device__ __forceinline__ double block_max(double v, double *lds) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    v = wave_max(v);
-    __syncthreads();
-    if (lane == 0) lds[wv] = v;
-    __syncthreads();
-    double r = lds[0];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w) r = fmax(r, lds[w]);
-    return r;
+// Element-wise quartic minimiser (parity tests of the device math).
+template <bool MIXED>
+__global__ void k_quartic(int64_t N, const double *A, const double *B, const double *C, const double *D,
+                          const double *lo, const double *hi, int project, double *x, int32_t *codes) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
+        int code;
+        const double v = MIXED ? qmin_mixed(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code)
+                               : qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        x[e] = v;
+        codes[e] = code;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P) {
-    Ctrl *ctrl = P.ctrl;
-    if (ctrl->done) return;
-    const int t1 = ctrl->t + 1;
-    const bool check = (t1 % P.check_every) == 0;
-    const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group;
-    const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = kBlock / G;
-    const size_t slab = (size_t)q * nblk * m;
-    const double *pg = P.part, *pmax = P.part + slab, *pmin = P.part + 2 * slab;
-    const double *pr = P.part + 3 * slab;
-    const double nd = (double)P.n;
-    const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+    if (P.ctrl->done) return;
+    finalize_body(P);
+}
 
-    // (7b), (7g), (7d), (7i) per (i, j)
-    for (int base = 0; base < M; base += ngroups) {
-        const int pi = base + gid;
-        const bool active = pi < M;
-        const int j = active ? pi / m : 0, i = active ? pi % m : 0;
-        double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
-        if (active) {
-            for (int bb = gl; bb < nblk; bb += G) {
-                const size_t idx = ((size_t)j * nblk + bb) * m + i;
-                s += pg[idx];
-                if (check) { mx = fmax(mx, pmax[idx]); mn = fmin(mn, pmin[idx]); }
-            }
-        }
-        s = group_sum(s, G);
-        if (check) { mx = group_max(mx, G); mn = group_min(mn, G); }
-        if (active && gl == 0) {
-            const double lam_old = P.lam[pi], zoff_old = P.zoff[pi];
-            const double h_old = P.h[pi], p_old = P.p[pi];
-            const double W = s - nd * lam_old;              // 1'(g(x) - lambda)
-            const double kap = kfac * (h_old + p_old - W);
-            const double sumz = W + nd * kap;               // 1'z
-            const double zoff_new = kap - lam_old;          // z - g(x)
-            const double hn = fmin(P.cap[i], sumz - p_old);
-            const double pn = p_old + hn - sumz;
-            P.lam[pi] = kap;
-            P.zoff[pi] = zoff_new;
-            P.h[pi] = hn;
-            P.p[pi] = pn;
-            if (check) {
-                const double cz = zoff_new - zoff_old;
-                P.pair_r[pi] = fmax(fabs(zoff_new), fabs(hn - sumz));
-                P.pair_s[pi] = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)),
-                                    P.rho2 * fabs(hn - h_old));
-            }
-        }
+// ---------------------------------------------------- persistent resident
+
+// Grid barrier words: [0] arrivals, [1] generation, [2] abort.
+__device__ __forceinline__ bool grid_arrive(uint32_t *bar, int G) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (old == (uint32_t)(G - 1));
     }
     __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
 
-    // (7c): x_1 = mean_j (x_1^(i,j) - nu^(i,j)); (7h): nu += x_1 - x_1^(i,j)
-    if (P.consensus) {
-        int G2 = 64;
-        while (G2 > 1 && m * G2 > kBlock) G2 >>= 1;
-        const int g2l = tid & (G2 - 1), g2id = tid / G2;
-        for (int base = 0; base < m; base += kBlock / G2) {
-            const int i = base + g2id;
-            double s = 0.0;
-            if (i < m)
-                for (int jj = g2l; jj < q; jj += G2) s += P.x1[jj * m + i] - P.nu[jj * m + i];
-            s = group_sum(s, G2);
-            if (i < m && g2l == 0) P.xbar1[i] = s * P.inv_q;
-        }
-        __syncthreads();
-        for (int pi = tid; pi < M; pi += kBlock) {
-            const double res = P.xbar1[pi % m] - P.x1[pi];
-            P.nu[pi] += res;
-            if (check) P.pair_r[pi] = fmax(P.pair_r[pi], fabs(res));
-        }
-        __syncthreads();
+__device__ __forceinline__ void grid_release(uint32_t *bar) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(bar + 1, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+    __syncthreads();
+}
 
-    __shared__ double lds[kWaves];
-    if (check) {
-        double r = 0.0, sg = 0.0;
-        for (int pi = tid; pi < M; pi += kBlock) {
-            r = fmax(r, P.pair_r[pi]);
-            sg = fmax(sg, P.pair_s[pi]);
+// Wait until the generation reaches `target`.  Bounded: after `limit`
+// polls the block raises the abort word and every block leaves.
+__device__ __forceinline__ bool grid_wait(uint32_t *bar, uint32_t target, uint32_t limit) {
+    __shared__ int ok;
+    if (threadIdx.x == 0) {
+        int res = 1;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(bar + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { res = 0; break; }
+            if (++spins > limit) {
+                __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                res = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
         }
-        for (int bb = tid; bb < q * nblk; bb += kBlock) {
-            r = fmax(r, pr[2 * bb]);
-            sg = fmax(sg, P.rho3 * pr[2 * bb + 1]);
-        }
-        r = block_max(r, lds);
-        sg = block_max(sg, lds);
-        if (tid == 0) {
-            ctrl->r = r;
-            ctrl->sigma = sg;
-            if (!(r == r) || !(sg == sg)) { ctrl->status = -4; ctrl->done = 1; }
-            else if (r < P.eps_p && sg < P.eps_d) { ctrl->status = 0; ctrl->done = 1; }
-        }
+        ok = res;
     }
-    if (tid == 0) {
-        ctrl->t = t1;
-        if (!ctrl->done && t1 >= P.max_iter) { ctrl->status = 2; ctrl->done = 1; }
+    __syncthreads();
+    __threadfence();
+    return ok != 0;
+}
+
+// Persistent solve: one block per tile (j, blockIdx.x % nblk), R columns per
+// thread kept in registers across iterations; each iteration ends in a grid
+// barrier whose last arriving block runs the scalar steps.  Launched
+// cooperatively (all blocks resident) for at most `chunk` iterations.
+template <typename T, int MAXM, int R, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_persist(SolveParams P, uint32_t *bar, int chunk, uint32_t spin_limit) {
+    const int tile = blockIdx.x;
+    const int j = tile / P.nblk, kb = tile - j * P.nblk;
+    Col<T, MAXM> d[R];
+    int kk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        kk[r] = kb * (kBlock * R) + r * kBlock + threadIdx.x;
+        if (kk[r] < P.n) col_load(P, j, kk[r], d[r]);
     }
+    __shared__ double lds[MAXM + 2][kBlock];
+    uint32_t gen = 0;
+    for (int it = 0; it < chunk; ++it) {
+        // keep the resident columns opaque to loop-invariant code motion:
+        // values derived from the coefficients are recomputed each
+        // iteration instead of occupying registers across iterations
+#pragma unroll
+        for (int r = 0; r < R; ++r) opaque(d[r]);
+        if (__hip_atomic_load(&P.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        const int t1 = __hip_atomic_load(&P.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+        const bool check = (t1 % P.check_every) == 0;
+        Scal<MAXM> sc;
+        scal_load<MAXM, true>(P, j, sc);
+        Acc<MAXM> acc;
+        acc.reset();
+        if (check) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (kk[r] < P.n) col_update<T, MAXM, MIXED, true>(P, j, kk[r], d[r], sc, acc);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (kk[r] < P.n) col_update<T, MAXM, MIXED, false>(P, j, kk[r], d[r], sc, acc);
+        }
+        block_partials<MAXM>(P, (size_t)tile, acc, check, lds);
+        if (grid_arrive(bar, gridDim.x)) {
+            finalize_body(P);
+            grid_release(bar);
+        }
+        ++gen;
+        if (!grid_wait(bar, gen, spin_limit)) break;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (kk[r] < P.n) col_store(P, j, kk[r], d[r]);
 }
 
 // ------------------------------------------------------------ pack / init
@@ -446,13 +239,14 @@ __global__ void k_pack(SolveParams P, const S *f2, const S *f1, const S *g2, con
 template <typename T, int MAXM>
 __global__ __launch_bounds__(kBlock) void k_init_cols(SolveParams P) {
     const int m = P.m, n = P.n, n_pad = P.n_pad, j = blockIdx.y, tid = threadIdx.x;
-    const int k = blockIdx.x * kBlock + tid;
     const V4<T> *coef = (const V4<T> *)P.coef;
     const T *G0 = (const T *)P.g0;
     double gsum[MAXM];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) gsum[i] = 0.0;
-    if (k < n) {
+    for (int cc = 0; cc < P.cpt; ++cc) {
+        const int k = blockIdx.x * (kBlock * P.cpt) + cc * kBlock + tid;
+        if (k >= n) continue;
         const size_t col = (size_t)j * n_pad + k;
         double sx = 0.0;
 #pragma unroll
@@ -472,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_init_cols(SolveParams P) {
                 if (k == 0) P.x1[j * m + i] = x0;
                 const V4<T> cf = coef[e];
                 const double g0 = G0 ? (double)G0[e] : 0.0;
-                gsum[i] = ((double)cf.c * x0 + (double)cf.d) * x0 + g0;
+                gsum[i] += ((double)cf.c * x0 + (double)cf.d) * x0 + g0;
                 sx += x0;
             }
         }
@@ -613,18 +407,70 @@ __global__ __launch_bounds__(kBlock) void k_obj_final(SolveParams P, const doubl
 
 int max_m_supported() { return 8; }
 
-template <typename T>
-static void launch_sweep_t(const SolveParams &P, hipStream_t s) {
+template <typename T, bool MIXED, int CPT, bool CHECK>
+static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (P.m <= 2) k_sweep<T, 2><<<grid, kBlock, 0, s>>>(P);
-    else if (P.m <= 4) k_sweep<T, 4><<<grid, kBlock, 0, s>>>(P);
-    else k_sweep<T, 8><<<grid, kBlock, 0, s>>>(P);
+    if (P.m <= 2) k_sweep<T, 2, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
+    else if (P.m <= 4) k_sweep<T, 4, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
+    else k_sweep<T, 8, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
 }
 
-hipError_t launch_sweep(const SolveParams &P, int dtype, hipStream_t s) {
-    if (dtype == 0) launch_sweep_t<double>(P, s);
-    else launch_sweep_t<float>(P, s);
+template <typename T, bool MIXED, bool CHECK>
+static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
+    switch (P.cpt) {
+    case 1: launch_sweep_c<T, MIXED, 1, CHECK>(P, s); break;
+    case 2: launch_sweep_c<T, MIXED, 2, CHECK>(P, s); break;
+    default: launch_sweep_c<T, MIXED, 4, CHECK>(P, s); break;
+    }
+}
+
+// `check`: the iteration this launch performs is a residual-check
+// iteration (the caller knows the iteration number: graphs are captured
+// in chunks that start at a multiple of check_every).
+hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s) {
+    if (dtype == 0) {
+        if (check) launch_sweep_k<double, false, true>(P, s);
+        else launch_sweep_k<double, false, false>(P, s);
+    } else {
+        if (check) launch_sweep_k<float, true, true>(P, s);
+        else launch_sweep_k<float, true, false>(P, s);
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, const double *C, const double *D,
+                               const double *lo, const double *hi, int project, int mixed, double *x,
+                               int32_t *codes, hipStream_t s) {
+    int64_t g = (N + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    if (mixed) k_quartic<true><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    else k_quartic<false><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    return hipGetLastError();
+}
+
+template <typename T, int MAXM, int R, bool MIXED>
+static const void *persist_fn() {
+    return (const void *)k_persist<T, MAXM, R, MIXED>;
+}
+
+template <typename T, bool MIXED>
+static const void *persist_fn_m(int m, int R) {
+    if (m <= 2) return R == 1 ? persist_fn<T, 2, 1, MIXED>() : R == 2 ? persist_fn<T, 2, 2, MIXED>() : persist_fn<T, 2, 4, MIXED>();
+    if (m <= 4) return R == 1 ? persist_fn<T, 4, 1, MIXED>() : R == 2 ? persist_fn<T, 4, 2, MIXED>() : persist_fn<T, 4, 4, MIXED>();
+    return R == 1 ? persist_fn<T, 8, 1, MIXED>() : R == 2 ? persist_fn<T, 8, 2, MIXED>() : persist_fn<T, 8, 4, MIXED>();
+}
+
+const void *persist_kernel(int dtype, int m, int R) {
+    return dtype == 0 ? persist_fn_m<double, false>(m, R) : persist_fn_m<float, true>(m, R);
+}
+
+hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int chunk, uint32_t spin_limit,
+                          hipStream_t s) {
+    const void *fn = persist_kernel(dtype, P.m, P.cpt);
+    SolveParams Pc = P;
+    void *args[] = {&Pc, &bar, &chunk, &spin_limit};
+    return hipLaunchCooperativeKernel(fn, dim3(P.nblk * P.q), dim3(kBlock), args, 0, s);
 }
 
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
@@ -632,8 +478,8 @@ hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const SolveParams &P, int dtype, hipStream_t s) {
-    hipError_t e = launch_sweep(P, dtype, s);
+hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s) {
+    hipError_t e = launch_sweep(P, dtype, check, s);
     if (e != hipSuccess) return e;
     return launch_finalize(P, s);
 }

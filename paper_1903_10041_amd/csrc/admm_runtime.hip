@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <string>
@@ -38,6 +39,7 @@ DeviceGuard::~DeviceGuard() {
 }
 
 admm_status Arena::ensure(DevBuf &b, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
     if (bytes == 0) bytes = 256;
     bytes = (bytes + 255) & ~size_t(255);
     if (b.bytes >= bytes) return ADMM_OK;
@@ -55,6 +57,7 @@ admm_status Arena::ensure(DevBuf &b, size_t bytes) {
 }
 
 void Arena::release(DevBuf &b) {
+    std::lock_guard<std::mutex> lk(mu);
     if (b.p) { (void)hipFree(b.p); used -= b.bytes; }
     b.p = nullptr;
     b.bytes = 0;
@@ -163,10 +166,15 @@ extern "C" admm_status admm_create(admm_context **out, int device, size_t budget
     if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->hctrl, 2 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&ctx->hctrl, 4 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return fail(ADMM_E_DEVICE, "stream/event/pinned allocation failed");
     }
+    int coop = 0, ncu = 0;
+    (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    ctx->coop = coop != 0;
+    ctx->num_cu = ncu;
     *out = ctx;
     return ADMM_OK;
 }
@@ -228,6 +236,57 @@ static int pow2_floor(int v) {
     return p;
 }
 
+// Columns per sweep thread: more columns amortise the per-block scalar
+// loads and reductions, fewer keep more waves in flight.  ADMM_SWEEP_CPT
+// overrides (1, 2 or 4) for tuning sweeps.
+int sweep_cpt(int n, int q) {
+    static int forced = [] {
+        const char *e = std::getenv("ADMM_SWEEP_CPT");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 1 || v == 2 || v == 4) ? v : 0;
+    }();
+    if (forced) return forced;
+    (void)n;
+    (void)q;
+    return 1;
+}
+
+// Columns per thread of the persistent resident path, or 0 when the
+// problem does not fit the co-resident grid (then the graph path runs).
+// One block per tile of 256 R columns; the smallest R whose grid fits.
+// ADMM_PATH=graph forces the graph path.
+int persist_columns(admm_context *ctx, int dtype, int m, int n, int q) {
+    static const bool graph_only = [] {
+        const char *e = std::getenv("ADMM_PATH");
+        return e && std::string(e) == "graph";
+    }();
+    if (graph_only || !ctx->coop) return 0;
+    // the grid barrier costs tens of microseconds on a full grid; the
+    // resident path pays off only for small grids (ADMM_PERSIST_MAX_TILES)
+    static const long max_tiles = [] {
+        const char *e = std::getenv("ADMM_PERSIST_MAX_TILES");
+        return e ? std::atol(e) : 16L;
+    }();
+    static const int forced_r = [] {
+        const char *e = std::getenv("ADMM_PERSIST_R");
+        const int v = e ? std::atoi(e) : 0;
+        return (v == 1 || v == 2 || v == 4) ? v : 0;
+    }();
+    for (int R : {1, 2, 4}) {
+        if (forced_r && R != forced_r) continue;
+        const long tiles = (long)q * ((n + kBlock * R - 1) / (kBlock * R));
+        int &cap = ctx->persist_cap[dtype][m <= 2 ? 0 : (m <= 4 ? 1 : 2)][R == 1 ? 0 : (R == 2 ? 1 : 2)];
+        if (cap < 0) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel(dtype, m, R), kBlock, 0) != hipSuccess)
+                nb = 0;
+            cap = nb * ctx->num_cu;
+        }
+        if (tiles <= cap && tiles <= max_tiles) return R;
+    }
+    return 0;
+}
+
 int finalize_group(int m, int q, int nblk) {
     int G = pow2_floor(std::max(1, kBlock / (m * q)));
     if (G > 64) G = 64;
@@ -242,12 +301,16 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     Arena &A = ctx->arena;
     dtype = s->precision == ADMM_F64 ? 0 : 1;
     const size_t T = dtype == 0 ? 8 : 4;
+    std::memset(&P, 0, sizeof P);
     const int m = pr->m, n = pr->n, q = pr->q;
     const int n_pad = (n + kPad - 1) / kPad * kPad;
-    const int nblk = (n + kBlock - 1) / kBlock;
+    int cpt = sweep_cpt(n, q);
+    const int R = persist_columns(ctx, dtype, m, n, q);
+    if (R > 0) cpt = R;
+    const int nblk = (n + kBlock * cpt - 1) / (kBlock * cpt);
+    P.persistent = R > 0;
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
-    std::memset(&P, 0, sizeof P);
-    P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk;
+    P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     P.group = finalize_group(m, q, nblk);
     P.check_every = s->check_every;
     P.max_iter = s->max_iter;
@@ -255,7 +318,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.jacobi = s->sweep == ADMM_SWEEP_JACOBI;
     P.consensus = (q > 1) || s->consensus_q1;
     P.want_codes = s->debug_branch_codes ? 1 : 0;
-    P.rho1 = s->rho[0]; P.rho2 = s->rho[1]; P.rho3 = s->rho[2]; P.rho4 = s->rho[3];
+    P.rho1 = s->rho[0]; P.rho2 = s->rho[1] / (s->rho2_per_step ? (double)n : 1.0);
+    P.rho3 = s->rho[2]; P.rho4 = s->rho[3];
     P.inv_q = 1.0 / q;
     P.eps_p = s->eps_primal;
     P.eps_d = s->eps_dual;
@@ -267,7 +331,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     ENS(W.w, K * T);
     ENS(W.scal, (7 * M + m + 3 * (size_t)m) * sizeof(double) + 2 * M * sizeof(double));
     ENS(W.part, part_doubles(m, q, nblk) * sizeof(double));
-    ENS(W.ctrl, sizeof(Ctrl));
+    ENS(W.ctrl, sizeof(Ctrl) + 64);
     ENS(W.obj, 1024 * sizeof(double));
     if (pr->g0) ENS(W.g0, E * T);
     if (pr->f0) ENS(W.f0, E * T);
@@ -286,6 +350,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.codes = P.want_codes ? (uint8_t *)W.codes.p : nullptr;
     P.part = (double *)W.part.p;
     P.ctrl = (Ctrl *)W.ctrl.p;
+    P.bar = (uint32_t *)((char *)W.ctrl.p + sizeof(Ctrl));
     return ADMM_OK;
 }
 
@@ -448,8 +513,37 @@ static int chunk_for(int check_every) {
     return c;
 }
 
+// Persistent path: cooperative launches of at most kPersistChunk iterations
+// each, until the device stop flag is set.
+constexpr int kPersistChunk = 20000;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+admm_status iterate_persistent(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms) {
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    int done = P.max_iter == 0;
+    long launched_iters = 0;
+    while (!done && launched_iters < (long)P.max_iter + kPersistChunk) {
+        HIPCHK(hipMemsetAsync(P.bar, 0, 4 * sizeof(uint32_t), s));
+        hipError_t e = launch_persist(P, dtype, P.bar, kPersistChunk, kSpinLimit, s);
+        if (e != hipSuccess) return fail(ADMM_E_DEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
+        launched_iters += kPersistChunk;
+        HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl) + 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const uint32_t *hb = (const uint32_t *)((const char *)ctx->hctrl + sizeof(Ctrl));
+        if (hb[2]) return fail(ADMM_E_DEVICE, "grid barrier timed out (aborted)");
+        done = ctx->hctrl->done;
+    }
+    HIPCHK(hipEventRecord(ctx->ev1, s));
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (dev_ms) *dev_ms = ms;
+    return ADMM_OK;
+}
+
 // Run the iteration to the device stop flag with a captured graph per chunk.
 admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms) {
+    if (P.persistent) return iterate_persistent(ctx, P, dtype, s, dev_ms);
     const int chunk = chunk_for(P.check_every);
     const bool reuse = ctx->gexec && ctx->gdtype == dtype && ctx->gchunk == chunk &&
                        std::memcmp(&ctx->gparams, &P, sizeof P) == 0;
@@ -458,7 +552,7 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < chunk; ++c) {
-            hipError_t e = launch_iteration(P, dtype, s);
+            hipError_t e = launch_iteration(P, dtype, (c + 1) % P.check_every == 0, s);
             if (e != hipSuccess) {
                 hipGraph_t junk;
                 (void)hipStreamEndCapture(s, &junk);
@@ -596,6 +690,7 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     }
     HIPCHK(hipStreamSynchronize(s));
     const Ctrl c = *ctx->hctrl;
+    if (c.bad_input & 2) return fail(ADMM_E_DEVICE, "check-iteration schedule out of step");
     if (state_out && (st = export_state(ctx, pr, P, dtype, state_out, s)) != ADMM_OK) return st;
     admm_info inf;
     std::memset(&inf, 0, sizeof inf);
@@ -688,14 +783,69 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
     HIPCHK(launch_cold_init(P, dtype, s));
     const int per = 20, reps = std::max(1, iters / per);
     double sw = 0, fi = 0, it = 0;
-    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, s); }, &sw)) != ADMM_OK) return st;
+    // per = 20 launches per graph, two check iterations among them (the
+    // check variant of the sweep is used where the iteration count says so)
+    int c1 = 0, c2 = 0, c3 = 0;
+    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, (++c1 % 10) == 0, s); }, &sw)) != ADMM_OK) return st;
     if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, s); }, &fi)) != ADMM_OK) return st;
-    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, s); }, &it)) != ADMM_OK) return st;
+    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, (++c3 % 10) == 0, s); }, &it)) != ADMM_OK) return st;
+    (void)c2;
     out[0] = sw;
     out[1] = fi;
     out[2] = it;
     out[3] = (double)reps * per;
+    out[4] = 0.0;
+    out[5] = 0.0;
+    if (P.persistent) {
+        // the resident path: one cooperative launch of `n_it` iterations
+        const int n_it = std::max(20, iters);
+        SolveParams Q = P;
+        HIPCHK(launch_cold_init(Q, dtype, s));
+        HIPCHK(hipMemsetAsync(Q.bar, 0, 4 * sizeof(uint32_t), s));
+        HIPCHK(launch_persist(Q, dtype, Q.bar, 10, 1u << 22, s));   // warm
+        HIPCHK(hipMemsetAsync(Q.bar, 0, 4 * sizeof(uint32_t), s));
+        HIPCHK(hipEventRecord(ctx->ev0, s));
+        HIPCHK(launch_persist(Q, dtype, Q.bar, n_it, 1u << 22, s));
+        HIPCHK(hipEventRecord(ctx->ev1, s));
+        HIPCHK(hipStreamSynchronize(s));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+        HIPCHK(hipMemcpy(ctx->hctrl, Q.ctrl, sizeof(Ctrl) + 16, hipMemcpyDeviceToHost));
+        const uint32_t *hb = (const uint32_t *)((const char *)ctx->hctrl + sizeof(Ctrl));
+        if (hb[2]) return fail(ADMM_E_DEVICE, "grid barrier timed out (aborted)");
+        out[4] = 1000.0 * ms / n_it;
+        out[5] = (double)P.cpt;
+    }
     HIPCHK(hipEventRecord(ctx->join, s));
     HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    return ADMM_OK;
+}
+
+// Element-wise device quartic minimiser over host arrays (tests of the
+// device math against the oracle).
+extern "C" admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const double *A, const double *B,
+                                          const double *C, const double *D, const double *lo, const double *hi,
+                                          int32_t paper_project, int32_t precision, double *x_out,
+                                          int32_t *codes_out) {
+    if (!ctx || !A || !B || !C || !D || !lo || !hi || !x_out || !codes_out || N < 0)
+        return fail(ADMM_E_INVALID_ARG, "NULL argument");
+    if (N == 0) return ADMM_OK;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->own;
+    const size_t bytes = (size_t)N * (7 * sizeof(double) + sizeof(int32_t));
+    admm_status st = ctx->arena.ensure(ctx->ws.staging, bytes);
+    if (st != ADMM_OK) return st;
+    double *d = (double *)ctx->ws.staging.p;
+    const double *src[6] = {A, B, C, D, lo, hi};
+    for (int a = 0; a < 6; ++a)
+        HIPCHK(hipMemcpyAsync(d + (size_t)a * N, src[a], N * sizeof(double), hipMemcpyHostToDevice, s));
+    double *xd = d + 6 * (size_t)N;
+    int32_t *cd = (int32_t *)(d + 7 * (size_t)N);
+    HIPCHK(launch_quartic_test(N, d, d + N, d + 2 * N, d + 3 * N, d + 4 * N, d + 5 * N, paper_project,
+                               precision == ADMM_F32_MIXED, xd, cd, s));
+    HIPCHK(hipMemcpyAsync(x_out, xd, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(codes_out, cd, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return ADMM_OK;
 }

@@ -1,0 +1,126 @@
+"""Batched solve: many instances of different (m, n) in one launch, each
+checked against the FP64 oracle and against the same instance solved
+alone."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10041_amd import admm
+from paper_1903_10041_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = admm.Context(0)
+    yield c
+    c.close()
+
+
+def mixed_batch(count=48, seed=300, n_hi=700):
+    """Instances with m in 1..8 and n in 1..n_hi; capacities 0.7 sum g(2)
+    (slack) or, for m >= 4, 0.3 sum g(2) (binding but feasible)."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for b in range(count):
+        m = int(rng.integers(1, 9))
+        n = int(rng.integers(1, n_hi))
+        frac = float(rng.choice([0.7, 0.3])) if m >= 4 else 0.7
+        probs.append(W.uniform_problem(m, n, seed * 1000 + b, cap_fraction=frac))
+    return probs
+
+
+def fixed(iters, **kw):
+    return admm.Settings(max_iter=iters, eps_primal=0.0, eps_dual=0.0, **kw)
+
+
+def test_batch_trajectory_parity_fp64(ctx):
+    probs = mixed_batch()
+    print(f"[batch trajectory] {len(probs)} instances, 300 iterations", flush=True)
+    xs, infos = ctx.solve_batch(probs, fixed(300))
+    for p, x, inf in zip(probs, xs, infos):
+        st, oi, _ = oracle.run(p, max_iter=300)
+        assert inf["iters"] == 300 and inf["status"] == admm.MAX_ITER
+        assert np.abs(x - st["x"]).max() <= 1e-9, (p.m, p.n)
+        assert abs(inf["objective"] - oi["objective"]) <= 1e-9 * (1 + abs(oi["objective"]))
+        assert abs(inf["r"] - oi["r"]) <= 1e-6 * abs(oi["r"]) + 1e-10
+        assert abs(inf["sigma"] - oi["sigma"]) <= 1e-6 * abs(oi["sigma"]) + 1e-10
+
+
+def test_batch_matches_alone_and_converges(ctx):
+    probs = mixed_batch(count=24, seed=301, n_hi=300)
+    s = admm.Settings(max_iter=100000, eps_primal=1e-6, eps_dual=1e-6)
+    print("[batch converge] 24 instances to 1e-6", flush=True)
+    xs, infos = ctx.solve_batch(probs, s)
+    for p, x, inf in zip(probs, xs, infos):
+        xa, ia, _ = ctx.solve(p, s)
+        assert inf["status"] == admm.OK and ia["status"] == admm.OK
+        assert abs(inf["iters"] - ia["iters"]) <= 10
+        assert abs(inf["objective"] - ia["objective"]) <= 1e-8 * (1 + abs(ia["objective"]))
+
+
+def test_batch_result_independent_of_the_mix(ctx):
+    """Each instance's result is bit-identical alone (a batch of one) and
+    inside a larger batch."""
+    probs = mixed_batch(count=32, seed=302)
+    s = fixed(200)
+    xs, infos = ctx.solve_batch(probs, s)
+    for b in (0, 7, 31):
+        xa, ia = ctx.solve_batch([probs[b]], s)
+        assert np.array_equal(xa[0], xs[b])
+        assert ia[0]["objective"] == infos[b]["objective"]
+
+
+def test_batch_fp32_mixed(ctx):
+    probs = mixed_batch(count=24, seed=303, n_hi=300)
+    s = admm.Settings(max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED)
+    print("[batch fp32] 24 instances to 1e-4", flush=True)
+    xs, infos = ctx.solve_batch(probs, s)
+    for p, x, inf in zip(probs, xs, infos):
+        st, oi, _ = oracle.run(p, max_iter=100000, eps_primal=1e-4, eps_dual=1e-4)
+        assert inf["status"] == admm.OK
+        assert abs(inf["objective"] - oi["objective"]) <= 1e-4 * (1 + abs(oi["objective"]))
+
+
+def test_batch_device_inputs_match_host(ctx):
+    import torch
+    probs = mixed_batch(count=16, seed=304)
+    dev = torch.device("cuda:0")
+    tp = []
+    for p in probs:
+        t = W.Problem(**{k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) and k != "c" else v)
+                         for k, v in vars(p).items()})
+        t.c = p.c
+        tp.append(t)
+    xh, ih = ctx.solve_batch(probs, fixed(150))
+    xd, idv = ctx.solve_batch(tp, fixed(150))
+    for a, b in zip(xh, xd):
+        assert np.array_equal(a, b.cpu().numpy())
+
+
+def test_batch_with_instances_outside_the_kernel(ctx):
+    """q > 1 and per-step bounds go through the plain path inside the same
+    call; results equal solving them alone."""
+    rob = W.phev_c4(seed=9, q=3, n=50)
+    ps = W.uniform_problem(3, 80, 11)
+    ps.xlo = np.zeros((3, 80))
+    ps.xhi = np.full((3, 80), 2.0)
+    plain = W.uniform_problem(2, 90, 12)
+    s = fixed(120)
+    xs, infos = ctx.solve_batch([rob, ps, plain], s)
+    for p, x in zip([rob, ps], xs[:2]):
+        xa, _, _ = ctx.solve(p, s)
+        assert np.array_equal(x, xa)
+    st, _, _ = oracle.run(plain, max_iter=120)
+    assert np.abs(xs[2] - st["x"]).max() <= 1e-9
+
+
+def test_batch_invalid_instance(ctx):
+    probs = mixed_batch(count=5, seed=305)
+    probs[3].g2[0, 0, 0] = -1.0
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.solve_batch(probs, fixed(10))
+    assert e.value.status == admm.E_INVALID_ARG

@@ -1,0 +1,79 @@
+"""Device quartic minimiser (Alg. 1 with the box rule) against the oracle,
+element by element, on the same random quartic families the oracle's own
+pins use (ADMM-shaped, stress and generic)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10041_amd import admm
+from tests.test_oracle_quartic import _random_quartics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = admm.Context(0)
+    yield c
+    c.close()
+
+
+def _f(A, B, C, D, x):
+    return (((A * x + B) * x + C) * x + D) * x
+
+
+@pytest.mark.parametrize("kind", ["config", "stress", "generic"])
+@pytest.mark.parametrize("project", [False, True])
+def test_device_quartic_fp64(ctx, kind, project):
+    print(f"[quartic fp64] {kind} project={project}", flush=True)
+    rng = np.random.default_rng({"config": 71, "stress": 72, "generic": 73}[kind])
+    N = 200_000
+    A, B, C, D, lo, hi = _random_quartics(rng, N, kind)
+    xo, co, mg = oracle.quartic_min(A, B, C, D, lo, hi, paper_project=project)
+    xg, cg = admm.admm_debug_quartic(ctx, A, B, C, D, lo, hi, paper_project=project, precision=admm.F64)
+    firm_b = (mg[:, 0] > 1e-10) & (mg[:, 1] > 1e-10)
+    firm_c = mg[:, 2] > 1e-12
+    assert np.all((cg // 3 == co // 3) | ~firm_b)
+    assert np.all((cg % 3 == co % 3) | ~firm_c)
+    cond = 1.0 / np.sqrt(np.clip(mg[:, 0], 1e-16, 1.0))
+    b3 = np.abs(B / (4 * A))
+    tol = 64 * 2.2e-16 * (1 + b3 + np.abs(xo)) * cond
+    ok = np.abs(xg - xo) <= tol
+    assert np.all(ok | ~(firm_b & firm_c)), np.abs(xg - xo)[~ok & firm_b & firm_c].max()
+    # the value is never worse than the oracle's beyond rounding
+    sc = np.abs(A) * xo ** 4 + np.abs(B) * np.abs(xo) ** 3 + np.abs(C) * xo ** 2 + np.abs(D) * np.abs(xo) + 1e-300
+    assert ((_f(A, B, C, D, xg) - _f(A, B, C, D, xo)) / sc).max() <= 1e-13
+
+
+@pytest.mark.parametrize("kind", ["config", "stress", "generic"])
+def test_device_quartic_mixed(ctx, kind):
+    print(f"[quartic mixed] {kind}", flush=True)
+    rng = np.random.default_rng({"config": 81, "stress": 82, "generic": 83}[kind])
+    N = 200_000
+    A, B, C, D, lo, hi = _random_quartics(rng, N, kind)
+    xo, co, mg = oracle.quartic_min(A, B, C, D, lo, hi)
+    xg, cg = admm.admm_debug_quartic(ctx, A, B, C, D, lo, hi, precision=admm.F32_MIXED)
+    firm_b = (mg[:, 0] > 1e-10) & (mg[:, 1] > 1e-10)
+    assert np.all((cg // 3 == co // 3) | ~firm_b)
+    err = np.abs(xg - xo) / (1 + np.abs(xo))
+    print(f"   max rel err {err[firm_b].max():.2e}  median {np.median(err):.2e}", flush=True)
+    assert err[firm_b].max() <= 1e-6
+    sc = np.abs(A) * xo ** 4 + np.abs(B) * np.abs(xo) ** 3 + np.abs(C) * xo ** 2 + np.abs(D) * np.abs(xo) + 1e-300
+    assert ((_f(A, B, C, D, xg) - _f(A, B, C, D, xo)) / sc).max() <= 1e-10
+
+
+def test_device_quartic_worked_examples(ctx):
+    import json, os
+    cases = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "quartic_worked.json")))["cases"]
+    for c in cases:
+        for project in (False, True):
+            for prec in (admm.F64, admm.F32_MIXED):
+                x, code = admm.admm_debug_quartic(ctx, np.array([c["A"]]), c["B"], c["C"], c["D"], c["lo"], c["hi"],
+                                                  paper_project=project, precision=prec)
+                key = "x_star_project" if project else "x_star"
+                want = [eval(c[key])]
+                tie = c["tie_project"] if project else c["tie_box"]
+                if tie:
+                    want.append(eval(c.get(key + "_alt", c.get("x_star_alt"))))
+                tol = 4e-15 if prec == admm.F64 else 1e-7
+                assert min(abs(float(x[0]) - w) for w in want) <= tol * 8, (c["name"], project, prec, x)

@@ -1,0 +1,166 @@
+"""Serving (admm_submit / admm_poll): continuous batching over the batched
+kernel.  Each served result equals the same instance solved by the batched
+path alone; with warm keys, results are the same whether the request
+streams run alone or interleaved with others."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_10041_amd import admm
+from paper_1903_10041_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def settings(**kw):
+    base = dict(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED, rho2_per_step=True)
+    base.update(kw)
+    return admm.Settings(**base)
+
+
+def wait(ctx, ticket, p, timeout=120.0):
+    t0 = time.time()
+    while True:
+        out = ctx.poll(ticket, p.m, p.n, p.q)
+        if out is not None:
+            return out
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"ticket {ticket} not done after {timeout}s")
+        time.sleep(0.0005)
+
+
+def requests(count, seed, n_hi=3000):
+    rng = np.random.default_rng(seed)
+    return [W.uniform_problem(int(rng.choice([2, 4])), int(np.exp(rng.uniform(np.log(50), np.log(n_hi)))),
+                              seed * 100 + r) for r in range(count)]
+
+
+def test_served_equals_batched_alone():
+    ctx = admm.Context(0, hbm_budget_bytes=2 << 30)
+    probs = requests(24, 401)
+    s = settings()
+    print("[serve] 24 concurrent requests", flush=True)
+    tickets = [ctx.submit(p, s) for p in probs]
+    outs = [wait(ctx, t, p) for t, p in zip(tickets, probs)]
+    for p, (x, inf) in zip(probs, outs):
+        xb, ib = ctx.solve_batch([p], s)
+        assert inf["status"] == admm.OK
+        assert np.array_equal(x, xb[0])
+        assert inf["iters"] == ib[0]["iters"]
+        st, oi, _ = oracle.run(p, max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, rho=(1.0, 1.0 / p.n, 1.0, 1.0))
+        assert abs(inf["objective"] - oi["objective"]) <= 1e-4 * (1 + abs(oi["objective"]))
+    ctx.close()
+
+
+def _run_streams(ctx, streams, s, interleave):
+    """Each stream's requests are sequential (the next one is submitted
+    when the previous is done, so its warm start is that result); streams
+    run interleaved or one after another."""
+    results = {}
+    if interleave:
+        pos = {k: 0 for k in streams}
+        live = {}
+        for k in streams:
+            live[k] = ctx.submit(streams[k][0], s, warm_key=k)
+        while live:
+            for k in list(live):
+                p = streams[k][pos[k]]
+                out = ctx.poll(live[k], p.m, p.n)
+                if out is None:
+                    continue
+                results[(k, pos[k])] = out
+                pos[k] += 1
+                if pos[k] < len(streams[k]):
+                    live[k] = ctx.submit(streams[k][pos[k]], s, warm_key=k)
+                else:
+                    del live[k]
+            time.sleep(0.0002)
+    else:
+        for k in streams:
+            for r, p in enumerate(streams[k]):
+                results[(k, r)] = wait(ctx, ctx.submit(p, s, warm_key=k), p)
+    return results
+
+
+def test_alone_vs_mix_with_warm_starts():
+    rng = np.random.default_rng(402)
+    streams = {}
+    for k in range(1, 6):
+        m = int(rng.choice([2, 4]))
+        streams[k] = [W.uniform_problem(m, int(rng.integers(100, 2000)), 4020 + 10 * k + r) for r in range(4)]
+    s = settings()
+    print("[serve] alone vs mix, 5 streams x 4 warm-started requests", flush=True)
+    ctx_a = admm.Context(0, hbm_budget_bytes=2 << 30)
+    alone = _run_streams(ctx_a, streams, s, interleave=False)
+    ctx_a.close()
+    ctx_b = admm.Context(0, hbm_budget_bytes=2 << 30)
+    mixed = _run_streams(ctx_b, streams, s, interleave=True)
+    ctx_b.close()
+    for key in alone:
+        xa, ia = alone[key]
+        xm, im = mixed[key]
+        assert ia["status"] == admm.OK
+        assert np.array_equal(xa, xm), key
+        assert ia["iters"] == im["iters"]
+
+
+def test_warm_start_reaches_same_optimum():
+    """A warm-started re-solve converges to the same optimum as a cold one."""
+    ctx = admm.Context(0, hbm_budget_bytes=1 << 30)
+    p1 = W.uniform_problem(4, 600, 4101)
+    p2 = W.uniform_problem(4, 600, 4102)
+    s = settings(precision=admm.F64, eps_primal=1e-7, eps_dual=1e-7)
+    wait(ctx, ctx.submit(p1, s, warm_key=7), p1)
+    xw, iw = wait(ctx, ctx.submit(p2, s, warm_key=7), p2)
+    xc, ic = wait(ctx, ctx.submit(p2, s), p2)
+    assert iw["status"] == admm.OK and ic["status"] == admm.OK
+    assert abs(iw["objective"] - ic["objective"]) <= 1e-6 * (1 + abs(ic["objective"]))
+    ctx.release_warm(7)
+    ctx.close()
+
+
+def test_poll_semantics_and_errors():
+    ctx = admm.Context(0, hbm_budget_bytes=256 << 20)
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.poll(12345, 2, 10)
+    assert e.value.status == admm.E_UNKNOWN_TICKET
+    p = W.uniform_problem(2, 200, 4201)
+    t = ctx.submit(p, settings())
+    x, inf = wait(ctx, t, p)
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.poll(t, p.m, p.n)
+    assert e.value.status == admm.E_UNKNOWN_TICKET
+    bad = W.uniform_problem(2, 50, 4202)
+    bad.f2[0, 0, 3] = -1.0
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.submit(bad, settings())
+    assert e.value.status == admm.E_INVALID_ARG
+    huge = W.uniform_problem(8, 2_000_000, 4203)
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.submit(huge, settings())
+    assert e.value.status == admm.E_OUT_OF_BUDGET
+    ctx.close()
+
+
+def test_submit_from_many_threads():
+    ctx = admm.Context(0, hbm_budget_bytes=2 << 30)
+    probs = requests(32, 403, n_hi=1500)
+    s = settings()
+    tickets = [None] * len(probs)
+
+    def go(lo, hi):
+        for i in range(lo, hi):
+            tickets[i] = ctx.submit(probs[i], s)
+
+    th = [threading.Thread(target=go, args=(i * 8, i * 8 + 8)) for i in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    outs = [wait(ctx, t, p) for t, p in zip(tickets, probs)]
+    assert len(set(tickets)) == len(tickets)
+    assert all(o[1]["status"] == admm.OK for o in outs)
+    ctx.close()
