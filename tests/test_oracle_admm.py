@@ -268,3 +268,46 @@ def test_branch_mix_on_stress():
     st, info, _ = oracle.run(p, max_iter=20, want_codes=True)
     br = np.bincount(info["codes"].ravel() // 3, minlength=5)
     assert br[oracle.TRIG_LO] + br[oracle.TRIG_HI] > 0
+
+
+# ------------------------------------------------------- adaptive rho (R12)
+
+def test_adaptive_rho_reaches_the_dual_reference_optimum():
+    for case in ("c1", "binding"):
+        p = W.small_c1() if case == "c1" else binding_c1()
+        st, info, _ = oracle.run(p, max_iter=200_000, eps_primal=1e-10, eps_dual=1e-10, adaptive_rho=True)
+        assert info["status"] == 0
+        _, obj_ref, _, _ = solve_nominal(p)
+        assert abs(info["objective"] - obj_ref) <= 1e-8 * (1 + abs(obj_ref))
+
+
+def test_adaptive_rho_step_is_a_rescaled_fixed_step():
+    """One check iteration with adaptation equals the same iteration at
+    fixed rho followed by rho <- f rho and (mu, lambda, nu, p) <- (.) / f,
+    with f = tau or 1/tau from the band test on r/sigma (Sec. IV-A)."""
+    p = W.phev_c4(seed=13, q=3, n=40)
+    st0, _, _ = oracle.run(p, max_iter=37)
+    eps_p, eps_d = 1e-12, 1e-11
+    a, ia, ha = oracle.run(p, max_iter=10, state=st0, eps_primal=eps_p, eps_dual=eps_d, adaptive_rho=True)
+    b, ib, hb = oracle.run(p, max_iter=10, state=st0, eps_primal=eps_p, eps_dual=eps_d)
+    r, sg = hb[-1, 1], hb[-1, 2]
+    ratio, target = r / sg, eps_p / eps_d
+    f = 1.1 if ratio > 1.2 * target else (1 / 1.1 if ratio < 0.8 * target else 1.0)
+    assert f != 1.0
+    assert np.allclose(ia["rho"], np.array(p.rho) * f, rtol=0, atol=0)
+    for k in ("x", "z", "s", "h", "xbar1"):
+        assert np.array_equal(a[k], b[k]), k
+    for k in ("mu", "lam", "p", "nu"):
+        assert np.array_equal(a[k], b[k] / f), k
+
+
+def test_rho2_scaled_by_horizon_converges_fast():
+    """With the capacity penalty rho_2 = rho_1 / n the iteration count stays
+    near a hundred at any horizon, and the optimum is unchanged."""
+    for m, n in ((2, 100), (5, 900), (8, 4000)):
+        p = W.uniform_problem(m, n, 7)
+        st, info, _ = oracle.run(p, max_iter=100000, eps_primal=1e-7, eps_dual=1e-7, rho=(1.0, 1.0 / n, 1.0, 1.0),
+                                 nthreads=4)
+        assert info["status"] == 0 and info["iters"] < 2000, (m, n, info["iters"])
+        _, obj_ref, _, _ = solve_nominal(p)
+        assert abs(info["objective"] - obj_ref) <= 1e-7 * (1 + abs(obj_ref))
