@@ -59,9 +59,9 @@ def run_gpu(args, precision_name):
     from paper_1903_10041_amd import admm
     from paper_1903_10041_amd import workloads as W
 
-    prec = admm.F32_MIXED if precision_name == "f32" else admm.F64
-    tdt = torch.float32 if precision_name == "f32" else torch.float64
-    word = 4 if precision_name == "f32" else 8
+    prec = {"f32": admm.F32, "mixed": admm.F32_MIXED, "f64": admm.F64}[precision_name]
+    tdt = torch.float64 if precision_name == "f64" else torch.float32
+    word = 8 if precision_name == "f64" else 4
     p = W.large_c2(n=args.n, m=args.m)
     pd = to_device(p, tdt)
     torch.cuda.synchronize()
@@ -94,19 +94,26 @@ def run_gpu(args, precision_name):
                        "bytes_per_launch": byts, "kernel": "k_sweep"}
 
     if not args.skip_converge:
-        eps = 1e-4 if precision_name == "f32" else 1e-6
-        s = admm.Settings(rho=p.rho, max_iter=args.converge_max_iter, eps_primal=eps, eps_dual=eps,
-                          precision=prec)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, info, _ = ctx.solve(pd, s)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        res["solve"] = {"residual": eps, "status": info["status"], "iters": info["iters"],
-                        "r": info["r"], "sigma": info["sigma"], "objective": info["objective"],
-                        "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
+        eps = 1e-6 if precision_name == "f64" else 1e-4
+        res["solve"] = {}
+        for tag, r2, cap in (("rho1", False, args.converge_max_iter), ("rho2_per_step", True, 100000)):
+            s = admm.Settings(rho=p.rho, max_iter=cap, eps_primal=eps, eps_dual=eps,
+                              precision=prec, rho2_per_step=r2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info, _ = ctx.solve(pd, s)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            res["solve"][tag] = {"residual": eps, "status": info["status"], "iters": info["iters"],
+                                 "r": info["r"], "sigma": info["sigma"], "objective": info["objective"],
+                                 "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
     ctx.close()
     return res
+
+
+def _prec(args):
+    from paper_1903_10041_amd import admm
+    return {"f32": admm.F32, "mixed": admm.F32_MIXED, "f64": admm.F64}[args.precision]
 
 
 def _device_problem(p, dtype):
@@ -124,7 +131,7 @@ def run_batch(args):
     dp = [_device_problem(p, torch.float32) for p in probs]
     torch.cuda.synchronize()
     ctx = admm.Context(0, hbm_budget_bytes=16 << 30)
-    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=_prec(args),
                       rho2_per_step=True)
     ctx.solve_batch(dp[:64], s)                     # warm-up (code objects, buffers)
     torch.cuda.synchronize()
@@ -177,7 +184,7 @@ def run_serve(args):
     gaps = rng.exponential(1.0 / args.serve_rate, size=nreq)
     keys = rng.integers(1, 257, size=nreq)
     ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
-    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=_prec(args),
                       rho2_per_step=True)
     # warm-up
     for p in pool[:8]:
@@ -247,8 +254,8 @@ def run_robust(args):
     out = {"workload": "m=2 q=200 n=3600 robust scenario program, f32 storage, residual 1e-4"}
     for tag, r2 in (("rho1", False), ("rho2_per_step", True)):
         s = admm.Settings(max_iter=args.robust_max_iter, eps_primal=1e-4, eps_dual=1e-4,
-                          precision=admm.F32_MIXED, rho2_per_step=r2)
-        ctx.solve(pd, admm.Settings(max_iter=50, eps_primal=0, eps_dual=0, precision=admm.F32_MIXED))
+                          precision=_prec(args), rho2_per_step=r2)
+        ctx.solve(pd, admm.Settings(max_iter=50, eps_primal=0, eps_dual=0, precision=_prec(args)))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, info, _ = ctx.solve(pd, s)
@@ -284,7 +291,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--precision", choices=["f32", "mixed", "f64"], default="mixed")
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--m", type=int, default=4)
     ap.add_argument("--profile-iters", type=int, default=400)
@@ -301,8 +308,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=384)
     ap.add_argument("--robust-max-iter", type=int, default=100000)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="first copy a buffer of this many MiB 3 times (a plain copy kernel of known "
-                         "size, to scale hardware byte counters)")
+                    help="first run the library's plain copy kernel (k_copy_calib) 3 times over this "
+                         "many MiB, to scale hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -314,21 +321,20 @@ def main():
     if not os.path.exists(hb.LIB):
         hb.build()
     if args.copy_calibration_mib:
-        import torch
-        nb = args.copy_calibration_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        from paper_1903_10041_amd import admm
+        cctx = admm.Context(0)
+        admm.admm_debug_copy(cctx, args.copy_calibration_mib << 20, 3)
+        cctx.close()
     head = run_gpu(args, args.precision)
-    other = "f64" if args.precision == "f32" else "f32"
-    variant = None
+    variants = {}
     if not args.skip_variant:
-        a2 = argparse.Namespace(**vars(args))
-        a2.steps = max(100, args.steps // 2)
-        variant = run_gpu(a2, other)
+        for other in ("f32", "mixed", "f64"):
+            if other == args.precision:
+                continue
+            a2 = argparse.Namespace(**vars(args))
+            a2.steps = max(100, args.steps // 2)
+            a2.converge_max_iter = min(args.converge_max_iter, 100000)
+            variants[other] = run_gpu(a2, other)
     extras = {}
     if not args.skip_extras:
         extras["batched"] = run_batch(args)
@@ -336,7 +342,10 @@ def main():
         extras["robust"] = run_robust(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
-    storage = {"f32": "f32 storage, f64 arithmetic", "f64": "f64"}
+    storage = {"f32": "f32 storage and x-step arithmetic, f64 reductions",
+               "mixed": "f32 storage and closed form, f64 assembly and Newton polish",
+               "f64": "f64"}
+    dtype = {"f32": "f32", "mixed": "f32+f64", "f64": "f64"}[args.precision]
     line = {
         "metric": METRIC,
         "value": head["iters_per_s"],
@@ -348,7 +357,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"plain single instance m={args.m} n={args.n} q=1 rho=1, "
                                f"{args.precision} path ({storage[args.precision]}), residual check every 10",
@@ -357,7 +366,7 @@ def main():
         "cpu_baseline": cpu,
         "kernel_us": head["kernel_us"],
         "solve": head.get("solve"),
-        "variants": {other: variant} if variant else None,
+        "variants": variants or None,
     }
     line.update(extras)
     print(json.dumps(line), flush=True)

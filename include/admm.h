@@ -59,7 +59,14 @@ typedef enum {
     ADMM_E_UNSUPPORTED = -7      /* valid request outside what this build supports */
 } admm_status;
 
-typedef enum { ADMM_F64 = 0, ADMM_F32_MIXED = 1 } admm_precision;
+/* Arithmetic of the iteration.  ADMM_F64: everything in FP64.
+ * ADMM_F32_MIXED: FP32 storage; the x-step closed form in FP32 followed by
+ * one FP64 Newton step; FP64 coefficient assembly, reductions and scalars.
+ * ADMM_F32: FP32 storage, x-step assembly and closed form in FP32, no
+ * polish; FP64 reductions and scalars.  Both FP32 modes fall back to the
+ * FP64 closed form near repeated roots and for three real roots.  Device
+ * arrays of a problem are double for ADMM_F64 and float otherwise. */
+typedef enum { ADMM_F64 = 0, ADMM_F32_MIXED = 1, ADMM_F32 = 2 } admm_precision;
 
 /* Box semantics of the x-step (7a).  EXACT_BOX minimises the quartic over
  * the box, i.e. over L with the box indicator, comparing the quartic at the
@@ -210,6 +217,11 @@ admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const double *A, co
                                const double *C, const double *D, const double *lo, const double *hi,
                                int32_t paper_project, int32_t precision, double *x_out,
                                int32_t *codes_out);
+
+/* Measurement hook: a plain copy kernel (k_copy_calib) over `bytes` of
+ * device memory, `reps` times, on freshly allocated buffers; the reference
+ * of known size for scaling hardware byte counters. */
+admm_status admm_debug_copy(admm_context *ctx, size_t bytes, int32_t reps);
 
 void admm_destroy(admm_context *ctx);
 const char *admm_status_string(admm_status s);

@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libadmm.so")
 OK, NOT_READY, MAX_ITER = 0, 1, 2
 E_INVALID_ARG, E_OUT_OF_BUDGET, E_DEVICE, E_NUMERICAL = -1, -2, -3, -4
 E_UNKNOWN_TICKET, E_QUEUE_FULL, E_UNSUPPORTED = -5, -6, -7
-F64, F32_MIXED = 0, 1
+F64, F32_MIXED, F32 = 0, 1, 2
 XSTEP_EXACT_BOX, XSTEP_PAPER_PROJECT = 0, 1
 SWEEP_GAUSS_SEIDEL, SWEEP_JACOBI = 0, 1
 HOST, DEVICE = 0, 1
@@ -99,6 +99,7 @@ def lib():
             "admm_debug_codes": (C.c_int, [vp, vp, vp]),
             "admm_profile": (C.c_int, [vp, vp, vp, i32, vp]),
             "admm_debug_quartic": (C.c_int, [vp, C.c_int64] + [vp] * 6 + [i32, i32, vp, vp]),
+            "admm_debug_copy": (C.c_int, [vp, C.c_size_t, i32]),
         }
         for name, (res, args) in sigs.items():
             fn = getattr(L, name)
@@ -366,6 +367,11 @@ def admm_debug_quartic(ctx: "Context", A, B, Cc, D, lo, hi, paper_project=False,
     _check(lib().admm_debug_quartic(ctx.h, N, *[a.ctypes.data for a in arrs], int(paper_project),
                                     int(precision), x.ctypes.data, codes.ctypes.data), allow=(OK,))
     return x.reshape(np.shape(A)), codes.reshape(np.shape(A))
+
+
+def admm_debug_copy(ctx: "Context", nbytes: int, reps: int = 3):
+    """Plain device copy kernel of known size (counter calibration)."""
+    _check(lib().admm_debug_copy(ctx.h, int(nbytes), int(reps)), allow=(OK,))
 
 
 def admm_create(device: int = 0, hbm_budget_bytes: int = 0, defaults: Optional[Settings] = None) -> Context:

@@ -82,7 +82,7 @@ static int batch_grid(admm_context *ctx, K kernel, int count) {
     return std::max(1, std::min(count, nb * std::max(1, ctx->num_cu)));
 }
 
-template <typename T, bool MIXED>
+template <typename T, int MIXED>
 static hipError_t launch_batch_class(admm_context *ctx, int cls, const BatchParams &B, bool init, hipStream_t s) {
     if (B.count == 0) return hipSuccess;
     if (cls == 0) {
@@ -99,8 +99,9 @@ static hipError_t launch_batch_class(admm_context *ctx, int cls, const BatchPara
 }
 
 hipError_t launch_batch(admm_context *ctx, int dtype, int cls, const BatchParams &B, bool init, hipStream_t s) {
-    return dtype == 0 ? launch_batch_class<double, false>(ctx, cls, B, init, s)
-                      : launch_batch_class<float, true>(ctx, cls, B, init, s);
+    if (dtype == 0) return launch_batch_class<double, MODE_F64>(ctx, cls, B, init, s);
+    if (dtype == 1) return launch_batch_class<float, MODE_MIXED>(ctx, cls, B, init, s);
+    return launch_batch_class<float, MODE_F32>(ctx, cls, B, init, s);
 }
 
 int batch_class(int m) { return m <= 2 ? 0 : (m <= 4 ? 1 : 2); }
@@ -161,7 +162,7 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
     BatchState *bs = nullptr;
     admm_status st = batch_state(ctx, bs);
     if (st != ADMM_OK) return st;
-    const int dtype = S.precision == ADMM_F64 ? 0 : 1;
+    const int dtype = (int)S.precision;
     const size_t T = dtype == 0 ? 8 : 4;
     const admm_problem &p0 = probs[idx[0]];
     const bool host = p0.mem == ADMM_HOST;
@@ -976,7 +977,7 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     if (prob->mem != ADMM_HOST) return fail(ADMM_E_UNSUPPORTED, "admm_submit takes host arrays");
     if (!batchable(*prob))
         return fail(ADMM_E_UNSUPPORTED, "admm_submit serves q = 1 instances with per-source bounds and no g0/f0");
-    const int dtype = S.precision == ADMM_F64 ? 0 : 1;
+    const int dtype = (int)S.precision;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         if ((st = serve_start(ctx, dtype)) != ADMM_OK) return st;

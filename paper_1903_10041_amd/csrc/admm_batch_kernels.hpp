@@ -130,7 +130,7 @@ __device__ __forceinline__ void block_max_rows(int rows, const double *v, double
     __syncthreads();
 }
 
-template <typename T, int MAXM, bool MIXED>
+template <typename T, int MAXM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
     __shared__ double lds[MAXM + 2][kBlock];
     __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM];
@@ -184,14 +184,14 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
                 for (int k = tid; k < n; k += kBlock) {
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
-                    col_update<T, MAXM, MIXED, true>(P, 0, k, d, sc, acc);
+                    col_update<T, MAXM, MODE, true>(P, 0, k, d, sc, acc);
                     col_store(P, 0, k, d);
                 }
             } else {
                 for (int k = tid; k < n; k += kBlock) {
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
-                    col_update<T, MAXM, MIXED, false>(P, 0, k, d, sc, acc);
+                    col_update<T, MAXM, MODE, false>(P, 0, k, d, sc, acc);
                     col_store(P, 0, k, d);
                 }
             }

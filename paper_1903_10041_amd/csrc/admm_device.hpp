@@ -52,10 +52,29 @@ __device__ __forceinline__ double st_round(double v) { return (double)(T)v; }
 //   A = rho1 g2^2 / 2, B = rho1 g2 g1,
 //   C = f2/q + rho1 (g1^2/2 - g2 (theta - g0)) + rho3/2 [+ rho4/2 at k = 1],
 //   D = f1/q - rho1 g1 (theta - g0) - rho3 phi [- rho4 (x_1 + nu) at k = 1].
-template <bool MIXED>
+// Arithmetic of the x-step: FP64; FP32 closed form with an FP64 Newton
+// polish (mixed); FP32 assembly and closed form (f32).  The last two fall
+// back to the FP64 closed form near repeated roots and for three real roots.
+enum { MODE_F64 = 0, MODE_MIXED = 1, MODE_F32 = 2 };
+
+template <int MODE>
 __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double f1, double g2, double g1,
                                         double tg, double phi, bool first_step, double cons,
                                         double lo, double hi, int &code) {
+    if (MODE == MODE_F32) {
+        const float r1 = (float)P.rho1, r3 = (float)P.rho3;
+        const float g2f = (float)g2, g1f = (float)g1, tgf = (float)tg;
+        const float A = 0.5f * r1 * g2f * g2f;
+        const float B = r1 * g2f * g1f;
+        float C = (float)f2 * (float)P.inv_q + r1 * (0.5f * g1f * g1f - g2f * tgf) + 0.5f * r3;
+        float D = (float)f1 * (float)P.inv_q - r1 * g1f * tgf - r3 * (float)phi;
+        if (first_step) {
+            C += 0.5f * (float)P.rho4;
+            D -= (float)P.rho4 * (float)cons;
+        }
+        double x;
+        if (qmin_f32_fast(A, B, C, D, (float)lo, (float)hi, x, code)) return x;
+    }
     const double A = 0.5 * P.rho1 * g2 * g2;
     const double B = P.rho1 * g2 * g1;
     double C = f2 * P.inv_q + P.rho1 * (0.5 * g1 * g1 - g2 * tg) + 0.5 * P.rho3;
@@ -64,7 +83,12 @@ __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double 
         C += 0.5 * P.rho4;
         D -= P.rho4 * cons;
     }
-    if (MIXED) return qmin_mixed(A, B, C, D, lo, hi, P.xstep_project, code);
+    if (MODE == MODE_MIXED) return qmin_mixed(A, B, C, D, lo, hi, P.xstep_project, code);
+    if (MODE == MODE_F32) {
+        const QRes r = qmin_f64_call(A, B, C, D, lo, hi, P.xstep_project);
+        code = r.code;
+        return r.x;
+    }
     return qmin_f64(A, B, C, D, lo, hi, P.xstep_project, code);
 }
 
@@ -164,7 +188,7 @@ struct Acc {
 // One column: the x-step (7a) for every source in turn (Gauss-Seidel, or
 // Jacobi by flag), then the s- and mu-steps (7e)-(7f) through w = s - mu,
 // accumulating sum_k g(x_k) per source and the residual trackers.
-template <typename T, int MAXM, bool MIXED, bool CHECK>
+template <typename T, int MAXM, int MODE, bool CHECK>
 __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, Col<T, MAXM> &d,
                                            const Scal<MAXM> &sc, Acc<MAXM> &acc) {
     const int m = P.m;
@@ -203,7 +227,7 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
                 if (l < m && l != i) others += P.jacobi ? xo[l] : xc[l];
             const double phi = sm - others + y;
             int code;
-            const double xn = st_round<T>(xstep<MIXED>(P, f2, f1, g2, g1, theta - g0, phi,
+            const double xn = st_round<T>(xstep<MODE>(P, f2, f1, g2, g1, theta - g0, phi,
                                                        P.consensus && k == 0, sc.cons[i], lo, hi, code));
             xc[i] = xn;
             d.x[i] = (T)xn;

@@ -60,7 +60,8 @@ struct admm_context {
     int gdtype = -1, gchunk = 0;
     bool coop = false;              // cooperative launch supported
     int num_cu = 0;
-    int persist_cap[2][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+    int persist_cap[3][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
+                                {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
                                 {{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}}};
     admm::BatchState *batch = nullptr;
     admm::ServeState *serve = nullptr;

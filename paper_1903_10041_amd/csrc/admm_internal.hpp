@@ -82,6 +82,7 @@ hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, cons
 const void *persist_kernel(int dtype, int m, int R);
 hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int chunk, uint32_t spin_limit,
                           hipStream_t s);
+hipError_t launch_copy_calib(const void *src, void *dst, size_t bytes, hipStream_t s);
 int max_m_supported();
 
 }  // namespace admm

@@ -20,6 +20,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 
 namespace admm {
@@ -27,8 +28,10 @@ namespace admm {
 // Streaming sweep (graph path): one thread owns CPT columns of tile
 // (j, blockIdx.x), k = blockIdx.x * CPT * 256 + c * 256 + tid.  CHECK
 // selects the variant that also tracks the residual terms; it is used only
-// on check iterations.
-template <typename T, int MAXM, int CPT, bool MIXED, bool CHECK>
+// on check iterations.  FUSED: the last block to finish (an atomic count of
+// finished blocks, with release/acquire fences around it) runs the scalar
+// steps, so one launch is a whole iteration.
+template <typename T, int MAXM, int CPT, int MODE, bool CHECK, bool FUSED>
 __global__ __launch_bounds__(kBlock) void k_sweep(SolveParams P) {
     Ctrl *ctrl = P.ctrl;
     if (ctrl->done) return;
@@ -48,22 +51,43 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SolveParams P) {
         if (k < P.n) {
             Col<T, MAXM> d;
             col_load(P, j, k, d);
-            col_update<T, MAXM, MIXED, CHECK>(P, j, k, d, sc, acc);
+            col_update<T, MAXM, MODE, CHECK>(P, j, k, d, sc, acc);
             col_store(P, j, k, d);
         }
     }
     __shared__ double lds[MAXM + 2][kBlock];
     block_partials<MAXM>(P, (size_t)j * P.nblk + blockIdx.x, acc, CHECK, lds);
+    if (FUSED) {
+        __shared__ int last;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const uint32_t total = (uint32_t)(gridDim.x * gridDim.y);
+            last = __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == total - 1;
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            finalize_body(P);
+            if (threadIdx.x == 0) __hip_atomic_store(P.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // Element-wise quartic minimiser (parity tests of the device math).
-template <bool MIXED>
+template <int MODE>
 __global__ void k_quartic(int64_t N, const double *A, const double *B, const double *C, const double *D,
                           const double *lo, const double *hi, int project, double *x, int32_t *codes) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
         int code;
-        const double v = MIXED ? qmin_mixed(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code)
-                               : qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        double v;
+        if (MODE == MODE_MIXED) {
+            v = qmin_mixed(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        } else if (MODE == MODE_F32) {
+            if (!qmin_f32_fast((float)A[e], (float)B[e], (float)C[e], (float)D[e], (float)lo[e], (float)hi[e], v, code))
+                v = qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        } else {
+            v = qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        }
         x[e] = v;
         codes[e] = code;
     }
@@ -127,7 +151,7 @@ __device__ __forceinline__ bool grid_wait(uint32_t *bar, uint32_t target, uint32
 // thread kept in registers across iterations; each iteration ends in a grid
 // barrier whose last arriving block runs the scalar steps.  Launched
 // cooperatively (all blocks resident) for at most `chunk` iterations.
-template <typename T, int MAXM, int R, bool MIXED>
+template <typename T, int MAXM, int R, int MIXED>
 __global__ __launch_bounds__(kBlock) void k_persist(SolveParams P, uint32_t *bar, int chunk, uint32_t spin_limit) {
     const int tile = blockIdx.x;
     const int j = tile / P.nblk, kb = tile - j * P.nblk;
@@ -403,24 +427,51 @@ __global__ __launch_bounds__(kBlock) void k_obj_final(SolveParams P, const doubl
     }
 }
 
+// Plain copy of known size (reads and writes `n16` 16-byte words once):
+// the reference for scaling hardware byte counters.
+__global__ __launch_bounds__(kBlock) void k_copy_calib(const float4 *src, float4 *dst, size_t n16) {
+    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n16; i += (size_t)gridDim.x * kBlock)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_calib(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    k_copy_calib<<<2048, kBlock, 0, s>>>((const float4 *)src, (float4 *)dst, n16);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ launchers
 
 int max_m_supported() { return 8; }
 
-template <typename T, bool MIXED, int CPT, bool CHECK>
+template <typename T, int MODE, int CPT, bool CHECK, bool FUSED>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (P.m <= 2) k_sweep<T, 2, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
-    else if (P.m <= 4) k_sweep<T, 4, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
-    else k_sweep<T, 8, CPT, MIXED, CHECK><<<grid, kBlock, 0, s>>>(P);
+    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
+    else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
+    else k_sweep<T, 8, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
 }
 
-template <typename T, bool MIXED, bool CHECK>
+template <typename T, int MODE, bool CHECK, bool FUSED>
 static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
     switch (P.cpt) {
-    case 1: launch_sweep_c<T, MIXED, 1, CHECK>(P, s); break;
-    case 2: launch_sweep_c<T, MIXED, 2, CHECK>(P, s); break;
-    default: launch_sweep_c<T, MIXED, 4, CHECK>(P, s); break;
+    case 1: launch_sweep_c<T, MODE, 1, CHECK, FUSED>(P, s); break;
+    case 2: launch_sweep_c<T, MODE, 2, CHECK, FUSED>(P, s); break;
+    default: launch_sweep_c<T, MODE, 4, CHECK, FUSED>(P, s); break;
+    }
+}
+
+template <bool FUSED>
+static void launch_sweep_f(const SolveParams &P, int dtype, bool check, hipStream_t s) {
+    if (dtype == 0) {
+        if (check) launch_sweep_k<double, MODE_F64, true, FUSED>(P, s);
+        else launch_sweep_k<double, MODE_F64, false, FUSED>(P, s);
+    } else if (dtype == 1) {
+        if (check) launch_sweep_k<float, MODE_MIXED, true, FUSED>(P, s);
+        else launch_sweep_k<float, MODE_MIXED, false, FUSED>(P, s);
+    } else {
+        if (check) launch_sweep_k<float, MODE_F32, true, FUSED>(P, s);
+        else launch_sweep_k<float, MODE_F32, false, FUSED>(P, s);
     }
 }
 
@@ -428,13 +479,12 @@ static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
 // iteration (the caller knows the iteration number: graphs are captured
 // in chunks that start at a multiple of check_every).
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s) {
-    if (dtype == 0) {
-        if (check) launch_sweep_k<double, false, true>(P, s);
-        else launch_sweep_k<double, false, false>(P, s);
-    } else {
-        if (check) launch_sweep_k<float, true, true>(P, s);
-        else launch_sweep_k<float, true, false>(P, s);
-    }
+    launch_sweep_f<false>(P, dtype, check, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_fused(const SolveParams &P, int dtype, bool check, hipStream_t s) {
+    launch_sweep_f<true>(P, dtype, check, s);
     return hipGetLastError();
 }
 
@@ -444,17 +494,18 @@ hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, cons
     int64_t g = (N + kBlock - 1) / kBlock;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
-    if (mixed) k_quartic<true><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
-    else k_quartic<false><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    if (mixed == 1) k_quartic<MODE_MIXED><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    else if (mixed == 2) k_quartic<MODE_F32><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    else k_quartic<MODE_F64><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
     return hipGetLastError();
 }
 
-template <typename T, int MAXM, int R, bool MIXED>
+template <typename T, int MAXM, int R, int MIXED>
 static const void *persist_fn() {
     return (const void *)k_persist<T, MAXM, R, MIXED>;
 }
 
-template <typename T, bool MIXED>
+template <typename T, int MIXED>
 static const void *persist_fn_m(int m, int R) {
     if (m <= 2) return R == 1 ? persist_fn<T, 2, 1, MIXED>() : R == 2 ? persist_fn<T, 2, 2, MIXED>() : persist_fn<T, 2, 4, MIXED>();
     if (m <= 4) return R == 1 ? persist_fn<T, 4, 1, MIXED>() : R == 2 ? persist_fn<T, 4, 2, MIXED>() : persist_fn<T, 4, 4, MIXED>();
@@ -462,7 +513,8 @@ static const void *persist_fn_m(int m, int R) {
 }
 
 const void *persist_kernel(int dtype, int m, int R) {
-    return dtype == 0 ? persist_fn_m<double, false>(m, R) : persist_fn_m<float, true>(m, R);
+    return dtype == 0 ? persist_fn_m<double, MODE_F64>(m, R)
+                      : (dtype == 1 ? persist_fn_m<float, MODE_MIXED>(m, R) : persist_fn_m<float, MODE_F32>(m, R));
 }
 
 hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int chunk, uint32_t spin_limit,
@@ -478,7 +530,16 @@ hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
     return hipGetLastError();
 }
 
+// One iteration: sweep + finalize launches (default), or the fused sweep
+// whose last block runs the scalar steps (ADMM_FUSED=1).  On MI355X the
+// fused form is slower: every block's release fence writes back its XCD's
+// dirty L2 lines (the sweep's x and w) before the arrival atomic.
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s) {
+    static const bool fused = [] {
+        const char *e = std::getenv("ADMM_FUSED");
+        return e && e[0] == '1';
+    }();
+    if (fused) return launch_sweep_fused(P, dtype, check, s);
     hipError_t e = launch_sweep(P, dtype, check, s);
     if (e != hipSuccess) return e;
     return launch_finalize(P, s);
@@ -522,6 +583,7 @@ hipError_t launch_pack(const SolveParams &P, int dtype, int src_dtype, const voi
                        const void *f1, const void *g2, const void *g1, const void *g0,
                        const void *f0, const void *y, const void *blo, const void *bhi,
                        void *g0d, void *f0d, void *yd, void *blod, void *bhid, hipStream_t s) {
+    dtype = dtype == 0 ? 0 : 1;   // storage type: double for F64, float otherwise
     if (dtype == 0 && src_dtype == 0)
         return launch_pack_ts<double, double>(P, f2, f1, g2, g1, g0, f0, y, blo, bhi, g0d, f0d, yd, blod, bhid, s);
     if (dtype == 1 && src_dtype == 0)

@@ -180,4 +180,35 @@ __device__ __forceinline__ double qmin_mixed(double A, double B, double C, doubl
     return r.x;
 }
 
+// FP32 closed form without polish: returns false (and leaves x unset) when
+// the FP32 branch test is not clear of the boundary or the quartic has three
+// real roots, so the caller falls back to FP64.
+__device__ __forceinline__ bool qmin_f32_fast(float A, float B, float C, float D, float lo, float hi,
+                                              double &x, int &code) {
+    float u;
+    if (A == 0.0f) {
+        u = -0.5f * D * rcp32(C);
+        code = 3 * BR_QUAD;
+    } else {
+        const float ia = rcp32(A);
+        const float b3 = 0.25f * B * ia;
+        const float c = 0.5f * C * ia;
+        const float d = 0.25f * D * ia;
+        const float Q = c * (1.0f / 3.0f) - b3 * b3;
+        const float R = 0.5f * (b3 * c - d) - b3 * b3 * b3;
+        const float Q3 = Q * Q * Q;
+        const float R2 = R * R;
+        const float Delta = Q3 + R2;
+        if (!(Delta > kMixedDeltaMargin * (fabsf(Q3) + R2))) return false;
+        const float sq = __builtin_sqrtf(Delta);
+        const float S = cbrt32(R + copysignf(sq, R));
+        const float T = (S != 0.0f) ? -Q * rcp32(S) : 0.0f;
+        u = S + T - b3;
+        code = 3 * BR_CARDANO;
+    }
+    code += (u < lo ? CL_LO : (u > hi ? CL_HI : CL_INTERIOR));
+    x = (double)(u < lo ? lo : (u > hi ? hi : u));
+    return true;
+}
+
 }  // namespace admm

@@ -84,7 +84,7 @@ admm_status validate_settings(const admm_settings *s) {
         return fail(ADMM_E_INVALID_ARG, "eps_primal and eps_dual must be >= 0");
     if (s->max_iter < 0) return fail(ADMM_E_INVALID_ARG, "max_iter must be >= 0");
     if (s->check_every < 1) return fail(ADMM_E_INVALID_ARG, "check_every must be >= 1");
-    if (s->precision != ADMM_F64 && s->precision != ADMM_F32_MIXED)
+    if (s->precision != ADMM_F64 && s->precision != ADMM_F32_MIXED && s->precision != ADMM_F32)
         return fail(ADMM_E_INVALID_ARG, "unknown precision");
     if (s->xstep != ADMM_XSTEP_EXACT_BOX && s->xstep != ADMM_XSTEP_PAPER_PROJECT)
         return fail(ADMM_E_INVALID_ARG, "unknown xstep");
@@ -102,7 +102,7 @@ admm_status validate_problem_shape(const admm_problem *p) {
     if (!p->f2 || !p->f1 || !p->g2 || !p->g1 || !p->x_lo || !p->x_hi || !p->y || !p->c)
         return fail(ADMM_E_INVALID_ARG, "f2, f1, g2, g1, x_lo, x_hi, y and c are required");
     if (p->mem != ADMM_HOST && p->mem != ADMM_DEVICE) return fail(ADMM_E_INVALID_ARG, "unknown memspace");
-    if (p->mem == ADMM_DEVICE && p->dtype != ADMM_F64 && p->dtype != ADMM_F32_MIXED)
+    if (p->mem == ADMM_DEVICE && p->dtype != ADMM_F64 && p->dtype != ADMM_F32_MIXED && p->dtype != ADMM_F32)
         return fail(ADMM_E_INVALID_ARG, "unknown dtype");
     if (p->bounds != ADMM_BOUNDS_PER_SOURCE && p->bounds != ADMM_BOUNDS_PER_STEP)
         return fail(ADMM_E_INVALID_ARG, "unknown bounds layout");
@@ -299,7 +299,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
                     int &dtype) {
     Workspace &W = ctx->ws;
     Arena &A = ctx->arena;
-    dtype = s->precision == ADMM_F64 ? 0 : 1;
+    dtype = (int)s->precision;   // 0 F64, 1 F32_MIXED, 2 F32 (float storage for 1 and 2)
     const size_t T = dtype == 0 ? 8 : 4;
     std::memset(&P, 0, sizeof P);
     const int m = pr->m, n = pr->n, q = pr->q;
@@ -378,7 +378,7 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
                 if (!std::isfinite(slo[i]) || !std::isfinite(shi[i]) || slo[i] > shi[i])
                     return fail(ADMM_E_INVALID_ARG, "bounds must be finite with x_lo <= x_hi");
         }
-        if (dtype == 1)
+        if (dtype != 0)
             for (int i = 0; i < m; ++i) { slo[i] = (double)(float)slo[i]; shi[i] = (double)(float)shi[i]; }
     } else {
         std::fill(slo.begin(), slo.end(), 0.0);
@@ -389,7 +389,7 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
     std::memcpy(hb.data() + m, shi.data(), m * sizeof(double));
     std::memcpy(hb.data() + 2 * m, pr->c, m * sizeof(double));
     HIPCHK(hipMemcpyAsync((void *)P.slo, hb.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl), s));
+    HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl) + 16, s));
 
     const void *f2 = pr->f2, *f1 = pr->f1, *g2 = pr->g2, *g1 = pr->g1, *g0 = pr->g0, *f0 = pr->f0;
     const void *y = pr->y, *blo = nullptr, *bhi = nullptr;
@@ -847,5 +847,25 @@ extern "C" admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const do
     HIPCHK(hipMemcpyAsync(x_out, xd, N * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(codes_out, cd, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return ADMM_OK;
+}
+
+// Plain copy kernel over `bytes` (multiple of 16) repeated `reps` times:
+// the reference for scaling hardware byte counters (FETCH_SIZE/WRITE_SIZE).
+extern "C" admm_status admm_debug_copy(admm_context *ctx, size_t bytes, int32_t reps) {
+    if (!ctx || bytes < 16 || reps < 1) return fail(ADMM_E_INVALID_ARG, "bad copy size");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    bytes &= ~size_t(15);
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, bytes) != hipSuccess) return fail(ADMM_E_DEVICE, "hipMalloc failed");
+    if (hipMalloc(&b, bytes) != hipSuccess) { (void)hipFree(a); return fail(ADMM_E_DEVICE, "hipMalloc failed"); }
+    hipStream_t s = ctx->own;
+    hipError_t e = hipMemsetAsync(a, 0, bytes, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy_calib(a, b, bytes, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(ADMM_E_DEVICE, hipGetErrorString(e));
     return ADMM_OK;
 }

@@ -74,9 +74,10 @@ def test_batch_result_independent_of_the_mix(ctx):
         assert ia[0]["objective"] == infos[b]["objective"]
 
 
-def test_batch_fp32_mixed(ctx):
+@pytest.mark.parametrize("prec", [admm.F32_MIXED, admm.F32])
+def test_batch_fp32(ctx, prec):
     probs = mixed_batch(count=24, seed=303, n_hi=300)
-    s = admm.Settings(max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED)
+    s = admm.Settings(max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=prec)
     print("[batch fp32] 24 instances to 1e-4", flush=True)
     xs, infos = ctx.solve_batch(probs, s)
     for p, x, inf in zip(probs, xs, infos):

@@ -200,11 +200,12 @@ def test_full_size_large_case_parity(ctx):
     assert dx <= 1e-9 and rel <= 1e-10
 
 
-def test_fp32_mixed_objective(ctx):
-    for name in ("c1", "c1_binding", "ragged_n1000_m5"):
+@pytest.mark.parametrize("prec", [admm.F32_MIXED, admm.F32])
+def test_fp32_objective(ctx, prec):
+    for name in ("c1", "c1_binding", "ragged_n1000_m5", "robust_q5_n60", "stress"):
         p = CASES[name]()
         say(f"[fp32] {name}")
-        s = admm.Settings(rho=tuple(p.rho), max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED)
+        s = admm.Settings(rho=tuple(p.rho), max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=prec)
         x, info, _ = ctx.solve(p, s)
         st, oinfo, _ = oracle.run(p, max_iter=100000, eps_primal=1e-4, eps_dual=1e-4)
         rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))

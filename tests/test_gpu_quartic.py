@@ -77,3 +77,23 @@ def test_device_quartic_worked_examples(ctx):
                     want.append(eval(c.get(key + "_alt", c.get("x_star_alt"))))
                 tol = 4e-15 if prec == admm.F64 else 1e-7
                 assert min(abs(float(x[0]) - w) for w in want) <= tol * 8, (c["name"], project, prec, x)
+
+
+@pytest.mark.parametrize("kind", ["config", "stress", "generic"])
+def test_device_quartic_f32(ctx, kind):
+    """FP32 closed form (no polish) with FP64 fallback: the minimiser to
+    FP32 accuracy, the branch exact outside the tie margins."""
+    rng = np.random.default_rng({"config": 91, "stress": 92, "generic": 93}[kind])
+    N = 200_000
+    A, B, C, D, lo, hi = _random_quartics(rng, N, kind)
+    xo, co, mg = oracle.quartic_min(A, B, C, D, lo, hi)
+    xg, cg = admm.admm_debug_quartic(ctx, A, B, C, D, lo, hi, precision=admm.F32)
+    firm_b = (mg[:, 0] > 1e-4) & (mg[:, 1] > 1e-6)
+    assert np.all((cg // 3 == co // 3) | ~firm_b)
+    # error bound of the FP32 closed form: rounding of b/3, c, d (~1e-7
+    # relative) amplified by the spread of the root terms
+    b3 = np.abs(B / (4 * A))
+    err = np.abs(xg - xo)
+    tol = 2e-5 * (1 + np.abs(xo) + b3)
+    print(f"   max err/tol {np.max(err[firm_b] / tol[firm_b]):.3f}", flush=True)
+    assert np.all((err <= tol) | ~firm_b)
