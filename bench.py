@@ -7,13 +7,16 @@ f1 ~ U[-1, 1], g2 ~ U[0.01, 0.1], g1 ~ U[0.8, 1.2], bounds [0, 2],
 y ~ U[0.5, 1.5], c = 0.7 sum_k g(2), rho = 1 (seed 2).  The inputs are
 uploaded to HBM before the timed region.
 
-A step is one whole ADMM iteration (7a)-(7i): the fused x/s/mu sweep and the
-finalize kernel with the z/lambda/h/p/consensus updates, with the residuals
-checked every 10 iterations.  `value` is iterations per second over exactly
---steps iterations.  Also reported: per-kernel times from HIP events on the
-library's stream (roofline of the sweep kernel), a solve to the residual
-threshold (iterations and solves per second), the FP64 variant, and the FP64
-oracle timed on the host's cores.
+A step is one whole ADMM iteration (7a)-(7i): the x/s/mu sweep with its block
+partials and the scalar z/lambda/h/p steps, with the residuals checked every
+10 iterations.  On this workload the default launch path issues one chained
+kernel per iteration (each launch finishes the previous iteration's scalar
+steps, then sweeps); --launch split times the sweep + finalize pair instead.
+`value` is iterations per second over exactly --steps iterations.  Also
+reported: per-kernel times from HIP events on the library's stream (roofline
+of the dominant kernel), solves to the residual threshold (iterations and
+solves per second), the other precisions, the batched, served and robust
+workloads, and the FP64 oracle timed on the host's cores.
 
 Prints one JSON line.
 """
@@ -47,6 +50,40 @@ def to_device(p, dtype):
     return W.Problem(**kw)
 
 
+# Device sources whose compiled code the hardware byte counters describe.
+KERNEL_SOURCES = ("admm_kernels.hip", "admm_device.hpp", "admm_quartic.hpp", "admm_internal.hpp")
+
+
+def kernel_sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1903_10041_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel, precision, m, n):
+    """HBM bytes per launch of `kernel` from the committed counter summaries
+    under profiles/ (a line `traffic-record: key=value ...` written from two
+    rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, each scaled by what the
+    counter reads for a plain copy of known size).  None when no record was
+    taken on the current kernel sources for this workload."""
+    import glob
+    digest = kernel_sources_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+                if (kv.get("kernel") == kernel and kv.get("precision") == precision
+                        and kv.get("m") == str(m) and kv.get("n") == str(n)
+                        and kv.get("sources") == digest):
+                    return float(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
+
+
 def sweep_bytes(m, n, q, word):
     """Algorithmic bytes of one sweep launch: per element 4 coefficient words
     + x read + x write; per column y + w read + w write."""
@@ -67,9 +104,12 @@ def run_gpu(args, precision_name):
     torch.cuda.synchronize()
     ctx = admm.Context(0)
 
+    launch = {"auto": admm.LAUNCH_AUTO, "split": admm.LAUNCH_SPLIT, "chained": admm.LAUNCH_CHAINED,
+              "resident": admm.LAUNCH_RESIDENT}[args.launch]
+
     def fixed(iters):
         return admm.Settings(rho=p.rho, max_iter=iters, eps_primal=0.0, eps_dual=0.0,
-                             precision=prec)
+                             precision=prec, launch=launch)
 
     ctx.solve(pd, fixed(max(1, args.warmup)))
     torch.cuda.synchronize()
@@ -81,24 +121,41 @@ def run_gpu(args, precision_name):
     wall = t1 - t0
     res = {"iters_per_s": args.steps / wall, "ms_per_step": 1000.0 * wall / args.steps,
            "device_ms": info["device_ms"]}
+    # spread: repeated shorter timed solves of the same instance
+    if args.repeats > 0:
+        rates = []
+        for _ in range(args.repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.solve(pd, fixed(args.repeat_steps))
+            torch.cuda.synchronize()
+            rates.append(args.repeat_steps / (time.perf_counter() - t0))
+        rates.sort()
+        res["repeats"] = {"count": len(rates), "steps": args.repeat_steps,
+                          "iters_per_s_median": rates[len(rates) // 2],
+                          "iters_per_s_min": rates[0], "iters_per_s_max": rates[-1]}
 
     prof = admm.admm_profile(ctx, pd, fixed(1), iters=args.profile_iters)
     byts = sweep_bytes(p.m, p.n, p.q, word)
     achieved = byts / (prof["sweep_us"] * 1e-6) / 1e9
+    res["launch"] = prof["launch"]
     res["kernel_us"] = {"sweep": prof["sweep_us"], "finalize": prof["finalize_us"],
                         "graph_iteration": prof["graph_iter_us"],
                         "persistent_iteration": prof["persist_iter_us"],
                         "persistent_cols_per_thread": prof["persist_cols_per_thread"]}
+    kernel = "k_chain" if prof["launch"] == "chained" else "k_sweep"
+    traffic, tsrc = traffic_record(kernel, precision_name, p.m, p.n)
     res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                       "bytes_per_launch": byts, "kernel": "k_sweep"}
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                       "bytes_per_launch": byts, "kernel": kernel,
+                       "traffic_from": tsrc, "sources": kernel_sources_digest()}
 
     if not args.skip_converge:
         eps = 1e-6 if precision_name == "f64" else 1e-4
         res["solve"] = {}
         for tag, r2, cap in (("rho1", False, args.converge_max_iter), ("rho2_per_step", True, 100000)):
             s = admm.Settings(rho=p.rho, max_iter=cap, eps_primal=eps, eps_dual=eps,
-                              precision=prec, rho2_per_step=r2)
+                              precision=prec, rho2_per_step=r2, launch=launch)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             x, info, _ = ctx.solve(pd, s)
@@ -107,8 +164,46 @@ def run_gpu(args, precision_name):
             res["solve"][tag] = {"residual": eps, "status": info["status"], "iters": info["iters"],
                                  "r": info["r"], "sigma": info["sigma"], "objective": info["objective"],
                                  "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
+            if r2:
+                # the same solve from host arrays: H2D of the problem, solve, D2H of x
+                t0 = time.perf_counter()
+                _, hinfo, _ = ctx.solve(p, s)
+                t1 = time.perf_counter()
+                res["solve"][tag]["host_inputs_ms"] = 1000.0 * (t1 - t0)
+                res["solve"][tag]["host_inputs_iters"] = hinfo["iters"]
     ctx.close()
     return res
+
+
+def run_large(args):
+    """The bandwidth shape with n = 2^22 (m = 4, 16.8M quartics per x-step):
+    a working set larger than the 256 MB last-level cache.  Fixed
+    iteration count, headline precision, the default launch path."""
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    prec = _prec(args)
+    tdt = torch.float64 if args.precision == "f64" else torch.float32
+    word = 8 if args.precision == "f64" else 4
+    p = W.large_c2(n=args.large_n, m=4)
+    pd = to_device(p, tdt)
+    ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
+    s = lambda it: admm.Settings(rho=p.rho, max_iter=it, eps_primal=0.0, eps_dual=0.0, precision=prec)
+    ctx.solve(pd, s(20))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info, _ = ctx.solve(pd, s(args.large_steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = admm.admm_profile(ctx, pd, s(1), iters=100)
+    ctx.close()
+    byts = sweep_bytes(p.m, p.n, p.q, word)
+    ach = byts / (prof["sweep_us"] * 1e-6) / 1e9
+    return {"workload": f"m=4 n={p.n} q=1 rho=1, {args.precision}, {args.large_steps} iterations",
+            "iters_per_s": args.large_steps / dt, "launch": prof["launch"],
+            "kernel_us": {"sweep": prof["sweep_us"], "finalize": prof["finalize_us"],
+                          "graph_iteration": prof["graph_iter_us"]},
+            "sweep_bytes": byts, "sweep_gbs": ach, "sweep_hbm_frac": ach / HBM_PEAK_GBS}
 
 
 def _prec(args):
@@ -281,9 +376,36 @@ def cpu_baseline(args):
     t0 = time.perf_counter()
     oracle.run(p, max_iter=iters, state=st, nthreads=nt)
     dt = time.perf_counter() - t0
-    return {"value": iters / dt, "unit": "iters/s", "cores": nt, "kind": "oracle",
-            "sample": f"FP64 oracle, same m={p.m} n={p.n} instance, {iters} iterations "
-                      f"({dt:.1f} s) after three warm-up iterations, OpenMP x-step on {nt} threads"}
+    out = {"value": iters / dt, "unit": "iters/s", "cores": nt, "kind": "oracle",
+           "sample": f"FP64 oracle, same m={p.m} n={p.n} instance, {iters} iterations "
+                     f"({dt:.1f} s) after three warm-up iterations, OpenMP x-step on {nt} threads"}
+    # one thread, shorter sample
+    t0 = time.perf_counter()
+    it1 = max(1, int(0.4 * iters / nt))
+    oracle.run(p, max_iter=it1, state=st, nthreads=1)
+    out["single_thread"] = {"value": it1 / (time.perf_counter() - t0), "iterations": it1}
+    # the served request mix through the oracle, one request after another
+    import math
+    import numpy as np
+    rng = np.random.default_rng(5)
+    lat, t_all = [], time.perf_counter()
+    for r in range(args.cpu_serve_requests):
+        m = int(rng.choice([2, 4]))
+        n = int(round(math.exp(rng.uniform(math.log(100), math.log(50000)))))
+        q = W.uniform_problem(m, n, 5 * 7_000_003 + r)
+        t0 = time.perf_counter()
+        oracle.run(q, max_iter=20000, eps_primal=1e-4, eps_dual=1e-4,
+                   rho=(1.0, 1.0 / n, 1.0, 1.0), nthreads=1)
+        lat.append(time.perf_counter() - t0)
+    if lat:
+        lat_ms = np.array(lat) * 1000.0
+        out["served_requests"] = {
+            "requests": len(lat), "threads": 1,
+            "sample": "first requests of the served pool (m in {2,4}, n log-uniform [100, 50000]), "
+                      "cold starts, residual 1e-4, rho_2 / n, one at a time on one thread",
+            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+            "solves_per_s_per_thread": len(lat) / (time.perf_counter() - t_all)}
+    return out
 
 
 def main():
@@ -295,6 +417,8 @@ def main():
     ap.add_argument("--n", type=int, default=262144)
     ap.add_argument("--m", type=int, default=4)
     ap.add_argument("--profile-iters", type=int, default=400)
+    ap.add_argument("--launch", choices=["auto", "split", "chained", "resident"], default="auto",
+                    help="launch path of the plain solve (auto: chained for this workload)")
     ap.add_argument("--converge-max-iter", type=int, default=400000)
     ap.add_argument("--skip-converge", action="store_true")
     ap.add_argument("--skip-variant", action="store_true")
@@ -307,6 +431,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-pool", type=int, default=384)
     ap.add_argument("--robust-max-iter", type=int, default=100000)
+    ap.add_argument("--repeats", type=int, default=10, help="repeated timed solves for the spread")
+    ap.add_argument("--repeat-steps", type=int, default=1000)
+    ap.add_argument("--large-n", type=int, default=1 << 22)
+    ap.add_argument("--large-steps", type=int, default=300)
+    ap.add_argument("--cpu-serve-requests", type=int, default=24)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run the library's plain copy kernel (k_copy_calib) 3 times over this "
                          "many MiB, to scale hardware byte counters")
@@ -333,6 +462,7 @@ def main():
                 continue
             a2 = argparse.Namespace(**vars(args))
             a2.steps = max(100, args.steps // 2)
+            a2.repeats = 0
             a2.converge_max_iter = min(args.converge_max_iter, 100000)
             variants[other] = run_gpu(a2, other)
     extras = {}
@@ -340,6 +470,7 @@ def main():
         extras["batched"] = run_batch(args)
         extras["served"] = run_serve(args)
         extras["robust"] = run_robust(args)
+        extras["large"] = run_large(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
     storage = {"f32": "f32 storage and x-step arithmetic, f64 reductions",
@@ -361,10 +492,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"plain single instance m={args.m} n={args.n} q=1 rho=1, "
                                f"{args.precision} path ({storage[args.precision]}), residual check every 10",
-                   "m": args.m, "n": args.n, "q": 1, "precision": args.precision},
+                   "m": args.m, "n": args.n, "q": 1, "precision": args.precision,
+                   "launch": head["launch"]},
         "roofline": {k: v for k, v in head["roofline"].items()},
         "cpu_baseline": cpu,
         "kernel_us": head["kernel_us"],
+        "repeats": head.get("repeats"),
         "solve": head.get("solve"),
         "variants": variants or None,
     }

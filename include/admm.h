@@ -80,6 +80,24 @@ typedef enum { ADMM_XSTEP_EXACT_BOX = 0, ADMM_XSTEP_PAPER_PROJECT = 1 } admm_xst
  * already-updated x^(l) for l < i, JACOBI uses the previous iterate. */
 typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
 
+/* How admm_solve issues the iterations on the GPU (results agree to
+ * rounding; each path is deterministic on its own).
+ * AUTO      RESIDENT when the problem fits in a few co-resident blocks,
+ *           else CHAINED when it applies, else SPLIT.
+ * SPLIT     a captured graph of two launches per iteration: the sweep
+ *           (7a), (7e), (7f) with block partials, then one block for the
+ *           scalar steps (7b)-(7d), (7g)-(7i), residuals and stop flag.
+ * CHAINED   one launch per iteration: each launch first completes the
+ *           previous iteration's scalar steps (every block computes them
+ *           from the partials), then sweeps.  q = 1 without consensus,
+ *           m <= 4 and n <= 524288 only (ADMM_E_UNSUPPORTED otherwise).
+ * RESIDENT  one cooperative launch whose blocks keep their columns in
+ *           registers and meet at a grid barrier every iteration; only
+ *           when every block fits on the device at once (else
+ *           ADMM_E_UNSUPPORTED). */
+typedef enum { ADMM_LAUNCH_AUTO = 0, ADMM_LAUNCH_SPLIT = 1, ADMM_LAUNCH_CHAINED = 2,
+               ADMM_LAUNCH_RESIDENT = 3 } admm_launch;
+
 typedef enum { ADMM_HOST = 0, ADMM_DEVICE = 1 } admm_memspace;
 typedef enum { ADMM_BOUNDS_PER_SOURCE = 0, ADMM_BOUNDS_PER_STEP = 1 } admm_bounds_layout;
 
@@ -112,6 +130,7 @@ typedef struct {
     int32_t consensus_q1;            /* keep the rho_4 block when q == 1 (default 0) */
     int32_t debug_branch_codes;      /* record per-element branch codes of the last x-step */
     int32_t rho2_per_step;           /* 1: the capacity block uses rho_2 / n (default 0) */
+    admm_launch launch;              /* admm_solve's launch path (default AUTO) */
 } admm_settings;
 
 /* Iterate of (7a)-(7i), in the paper's variables, host doubles.  Any NULL
@@ -142,7 +161,7 @@ typedef struct {
 
 /* Defaults: rho = 1, eps = 1e-6, max_iter = 10000, check_every = 10, F64,
  * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes,
- * rho2_per_step = 0.  rho2_per_step scales the penalty of the capacity
+ * rho2_per_step = 0, launch AUTO.  rho2_per_step scales the penalty of the capacity
  * constraint sum_k z_k = h (one constraint over n terms) by 1/n per
  * instance; with rho_2 = rho_1 the iteration count grows about linearly in
  * n, with rho_2 = rho_1 / n it stays near a hundred for any n. */
@@ -194,29 +213,45 @@ admm_status admm_poll(admm_context *ctx, uint64_t ticket, double *x_out, admm_in
 admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key);
 
 /* Measurement hook.  Stages the problem, starts from the cold start and
- * times each kernel of the plain path on the context's stream: a captured
- * graph of back-to-back launches of that kernel, replayed between one HIP
- * event pair, for about `iters` (20..100000) launches each; then whole
- * iterations the same way.  out[4]: mean microseconds per sweep launch, per
- * finalize launch, per iteration, and the launch count; out[4], out[5]:
- * when the problem takes the resident persistent path, microseconds per
- * iteration of one cooperative launch and its columns per thread (else 0).
+ * times the kernels of the launch path admm_solve would take, on the
+ * context's stream: a captured graph of back-to-back launches of one
+ * kernel, replayed between one HIP event pair, for about `iters`
+ * (20..100000) launches; then whole iterations the same way.
+ *   out[0]  microseconds per sweep launch (SPLIT, RESIDENT) or per chained
+ *           launch (CHAINED: the sweep and the previous scalar steps);
+ *   out[1]  microseconds per scalar-step launch (SPLIT; 0 for CHAINED);
+ *   out[2]  microseconds per iteration of the captured graph;
+ *   out[3]  launches timed per kernel;
+ *   out[4], out[5]  RESIDENT: microseconds per iteration of one
+ *           cooperative launch and its columns per thread (else 0);
+ *   out[6]  the admm_launch path taken (1 SPLIT, 2 CHAINED, 3 RESIDENT).
  * Thresholds are ignored; the timed launches advance the iterate and
- * results are not returned.  out must hold 6 doubles. */
+ * results are not returned.  out must hold 7 doubles. */
 admm_status admm_profile(admm_context *ctx, const admm_problem *prob,
                          const admm_settings *settings, int32_t iters, double *out);
 
-/* Test hooks.  admm_debug_codes: branch codes (3*branch + clamp state) of
- * the last x-step of the previous debug_branch_codes solve of `prob`,
- * [q][m][n] bytes.  admm_debug_quartic: the device x-step minimiser of
- * A x^4 + B x^3 + C x^2 + D x over [lo, hi] (Alg. 1 with the box rule of
- * `paper_project`, in the arithmetic of `precision`) applied to N host
- * arrays; writes x_out[N] and codes_out[N]. */
+/* Standalone x-step minimiser (Alg. 1, Sec. III-B): for e < N,
+ *   x[e] = argmin over [lo[e], hi[e]] of A x^4 + B x^3 + C x^2 + D x,
+ * with the box rule of `xstep` and the arithmetic of `precision` (as in the
+ * iteration).  Requires A >= 0 (A = 0 is the quadratic and then C > 0),
+ * finite A..D, lo <= hi (infinite bounds allowed).  codes[e] (may be NULL)
+ * is 3 * branch + clamp state, branch 0 quadratic, 1 one real root
+ * (Cardano), 2 triple root, 3 / 4 three real roots with the smaller / larger
+ * outer root chosen; clamp state 0 interior, 1 at lo, 2 at hi.
+ * mem == ADMM_HOST: host arrays, copied through the context's staging
+ * buffer.  mem == ADMM_DEVICE: device arrays, used in place on the stream of
+ * admm_set_stream.  Returns when the results are written.  Elements outside
+ * the domain get x = NaN, code -1, and the call returns ADMM_E_INVALID_ARG.
+ * device_ms (may be NULL): kernel time between HIP events. */
+admm_status admm_minimize_quartics(admm_context *ctx, int64_t N, admm_memspace mem,
+                                   const double *A, const double *B, const double *C,
+                                   const double *D, const double *lo, const double *hi,
+                                   admm_xstep xstep, admm_precision precision,
+                                   double *x_out, int32_t *codes_out, double *device_ms);
+
+/* Test hook: branch codes (3*branch + clamp state) of the last x-step of the
+ * previous debug_branch_codes solve of `prob`, [q][m][n] bytes. */
 admm_status admm_debug_codes(admm_context *ctx, const admm_problem *prob, uint8_t *out);
-admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const double *A, const double *B,
-                               const double *C, const double *D, const double *lo, const double *hi,
-                               int32_t paper_project, int32_t precision, double *x_out,
-                               int32_t *codes_out);
 
 /* Measurement hook: a plain copy kernel (k_copy_calib) over `bytes` of
  * device memory, `reps` times, on freshly allocated buffers; the reference

@@ -27,6 +27,7 @@ E_UNKNOWN_TICKET, E_QUEUE_FULL, E_UNSUPPORTED = -5, -6, -7
 F64, F32_MIXED, F32 = 0, 1, 2
 XSTEP_EXACT_BOX, XSTEP_PAPER_PROJECT = 0, 1
 SWEEP_GAUSS_SEIDEL, SWEEP_JACOBI = 0, 1
+LAUNCH_AUTO, LAUNCH_SPLIT, LAUNCH_CHAINED, LAUNCH_RESIDENT = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
 BOUNDS_PER_SOURCE, BOUNDS_PER_STEP = 0, 1
 
@@ -51,7 +52,8 @@ class admm_settings(C.Structure):
                 ("eps_dual", C.c_double), ("max_iter", C.c_int32),
                 ("check_every", C.c_int32), ("precision", C.c_int),
                 ("xstep", C.c_int), ("sweep", C.c_int), ("consensus_q1", C.c_int32),
-                ("debug_branch_codes", C.c_int32), ("rho2_per_step", C.c_int32)]
+                ("debug_branch_codes", C.c_int32), ("rho2_per_step", C.c_int32),
+                ("launch", C.c_int)]
 
 
 class admm_state(C.Structure):
@@ -98,7 +100,8 @@ def lib():
             "admm_last_error": (C.c_char_p, []),
             "admm_debug_codes": (C.c_int, [vp, vp, vp]),
             "admm_profile": (C.c_int, [vp, vp, vp, i32, vp]),
-            "admm_debug_quartic": (C.c_int, [vp, C.c_int64] + [vp] * 6 + [i32, i32, vp, vp]),
+            "admm_minimize_quartics": (C.c_int, [vp, C.c_int64, C.c_int] + [vp] * 6 + [C.c_int, C.c_int,
+                                                                                       vp, vp, vp]),
             "admm_debug_copy": (C.c_int, [vp, C.c_size_t, i32]),
         }
         for name, (res, args) in sigs.items():
@@ -132,13 +135,15 @@ class Settings:
     consensus_q1: bool = False
     debug_branch_codes: bool = False
     rho2_per_step: bool = False
+    launch: int = LAUNCH_AUTO
 
     def to_c(self) -> admm_settings:
         return admm_settings((C.c_double * 4)(*[float(r) for r in self.rho]),
                              float(self.eps_primal), float(self.eps_dual), int(self.max_iter),
                              int(self.check_every), int(self.precision), int(self.xstep),
                              int(self.sweep), int(bool(self.consensus_q1)),
-                             int(bool(self.debug_branch_codes)), int(bool(self.rho2_per_step)))
+                             int(bool(self.debug_branch_codes)), int(bool(self.rho2_per_step)),
+                             int(self.launch))
 
 
 def _is_torch(a) -> bool:
@@ -342,14 +347,15 @@ def admm_solve_batch(ctx: "Context", probs, settings: Optional[Settings] = None,
 def _profile(ctx, prob, settings, iters):
     mp = _Marshal(prob)
     s = settings.to_c() if settings else None
-    out = (C.c_double * 6)()
+    out = (C.c_double * 7)()
     if mp.device:
         import torch
         ctx.set_stream(torch.cuda.current_stream(prob.f2.device).cuda_stream)
     _check(lib().admm_profile(ctx.h, C.byref(mp.st), C.byref(s) if s is not None else None,
                               int(iters), out), allow=(OK,))
     return {"sweep_us": out[0], "finalize_us": out[1], "graph_iter_us": out[2], "iters": int(out[3]),
-            "persist_iter_us": out[4], "persist_cols_per_thread": int(out[5])}
+            "persist_iter_us": out[4], "persist_cols_per_thread": int(out[5]),
+            "launch": {1: "split", 2: "chained", 3: "resident"}.get(int(out[6]), "unknown")}
 
 
 def admm_profile(ctx: "Context", prob, settings: Optional[Settings] = None, iters: int = 200) -> dict:
@@ -357,16 +363,46 @@ def admm_profile(ctx: "Context", prob, settings: Optional[Settings] = None, iter
     return _profile(ctx, prob, settings, iters)
 
 
-def admm_debug_quartic(ctx: "Context", A, B, Cc, D, lo, hi, paper_project=False, precision=F64):
-    """Device quartic minimiser on arrays (returns x, codes)."""
-    arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), np.shape(A)).ravel())
+def minimize_quartics(ctx: "Context", A, B, Cc, D, lo, hi, paper_project=False, precision=F64,
+                      want_codes=True):
+    """The standalone x-step minimiser (Alg. 1) over arrays: numpy arrays
+    (host; broadcast to A's shape) or float64 CUDA tensors of one shape
+    (device, used in place on the current stream).  Returns
+    (x, codes or None, kernel milliseconds)."""
+    ms = C.c_double(0.0)
+    xs = XSTEP_PAPER_PROJECT if paper_project else XSTEP_EXACT_BOX
+    if _is_torch(A):
+        import torch
+        arrs = [A, B, Cc, D, lo, hi]
+        for a in arrs:
+            if a.dtype != torch.float64 or not a.is_contiguous() or a.shape != A.shape or a.device != A.device:
+                raise TypeError("device arrays must be contiguous float64 tensors of one shape and device")
+        x = torch.empty_like(A)
+        codes = torch.empty(A.shape, dtype=torch.int32, device=A.device) if want_codes else None
+        ctx.set_stream(torch.cuda.current_stream(A.device).cuda_stream)
+        st = lib().admm_minimize_quartics(ctx.h, A.numel(), DEVICE, *[a.data_ptr() for a in arrs], xs,
+                                          int(precision), x.data_ptr(),
+                                          codes.data_ptr() if codes is not None else None, C.byref(ms))
+        _check(st, allow=(OK,))
+        return x, codes, ms.value
+    shape = np.shape(A)
+    arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), shape).ravel())
             for v in (A, B, Cc, D, lo, hi)]
     N = arrs[0].size
     x = np.empty(N)
-    codes = np.empty(N, dtype=np.int32)
-    _check(lib().admm_debug_quartic(ctx.h, N, *[a.ctypes.data for a in arrs], int(paper_project),
-                                    int(precision), x.ctypes.data, codes.ctypes.data), allow=(OK,))
-    return x.reshape(np.shape(A)), codes.reshape(np.shape(A))
+    codes = np.empty(N, dtype=np.int32) if want_codes else None
+    st = lib().admm_minimize_quartics(ctx.h, N, HOST, *[a.ctypes.data for a in arrs], xs, int(precision),
+                                      x.ctypes.data, codes.ctypes.data if codes is not None else None,
+                                      C.byref(ms))
+    _check(st, allow=(OK,))
+    return x.reshape(shape), (codes.reshape(shape) if codes is not None else None), ms.value
+
+
+def admm_debug_quartic(ctx: "Context", A, B, Cc, D, lo, hi, paper_project=False, precision=F64):
+    """Host-array form of minimize_quartics returning (x, codes)."""
+    x, codes, _ = minimize_quartics(ctx, A, B, Cc, D, lo, hi, paper_project=paper_project,
+                                    precision=precision)
+    return x, codes
 
 
 def admm_debug_copy(ctx: "Context", nbytes: int, reps: int = 3):

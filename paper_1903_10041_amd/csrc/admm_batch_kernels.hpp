@@ -49,6 +49,7 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.nblk = 1;
     P.cpt = 1;
     P.persistent = 0;
+    P.chain = 0;
     P.group = 1;
     P.check_every = I.check_every;
     P.max_iter = I.max_iter;
@@ -86,6 +87,9 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.pair_s = nullptr;
     P.ctrl = nullptr;
     P.bar = nullptr;
+    P.scal1 = nullptr;
+    P.ctrl1 = nullptr;
+    P.part1 = nullptr;
     return P;
 }
 

@@ -9,6 +9,8 @@ namespace admm {
 constexpr int kBlock = 256;          // threads per block (4 wave64s)
 constexpr int kWaves = kBlock / 64;
 constexpr int kPad = 64;             // n is padded to a multiple of this
+constexpr int kChainBlock = 1024;    // threads per block of the chained iteration
+constexpr int kChainMaxBlocks = 512; // largest grid the chained iteration takes
 
 // Device-resident control block of one solve (one instance).
 struct Ctrl {
@@ -18,8 +20,11 @@ struct Ctrl {
     int32_t bad_input;  // set by the pack kernel when validation fails
     double r, sigma;    // residuals at the last check iteration
     double objective;
-    double pad_[3];
+    int32_t pending;    // chained path: the last sweep's scalar steps are still to do
+    int32_t pad_i;
+    double pad_[2];
 };
+static_assert(sizeof(Ctrl) == 64, "Ctrl is one 64-byte line");
 
 // Branch classes of the x-step (code = 3 * branch + clamp state).
 enum { BR_QUAD = 0, BR_CARDANO = 1, BR_TRIPLE = 2, BR_TRIG_LO = 3, BR_TRIG_HI = 4 };
@@ -32,7 +37,8 @@ struct SolveParams {
     int32_t m, n, q, n_pad;
     int32_t nblk;           // sweep blocks per scenario
     int32_t cpt;            // columns per sweep thread (1, 2 or 4)
-    int32_t persistent;     // 1: resident cooperative kernel, 0: graph of sweep + finalize
+    int32_t persistent;     // 1: resident cooperative kernel, 0: graph of launches
+    int32_t chain;          // 1: one chained launch per iteration (q = 1), 0: sweep + finalize
     int32_t group;          // finalize: lanes cooperating on one (i,j) pair
     int32_t check_every, max_iter;
     int32_t xstep_project, jacobi, consensus, want_codes;
@@ -53,6 +59,11 @@ struct SolveParams {
     double *pair_r, *pair_s;// [q][m] check scratch
     Ctrl *ctrl;
     uint32_t *bar;          // grid barrier words (persistent path)
+    // chained path: second copy of the per-source scalars (lam, zoff, h, p,
+    // [4][m]), of the control block and of the block partials
+    double *scal1;
+    Ctrl *ctrl1;
+    double *part1;
 };
 
 // Partials layout (doubles): g-sum [q][nblk][m], then dg-max, dg-min (same
@@ -72,13 +83,18 @@ hipError_t launch_cold_init(const SolveParams &P, int dtype, hipStream_t s);
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
+// Chained path: launch at graph position c reads slot c & 1 (rs).
+hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s);
+hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s);
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
 hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,
                          const void *w_src, hipStream_t s);
-hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, const double *C, const double *D,
-                               const double *lo, const double *hi, int project, int mixed, double *x,
-                               int32_t *codes, hipStream_t s);
+// precision: 0 FP64, 1 FP32 with FP64 polish, 2 FP32; codes may be null;
+// *bad is raised (atomic OR) for inputs outside the minimiser's domain.
+hipError_t launch_quartics(int64_t N, const double *A, const double *B, const double *C, const double *D,
+                           const double *lo, const double *hi, int project, int precision, double *x,
+                           int32_t *codes, int32_t *bad, hipStream_t s);
 const void *persist_kernel(int dtype, int m, int R);
 hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int chunk, uint32_t spin_limit,
                           hipStream_t s);

@@ -28,18 +28,13 @@ namespace admm {
 // Streaming sweep (graph path): one thread owns CPT columns of tile
 // (j, blockIdx.x), k = blockIdx.x * CPT * 256 + c * 256 + tid.  CHECK
 // selects the variant that also tracks the residual terms; it is used only
-// on check iterations.  FUSED: the last block to finish (an atomic count of
-// finished blocks, with release/acquire fences around it) runs the scalar
-// steps, so one launch is a whole iteration.
-template <typename T, int MAXM, int CPT, int MODE, bool CHECK, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_sweep(SolveParams P) {
+// on check iterations.  Kernels for up to four sources are held to 128
+// VGPRs so that four waves fit on each SIMD.
+template <typename T, int MAXM, int CPT, int MODE, bool CHECK>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 4 ? 4 : 2)))
+void k_sweep(SolveParams P) {
     Ctrl *ctrl = P.ctrl;
     if (ctrl->done) return;
-    // the graph places the check variant by iteration number; flag any
-    // disagreement with the device counter (reported as a device error)
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 &&
-        (((ctrl->t + 1) % P.check_every) == 0) != CHECK)
-        atomicOr(&ctrl->bad_input, 2);
     const int j = blockIdx.y;
     Scal<MAXM> sc;
     scal_load<MAXM, false>(P, j, sc);
@@ -57,45 +52,299 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SolveParams P) {
     }
     __shared__ double lds[MAXM + 2][kBlock];
     block_partials<MAXM>(P, (size_t)j * P.nblk + blockIdx.x, acc, CHECK, lds);
-    if (FUSED) {
-        __shared__ int last;
-        if (threadIdx.x == 0) {
-            __threadfence();
-            const uint32_t total = (uint32_t)(gridDim.x * gridDim.y);
-            last = __hip_atomic_fetch_add(P.bar, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == total - 1;
-        }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            finalize_body(P);
-            if (threadIdx.x == 0) __hip_atomic_store(P.bar, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    // the graph places the check variant by iteration number; flag any
+    // disagreement with the device counter (reported as a device error).
+    // Tested last: a test at the top costs registers in the column code.
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 &&
+        (((ctrl->t + 1) % P.check_every) == 0) != CHECK)
+        atomicOr(&ctrl->bad_input, 2);
 }
 
-// Element-wise quartic minimiser (parity tests of the device math).
+// Element-wise quartic minimiser (the standalone entry point and the
+// parity tests of the device math).  Inputs that break the minimiser's
+// preconditions (A < 0, a non-finite value, lo > hi, A = 0 with C <= 0)
+// raise *bad and give x = NaN, code -1.
 template <int MODE>
-__global__ void k_quartic(int64_t N, const double *A, const double *B, const double *C, const double *D,
-                          const double *lo, const double *hi, int project, double *x, int32_t *codes) {
+__global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, const double *B, const double *C,
+                                                    const double *D, const double *lo, const double *hi,
+                                                    int project, double *x, int32_t *codes, int32_t *bad) {
+    int flag = 0;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
-        int code;
-        double v;
-        if (MODE == MODE_MIXED) {
-            v = qmin_mixed(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+        const double a = A[e], b = B[e], c = C[e], d = D[e], l = lo[e], h = hi[e];
+        int code = -1;
+        double v = NAN;
+        const bool ok = a >= 0.0 && isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) &&
+                        !isnan(l) && !isnan(h) && l <= h && (a > 0.0 || c > 0.0);
+        if (!ok) {
+            flag = 1;
+        } else if (MODE == MODE_MIXED) {
+            v = qmin_mixed(a, b, c, d, l, h, project, code);
         } else if (MODE == MODE_F32) {
-            if (!qmin_f32_fast((float)A[e], (float)B[e], (float)C[e], (float)D[e], (float)lo[e], (float)hi[e], v, code))
-                v = qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+            if (!qmin_f32_fast((float)a, (float)b, (float)c, (float)d, (float)l, (float)h, v, code))
+                v = qmin_f64(a, b, c, d, l, h, project, code);
         } else {
-            v = qmin_f64(A[e], B[e], C[e], D[e], lo[e], hi[e], project, code);
+            v = qmin_f64(a, b, c, d, l, h, project, code);
         }
         x[e] = v;
-        codes[e] = code;
+        if (codes) codes[e] = code;
     }
+    if (flag) atomicOr(bad, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P) {
     if (P.ctrl->done) return;
     finalize_body(P);
+}
+
+// ------------------------------------------------------ chained iteration
+//
+// Single-scenario problems (q = 1, no consensus, m <= 4) whose columns fit
+// in at most kChainMaxBlocks blocks of kChainBlock threads run one launch
+// per iteration (1024-thread blocks cap a kernel at 128 VGPRs, which the
+// column code for up to four sources fits).  Launch t first completes iteration t-1: every block sums the
+// block partials that launch t-1 left, in the same fixed order, so every
+// block derives bit-identical scalars (7b)+(7g), (7d)+(7i), residuals and
+// stop decision.  Then it sweeps iteration t with them and leaves its own
+// partials.  Everything that crosses launches is double buffered: the launch
+// at graph position c reads slot rs = c & 1 (scalars, control block) and
+// partial buffer rs ^ 1, and writes slot rs ^ 1 (block 0 only) and partial
+// buffer rs.  No launch reads what it writes, so blocks never wait for one
+// another and the scalar steps cost no launch of their own.  A chunk has an
+// even number of launches, so it starts and ends on slot 0, which is where
+// the rest of the library (init, export, objective) keeps the state.
+
+struct ChainSlot {
+    double *lam, *zoff, *h, *p;
+    Ctrl *ctrl;
+};
+
+__device__ __forceinline__ ChainSlot chain_slot(const SolveParams &P, int s) {
+    ChainSlot c;
+    if (s == 0) {
+        c.lam = P.lam; c.zoff = P.zoff; c.h = P.h; c.p = P.p; c.ctrl = P.ctrl;
+    } else {
+        c.lam = P.scal1; c.zoff = P.scal1 + P.m; c.h = P.scal1 + 2 * P.m; c.p = P.scal1 + 3 * P.m;
+        c.ctrl = P.ctrl1;
+    }
+    return c;
+}
+
+// Scalars and decisions shared by the threads of one block.
+template <int MAXM>
+struct ChainShared {
+    double lam[MAXM], zoff[MAXM], h[MAXM], p[MAXM];   // state after the pending steps
+    double gsum[MAXM], dgmax[MAXM], dgmin[MAXM];       // partials summed over blocks
+    double pr[MAXM], ps[MAXM];                         // per-source residual terms
+    double rdem, sig3;
+    double r, sigma;
+    int t, status, done, bad;
+};
+
+// Completes the pending iteration (if any) from slot rs and partial buffer
+// rs ^ 1 into `sh`.  Ends with a block barrier.
+template <int MAXM, int NT>
+__device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, ChainShared<MAXM> &sh) {
+    const ChainSlot in = chain_slot(P, rs);
+    const double *part = rs ? P.part : P.part1;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = P.m, nb = P.nblk;
+    const Ctrl *c = in.ctrl;
+    const int t = c->t, pending = c->pending, done = c->done;
+    const bool fin = pending && !done;
+    const bool chk = fin && (t % P.check_every) == 0;
+    const size_t slab = (size_t)nb * m;
+    if (fin) {
+        if (wv < m) {
+            const int i = wv;
+            double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
+            for (int b = lane; b < nb; b += 64) {
+                s += part[(size_t)b * m + i];
+                if (chk) {
+                    mx = fmax(mx, part[slab + (size_t)b * m + i]);
+                    mn = fmin(mn, part[2 * slab + (size_t)b * m + i]);
+                }
+            }
+            s = wave_sum(s);
+            if (chk) { mx = wave_max(mx); mn = wave_min(mn); }
+            if (lane == 0) { sh.gsum[i] = s; sh.dgmax[i] = mx; sh.dgmin[i] = mn; }
+        } else if (wv == NT / 64 - 1 && chk) {
+            double r = 0.0, sg = 0.0;
+            for (int b = lane; b < nb; b += 64) {
+                r = fmax(r, part[3 * slab + 2 * (size_t)b]);
+                sg = fmax(sg, part[3 * slab + 2 * (size_t)b + 1]);
+            }
+            r = wave_max(r);
+            sg = wave_max(sg);
+            if (lane == 0) { sh.rdem = r; sh.sig3 = sg; }
+        }
+    }
+    __syncthreads();
+    if (tid < m) {
+        const int i = tid;
+        double lam = in.lam[i], zoff = in.zoff[i], h = in.h[i], p = in.p[i];
+        double pr = 0.0, ps = 0.0;
+        if (fin) {
+            const double nd = (double)P.n;
+            const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+            const double W = sh.gsum[i] - nd * lam;          // 1'(g(x) - lambda)
+            const double kap = kfac * (h + p - W);
+            const double sumz = W + nd * kap;                // 1'z
+            const double zn = kap - lam;                     // z - g(x)
+            const double hn = fmin(P.cap[i], sumz - p);
+            const double pn = p + hn - sumz;
+            if (chk) {
+                const double cz = zn - zoff;
+                pr = fmax(fabs(zn), fabs(hn - sumz));
+                ps = fmax(P.rho1 * fmax(fabs(sh.dgmax[i] + cz), fabs(sh.dgmin[i] + cz)), P.rho2 * fabs(hn - h));
+            }
+            lam = kap;
+            zoff = zn;
+            h = hn;
+            p = pn;
+        }
+        sh.lam[i] = lam; sh.zoff[i] = zoff; sh.h[i] = h; sh.p[i] = p;
+        sh.pr[i] = pr; sh.ps[i] = ps;
+    }
+    if (tid == 0) {
+        sh.t = t;
+        sh.status = c->status;
+        sh.done = done;
+        sh.bad = c->bad_input;
+        sh.r = c->r;
+        sh.sigma = c->sigma;
+    }
+    __syncthreads();
+    if (tid == 0 && fin) {
+        if (chk) {
+            double r = sh.rdem, sg = P.rho3 * sh.sig3;
+            for (int i = 0; i < m; ++i) { r = fmax(r, sh.pr[i]); sg = fmax(sg, sh.ps[i]); }
+            sh.r = r;
+            sh.sigma = sg;
+            if (!(r == r) || !(sg == sg)) { sh.status = -4; sh.done = 1; }
+            else if (r < P.eps_p && sg < P.eps_d) { sh.status = 0; sh.done = 1; }
+        }
+        if (!sh.done && t >= P.max_iter) { sh.status = 2; sh.done = 1; }
+    }
+    __syncthreads();
+}
+
+// Writes the state in `sh` into slot `ws` (one block).
+template <int MAXM>
+__device__ __forceinline__ void chain_store(const SolveParams &P, int ws, const ChainShared<MAXM> &sh,
+                                            int t, int pending, int bad) {
+    const ChainSlot o = chain_slot(P, ws);
+    const int tid = threadIdx.x;
+    if (tid < P.m) {
+        o.lam[tid] = sh.lam[tid];
+        o.zoff[tid] = sh.zoff[tid];
+        o.h[tid] = sh.h[tid];
+        o.p[tid] = sh.p[tid];
+    }
+    if (tid == 0) {
+        Ctrl *c = o.ctrl;
+        c->t = t;
+        c->status = sh.status;
+        c->done = sh.done;
+        c->bad_input = bad;
+        c->r = sh.r;
+        c->sigma = sh.sigma;
+        c->pending = pending;
+    }
+}
+
+// Block sums of one tile's accumulators: wave reductions, then the waves'
+// results in order.  Layout as the split path: g-sum [nblk][m], dg-max,
+// dg-min, then residual maxima [nblk][2].
+template <int MAXM, int NT>
+__device__ __forceinline__ void chain_partials(const SolveParams &P, double *part, int tile, const Acc<MAXM> &acc,
+                                               bool check, double (*red)[3 * MAXM + 2]) {
+    constexpr int NW = NT / 64;
+    const int m = P.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const size_t slab = (size_t)P.nblk * m;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        if (i < m) {
+            const double v = wave_sum(acc.gsum[i]);
+            if (lane == 0) red[wv][i] = v;
+            if (check) {
+                const double a = wave_max(acc.dgmax[i]), b = wave_min(acc.dgmin[i]);
+                if (lane == 0) { red[wv][MAXM + i] = a; red[wv][2 * MAXM + i] = b; }
+            }
+        }
+    }
+    if (check) {
+        const double a = wave_max(acc.rdem), b = wave_max(acc.sig3);
+        if (lane == 0) { red[wv][3 * MAXM] = a; red[wv][3 * MAXM + 1] = b; }
+    }
+    __syncthreads();
+    if (tid < m) {
+        double s = red[0][tid];
+        for (int w = 1; w < NW; ++w) s += red[w][tid];
+        part[(size_t)tile * m + tid] = s;
+        if (check) {
+            double a = red[0][MAXM + tid], b = red[0][2 * MAXM + tid];
+            for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][MAXM + tid]); b = fmin(b, red[w][2 * MAXM + tid]); }
+            part[slab + (size_t)tile * m + tid] = a;
+            part[2 * slab + (size_t)tile * m + tid] = b;
+        }
+    } else if (check && tid == 64) {
+        double a = red[0][3 * MAXM], b = red[0][3 * MAXM + 1];
+        for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][3 * MAXM]); b = fmax(b, red[w][3 * MAXM + 1]); }
+        part[3 * slab + 2 * (size_t)tile] = a;
+        part[3 * slab + 2 * (size_t)tile + 1] = b;
+    }
+}
+
+template <typename T, int MAXM, int MODE, bool CHECK>
+__global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
+    const int ws = rs ^ 1;
+    __shared__ ChainShared<MAXM> sh;
+    __shared__ double red[kChainBlock / 64][3 * MAXM + 2];
+    const Ctrl *cin = rs ? P.ctrl1 : P.ctrl;
+    if (cin->done) {
+        // stopped earlier: carry the final state into the other slot
+        chain_prologue<MAXM, kChainBlock>(P, rs, sh);
+        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad);
+        return;
+    }
+    // the column loads do not depend on the scalars: issue them first so
+    // that their latency overlaps the reads of the partials
+    const int k = blockIdx.x * kChainBlock + threadIdx.x;
+    const bool live = k < P.n;
+    Col<T, MAXM> d;
+    if (live) col_load(P, 0, k, d);
+    chain_prologue<MAXM, kChainBlock>(P, rs, sh);
+    if (sh.done) {
+        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad);
+        return;
+    }
+    Scal<MAXM> sc;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        const int ii = i < P.m ? i : 0;
+        sc.toff[i] = i < P.m ? sh.zoff[ii] + sh.lam[ii] : 0.0;
+        sc.cons[i] = 0.0;
+    }
+    Acc<MAXM> acc;
+    acc.reset();
+    if (live) {
+        col_update<T, MAXM, MODE, CHECK>(P, 0, k, d, sc, acc);
+        col_store(P, 0, k, d);
+    }
+    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red);
+    if (blockIdx.x == 0) {
+        const int t1 = sh.t + 1;
+        const int bad = sh.bad | (((t1 % P.check_every) == 0) != CHECK ? 2 : 0);
+        chain_store<MAXM>(P, ws, sh, t1, 1, bad);
+    }
+}
+
+// Completes a pending iteration in place in slot 0 (one block), after the
+// last chunk of a solve.
+template <int MAXM>
+__global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P) {
+    __shared__ ChainShared<MAXM> sh;
+    chain_prologue<MAXM, kChainBlock>(P, 0, sh);
+    chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad);
 }
 
 // ---------------------------------------------------- persistent resident
@@ -344,6 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_init_final(SolveParams P) {
         P.ctrl->sigma = INFINITY;
         P.ctrl->status = P.max_iter > 0 ? -1 : 2;
         P.ctrl->done = P.max_iter > 0 ? 0 : 1;
+        P.ctrl->pending = 0;
     }
 }
 
@@ -444,34 +694,20 @@ hipError_t launch_copy_calib(const void *src, void *dst, size_t bytes, hipStream
 
 int max_m_supported() { return 8; }
 
-template <typename T, int MODE, int CPT, bool CHECK, bool FUSED>
+template <typename T, int MODE, int CPT, bool CHECK>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
-    else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
-    else k_sweep<T, 8, CPT, MODE, CHECK, FUSED><<<grid, kBlock, 0, s>>>(P);
+    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
+    else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
+    else k_sweep<T, 8, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
 }
 
-template <typename T, int MODE, bool CHECK, bool FUSED>
+template <typename T, int MODE, bool CHECK>
 static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
     switch (P.cpt) {
-    case 1: launch_sweep_c<T, MODE, 1, CHECK, FUSED>(P, s); break;
-    case 2: launch_sweep_c<T, MODE, 2, CHECK, FUSED>(P, s); break;
-    default: launch_sweep_c<T, MODE, 4, CHECK, FUSED>(P, s); break;
-    }
-}
-
-template <bool FUSED>
-static void launch_sweep_f(const SolveParams &P, int dtype, bool check, hipStream_t s) {
-    if (dtype == 0) {
-        if (check) launch_sweep_k<double, MODE_F64, true, FUSED>(P, s);
-        else launch_sweep_k<double, MODE_F64, false, FUSED>(P, s);
-    } else if (dtype == 1) {
-        if (check) launch_sweep_k<float, MODE_MIXED, true, FUSED>(P, s);
-        else launch_sweep_k<float, MODE_MIXED, false, FUSED>(P, s);
-    } else {
-        if (check) launch_sweep_k<float, MODE_F32, true, FUSED>(P, s);
-        else launch_sweep_k<float, MODE_F32, false, FUSED>(P, s);
+    case 1: launch_sweep_c<T, MODE, 1, CHECK>(P, s); break;
+    case 2: launch_sweep_c<T, MODE, 2, CHECK>(P, s); break;
+    default: launch_sweep_c<T, MODE, 4, CHECK>(P, s); break;
     }
 }
 
@@ -479,24 +715,31 @@ static void launch_sweep_f(const SolveParams &P, int dtype, bool check, hipStrea
 // iteration (the caller knows the iteration number: graphs are captured
 // in chunks that start at a multiple of check_every).
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s) {
-    launch_sweep_f<false>(P, dtype, check, s);
+    if (dtype == 0) {
+        if (check) launch_sweep_k<double, MODE_F64, true>(P, s);
+        else launch_sweep_k<double, MODE_F64, false>(P, s);
+    } else if (dtype == 1) {
+        if (check) launch_sweep_k<float, MODE_MIXED, true>(P, s);
+        else launch_sweep_k<float, MODE_MIXED, false>(P, s);
+    } else {
+        if (check) launch_sweep_k<float, MODE_F32, true>(P, s);
+        else launch_sweep_k<float, MODE_F32, false>(P, s);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_fused(const SolveParams &P, int dtype, bool check, hipStream_t s) {
-    launch_sweep_f<true>(P, dtype, check, s);
-    return hipGetLastError();
-}
-
-hipError_t launch_quartic_test(int64_t N, const double *A, const double *B, const double *C, const double *D,
-                               const double *lo, const double *hi, int project, int mixed, double *x,
-                               int32_t *codes, hipStream_t s) {
+hipError_t launch_quartics(int64_t N, const double *A, const double *B, const double *C, const double *D,
+                           const double *lo, const double *hi, int project, int precision, double *x,
+                           int32_t *codes, int32_t *bad, hipStream_t s) {
     int64_t g = (N + kBlock - 1) / kBlock;
     if (g > 8192) g = 8192;
     if (g < 1) g = 1;
-    if (mixed == 1) k_quartic<MODE_MIXED><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
-    else if (mixed == 2) k_quartic<MODE_F32><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
-    else k_quartic<MODE_F64><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes);
+    if (precision == 1)
+        k_quartic<MODE_MIXED><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes, bad);
+    else if (precision == 2)
+        k_quartic<MODE_F32><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes, bad);
+    else
+        k_quartic<MODE_F64><<<(unsigned)g, kBlock, 0, s>>>(N, A, B, C, D, lo, hi, project, x, codes, bad);
     return hipGetLastError();
 }
 
@@ -525,21 +768,42 @@ hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int ch
     return hipLaunchCooperativeKernel(fn, dim3(P.nblk * P.q), dim3(kBlock), args, 0, s);
 }
 
+template <typename T, int MODE, bool CHECK>
+static void launch_chain_k(const SolveParams &P, int rs, hipStream_t s) {
+    const dim3 grid(P.nblk);
+    if (P.m <= 2) k_chain<T, 2, MODE, CHECK><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else k_chain<T, 4, MODE, CHECK><<<grid, kChainBlock, 0, s>>>(P, rs);
+}
+
+hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {
+    if (P.m > 4 || P.q != 1 || P.nblk > kChainMaxBlocks) return hipErrorInvalidValue;
+    if (dtype == 0) {
+        if (check) launch_chain_k<double, MODE_F64, true>(P, rs, s);
+        else launch_chain_k<double, MODE_F64, false>(P, rs, s);
+    } else if (dtype == 1) {
+        if (check) launch_chain_k<float, MODE_MIXED, true>(P, rs, s);
+        else launch_chain_k<float, MODE_MIXED, false>(P, rs, s);
+    } else {
+        if (check) launch_chain_k<float, MODE_F32, true>(P, rs, s);
+        else launch_chain_k<float, MODE_F32, false>(P, rs, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s) {
+    if (P.m > 4) return hipErrorInvalidValue;
+    if (P.m <= 2) k_chain_flush<2><<<1, kChainBlock, 0, s>>>(P);
+    else k_chain_flush<4><<<1, kChainBlock, 0, s>>>(P);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
     k_finalize<<<1, kBlock, 0, s>>>(P);
     return hipGetLastError();
 }
 
-// One iteration: sweep + finalize launches (default), or the fused sweep
-// whose last block runs the scalar steps (ADMM_FUSED=1).  On MI355X the
-// fused form is slower: every block's release fence writes back its XCD's
-// dirty L2 lines (the sweep's x and w) before the arrival atomic.
+// One iteration of the split path: sweep + finalize launches.
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s) {
-    static const bool fused = [] {
-        const char *e = std::getenv("ADMM_FUSED");
-        return e && e[0] == '1';
-    }();
-    if (fused) return launch_sweep_fused(P, dtype, check, s);
     hipError_t e = launch_sweep(P, dtype, check, s);
     if (e != hipSuccess) return e;
     return launch_finalize(P, s);

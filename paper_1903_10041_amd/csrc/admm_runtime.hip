@@ -90,6 +90,8 @@ admm_status validate_settings(const admm_settings *s) {
         return fail(ADMM_E_INVALID_ARG, "unknown xstep");
     if (s->sweep != ADMM_SWEEP_GAUSS_SEIDEL && s->sweep != ADMM_SWEEP_JACOBI)
         return fail(ADMM_E_INVALID_ARG, "unknown sweep");
+    if (s->launch < ADMM_LAUNCH_AUTO || s->launch > ADMM_LAUNCH_RESIDENT)
+        return fail(ADMM_E_INVALID_ARG, "unknown launch path");
     return ADMM_OK;
 }
 
@@ -143,6 +145,7 @@ extern "C" void admm_default_settings(admm_settings *s) {
     s->precision = ADMM_F64;
     s->xstep = ADMM_XSTEP_EXACT_BOX;
     s->sweep = ADMM_SWEEP_GAUSS_SEIDEL;
+    s->launch = ADMM_LAUNCH_AUTO;
 }
 
 extern "C" admm_status admm_create(admm_context **out, int device, size_t budget,
@@ -252,17 +255,12 @@ int sweep_cpt(int n, int q) {
 }
 
 // Columns per thread of the persistent resident path, or 0 when the
-// problem does not fit the co-resident grid (then the graph path runs).
-// One block per tile of 256 R columns; the smallest R whose grid fits.
-// ADMM_PATH=graph forces the graph path.
-int persist_columns(admm_context *ctx, int dtype, int m, int n, int q) {
-    static const bool graph_only = [] {
-        const char *e = std::getenv("ADMM_PATH");
-        return e && std::string(e) == "graph";
-    }();
-    if (graph_only || !ctx->coop) return 0;
-    // the grid barrier costs tens of microseconds on a full grid; the
-    // resident path pays off only for small grids (ADMM_PERSIST_MAX_TILES)
+// problem does not fit the co-resident grid.  One block per tile of 256 R
+// columns; the smallest R whose grid fits.  Under AUTO the resident path is
+// taken only for small grids (ADMM_PERSIST_MAX_TILES, default 16): on a
+// full grid its barrier costs more than a launch boundary.
+int persist_columns(admm_context *ctx, int dtype, int m, int n, int q, bool forced) {
+    if (!ctx->coop) return 0;
     static const long max_tiles = [] {
         const char *e = std::getenv("ADMM_PERSIST_MAX_TILES");
         return e ? std::atol(e) : 16L;
@@ -282,9 +280,16 @@ int persist_columns(admm_context *ctx, int dtype, int m, int n, int q) {
                 nb = 0;
             cap = nb * ctx->num_cu;
         }
-        if (tiles <= cap && tiles <= max_tiles) return R;
+        if (tiles <= cap && (forced || tiles <= max_tiles)) return R;
     }
     return 0;
+}
+
+// The chained path applies to single-scenario problems of up to four
+// sources whose columns fit in kChainMaxBlocks blocks.
+static bool chain_applies(const admm_problem *pr, const admm_settings *s) {
+    return pr->q == 1 && !s->consensus_q1 && pr->m <= 4 &&
+           (pr->n + kChainBlock - 1) / kChainBlock <= kChainMaxBlocks;
 }
 
 int finalize_group(int m, int q, int nblk) {
@@ -305,10 +310,32 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     const int m = pr->m, n = pr->n, q = pr->q;
     const int n_pad = (n + kPad - 1) / kPad * kPad;
     int cpt = sweep_cpt(n, q);
-    const int R = persist_columns(ctx, dtype, m, n, q);
+    int R = 0;
+    bool chain = false;
+    switch (s->launch) {
+    case ADMM_LAUNCH_RESIDENT:
+        R = persist_columns(ctx, dtype, m, n, q, true);
+        if (R == 0) return fail(ADMM_E_UNSUPPORTED, "the resident launch does not fit this problem on the device");
+        break;
+    case ADMM_LAUNCH_CHAINED:
+        if (!chain_applies(pr, s))
+            return fail(ADMM_E_UNSUPPORTED, "the chained launch needs q = 1, no consensus, m <= 4, n <= 524288");
+        chain = true;
+        break;
+    case ADMM_LAUNCH_SPLIT:
+        break;
+    default:
+        R = persist_columns(ctx, dtype, m, n, q, false);
+        chain = R == 0 && chain_applies(pr, s);
+        break;
+    }
     if (R > 0) cpt = R;
+    // the chained grid has kChainBlock columns per block; the cold-start
+    // kernel covers them as kChainBlock / kBlock columns per thread
+    if (chain) cpt = kChainBlock / kBlock;
     const int nblk = (n + kBlock * cpt - 1) / (kBlock * cpt);
     P.persistent = R > 0;
+    P.chain = chain ? 1 : 0;
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     P.group = finalize_group(m, q, nblk);
@@ -329,9 +356,9 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     ENS(W.x, E * T);
     ENS(W.y, K * T);
     ENS(W.w, K * T);
-    ENS(W.scal, (7 * M + m + 3 * (size_t)m) * sizeof(double) + 2 * M * sizeof(double));
-    ENS(W.part, part_doubles(m, q, nblk) * sizeof(double));
-    ENS(W.ctrl, sizeof(Ctrl) + 64);
+    ENS(W.scal, (7 * M + m + 3 * (size_t)m) * sizeof(double) + 2 * M * sizeof(double) + 4 * M * sizeof(double));
+    ENS(W.part, (chain ? 2 : 1) * part_doubles(m, q, nblk) * sizeof(double));
+    ENS(W.ctrl, 2 * sizeof(Ctrl) + 64);
     ENS(W.obj, 1024 * sizeof(double));
     if (pr->g0) ENS(W.g0, E * T);
     if (pr->f0) ENS(W.f0, E * T);
@@ -351,6 +378,9 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.part = (double *)W.part.p;
     P.ctrl = (Ctrl *)W.ctrl.p;
     P.bar = (uint32_t *)((char *)W.ctrl.p + sizeof(Ctrl));
+    P.scal1 = sc + 8 * M + 4 * m;
+    P.ctrl1 = (Ctrl *)((char *)W.ctrl.p + sizeof(Ctrl) + 64);
+    P.part1 = chain ? P.part + part_doubles(m, q, nblk) : nullptr;
     return ADMM_OK;
 }
 
@@ -507,9 +537,11 @@ admm_status load_warm(admm_context *ctx, const admm_problem *pr, const admm_stat
     return ADMM_OK;
 }
 
+// Iterations per captured graph: a multiple of check_every (so every chunk
+// starts at a multiple of it) and even (so a chained chunk ends on slot 0).
 static int chunk_for(int check_every) {
     int c = check_every;
-    while (c < 40) c += check_every;
+    while (c < 40 || (c & 1)) c += check_every;
     return c;
 }
 
@@ -552,7 +584,8 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
         hipGraph_t g;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         for (int c = 0; c < chunk; ++c) {
-            hipError_t e = launch_iteration(P, dtype, (c + 1) % P.check_every == 0, s);
+            const bool check = (c + 1) % P.check_every == 0;
+            hipError_t e = P.chain ? launch_chain(P, dtype, check, c & 1, s) : launch_iteration(P, dtype, check, s);
             if (e != hipSuccess) {
                 hipGraph_t junk;
                 (void)hipStreamEndCapture(s, &junk);
@@ -593,6 +626,8 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
             done = hc[wait_slot].done != 0;
         }
     }
+    // chained: the scalar steps of the last iteration run here
+    if (P.chain && launch_chain_flush(P, s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "flush launch failed"); }
     (void)hipEventRecord(ctx->ev1, s);
     if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "stream sync failed"); }
     cleanup();
@@ -785,17 +820,28 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
     double sw = 0, fi = 0, it = 0;
     // per = 20 launches per graph, two check iterations among them (the
     // check variant of the sweep is used where the iteration count says so)
-    int c1 = 0, c2 = 0, c3 = 0;
-    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, (++c1 % 10) == 0, s); }, &sw)) != ADMM_OK) return st;
-    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, s); }, &fi)) != ADMM_OK) return st;
-    if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, (++c3 % 10) == 0, s); }, &it)) != ADMM_OK) return st;
-    (void)c2;
+    int c1 = 0, c3 = 0;
+    if (P.chain) {
+        // one kernel per iteration: its time is the iteration's; the flush
+        // runs once per solve
+        if ((st = time_graph(ctx, s, reps, per, [&] {
+                 const int c = c1++;
+                 (void)launch_chain(P, dtype, (c + 1) % P.check_every == 0, c & 1, s);
+             }, &sw)) != ADMM_OK) return st;
+        it = sw;
+        fi = 0.0;
+    } else {
+        if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, (++c1 % 10) == 0, s); }, &sw)) != ADMM_OK) return st;
+        if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, s); }, &fi)) != ADMM_OK) return st;
+        if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, (++c3 % 10) == 0, s); }, &it)) != ADMM_OK) return st;
+    }
     out[0] = sw;
     out[1] = fi;
     out[2] = it;
     out[3] = (double)reps * per;
     out[4] = 0.0;
     out[5] = 0.0;
+    out[6] = P.persistent ? 3.0 : (P.chain ? 2.0 : 1.0);
     if (P.persistent) {
         // the resident path: one cooperative launch of `n_it` iterations
         const int n_it = std::max(20, iters);
@@ -821,32 +867,64 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
     return ADMM_OK;
 }
 
-// Element-wise device quartic minimiser over host arrays (tests of the
-// device math against the oracle).
-extern "C" admm_status admm_debug_quartic(admm_context *ctx, int64_t N, const double *A, const double *B,
-                                          const double *C, const double *D, const double *lo, const double *hi,
-                                          int32_t paper_project, int32_t precision, double *x_out,
-                                          int32_t *codes_out) {
-    if (!ctx || !A || !B || !C || !D || !lo || !hi || !x_out || !codes_out || N < 0)
-        return fail(ADMM_E_INVALID_ARG, "NULL argument");
+// Standalone x-step minimiser over N host or device arrays.
+extern "C" admm_status admm_minimize_quartics(admm_context *ctx, int64_t N, admm_memspace mem,
+                                              const double *A, const double *B, const double *C,
+                                              const double *D, const double *lo, const double *hi,
+                                              admm_xstep xstep, admm_precision precision, double *x_out,
+                                              int32_t *codes_out, double *device_ms) {
+    if (!ctx || !A || !B || !C || !D || !lo || !hi || !x_out || N < 0)
+        return fail(ADMM_E_INVALID_ARG, "NULL argument or N < 0");
+    if (mem != ADMM_HOST && mem != ADMM_DEVICE) return fail(ADMM_E_INVALID_ARG, "unknown memspace");
+    if (xstep != ADMM_XSTEP_EXACT_BOX && xstep != ADMM_XSTEP_PAPER_PROJECT)
+        return fail(ADMM_E_INVALID_ARG, "unknown xstep");
+    if (precision != ADMM_F64 && precision != ADMM_F32_MIXED && precision != ADMM_F32)
+        return fail(ADMM_E_INVALID_ARG, "unknown precision");
+    if (device_ms) *device_ms = 0.0;
     if (N == 0) return ADMM_OK;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    hipStream_t s = ctx->own;
-    const size_t bytes = (size_t)N * (7 * sizeof(double) + sizeof(int32_t));
-    admm_status st = ctx->arena.ensure(ctx->ws.staging, bytes);
-    if (st != ADMM_OK) return st;
-    double *d = (double *)ctx->ws.staging.p;
-    const double *src[6] = {A, B, C, D, lo, hi};
-    for (int a = 0; a < 6; ++a)
-        HIPCHK(hipMemcpyAsync(d + (size_t)a * N, src[a], N * sizeof(double), hipMemcpyHostToDevice, s));
-    double *xd = d + 6 * (size_t)N;
-    int32_t *cd = (int32_t *)(d + 7 * (size_t)N);
-    HIPCHK(launch_quartic_test(N, d, d + N, d + 2 * N, d + 3 * N, d + 4 * N, d + 5 * N, paper_project,
-                               precision == ADMM_F32_MIXED, xd, cd, s));
-    HIPCHK(hipMemcpyAsync(x_out, xd, N * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(codes_out, cd, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    const int project = xstep == ADMM_XSTEP_PAPER_PROJECT;
+    admm_status st;
+    if ((st = ctx->arena.ensure(ctx->ws.obj, 1024 * sizeof(double))) != ADMM_OK) return st;
+    int32_t *bad = (int32_t *)ctx->ws.obj.p;
+    hipStream_t s;
+    const double *a, *b, *c, *d, *l, *h;
+    double *xd;
+    int32_t *cd;
+    if (mem == ADMM_DEVICE) {
+        s = ctx->user;
+        a = A; b = B; c = C; d = D; l = lo; h = hi;
+        xd = x_out;
+        cd = codes_out;
+    } else {
+        s = ctx->own;
+        const size_t bytes = (size_t)N * (7 * sizeof(double) + sizeof(int32_t));
+        if ((st = ctx->arena.ensure(ctx->ws.staging, bytes)) != ADMM_OK) return st;
+        double *dd = (double *)ctx->ws.staging.p;
+        const double *src[6] = {A, B, C, D, lo, hi};
+        for (int k = 0; k < 6; ++k)
+            HIPCHK(hipMemcpyAsync(dd + (size_t)k * N, src[k], N * sizeof(double), hipMemcpyHostToDevice, s));
+        a = dd; b = dd + N; c = dd + 2 * N; d = dd + 3 * N; l = dd + 4 * N; h = dd + 5 * N;
+        xd = dd + 6 * (size_t)N;
+        cd = codes_out ? (int32_t *)(dd + 7 * (size_t)N) : nullptr;
+    }
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    HIPCHK(launch_quartics(N, a, b, c, d, l, h, project, (int)precision, xd, cd, bad, s));
+    HIPCHK(hipEventRecord(ctx->ev1, s));
+    if (mem == ADMM_HOST) {
+        HIPCHK(hipMemcpyAsync(x_out, xd, N * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (codes_out) HIPCHK(hipMemcpyAsync(codes_out, cd, N * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    int32_t hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (device_ms) *device_ms = ms;
+    if (hbad) return fail(ADMM_E_INVALID_ARG, "a quartic is outside the minimiser's domain "
+                                              "(A < 0, non-finite value, lo > hi, or A = 0 with C <= 0)");
     return ADMM_OK;
 }
 

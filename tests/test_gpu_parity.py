@@ -189,15 +189,95 @@ def test_device_tensor_inputs_match_host(ctx):
 
 def test_full_size_large_case_parity(ctx):
     """m = 4, n = 262144 (the bandwidth case), FP64, 20 iterations: every
-    element against the oracle."""
+    element against the oracle, through the default (chained) launch and
+    the split launch."""
     p = W.large_c2()
-    say("[full-size] m=4 n=262144 fp64, 20 iterations")
-    x, info, _ = ctx.solve(p, fixed(p, 20))
     st, oinfo, _ = oracle.run(p, max_iter=20, nthreads=8)
-    dx = float(np.abs(x - st["x"]).max())
+    for launch in (admm.LAUNCH_AUTO, admm.LAUNCH_SPLIT):
+        say(f"[full-size] m=4 n=262144 fp64, 20 iterations, launch {launch}")
+        x, info, _ = ctx.solve(p, fixed(p, 20, launch=launch))
+        dx = float(np.abs(x - st["x"]).max())
+        rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
+        say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
+        assert info["iters"] == 20
+        assert dx <= 1e-9 and rel <= 1e-10
+
+
+# ------------------------------------------------------------ launch paths
+# The three ways of issuing the iterations must each follow the oracle.
+LAUNCH_CASES = {
+    "c1": lambda: W.small_c1(),
+    "c1_binding": lambda: binding(),
+    "stress": lambda: W.stress(),
+    "ragged_n257_m3": lambda: binding(seed=5, n=257, m=3),
+    "n1": lambda: W.uniform_problem(2, 1, 9),
+    "m1": lambda: W.uniform_problem(1, 130, 10, cap_fraction=0.3),
+    "ragged_n70001_m4": lambda: W.uniform_problem(4, 70001, 11, cap_fraction=0.4),
+}
+LAUNCHES = {"split": admm.LAUNCH_SPLIT, "chained": admm.LAUNCH_CHAINED, "resident": admm.LAUNCH_RESIDENT}
+
+
+@pytest.mark.parametrize("launch", list(LAUNCHES))
+@pytest.mark.parametrize("name", list(LAUNCH_CASES))
+def test_launch_path_trajectory(ctx, name, launch):
+    p = LAUNCH_CASES[name]()
+    iters = 200 if p.n > 10000 else 500
+    if launch == "resident" and p.n > 10000:
+        pytest.skip("the resident launch only takes grids that fit on the device at once")
+    say(f"[launch] {name} {launch} m={p.m} n={p.n} iters={iters}")
+    x, info, _ = ctx.solve(p, fixed(p, iters, launch=LAUNCHES[launch]))
+    st, oinfo, _ = oracle.run(p, max_iter=iters, nthreads=8)
     rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
-    say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
-    assert dx <= 1e-9 and rel <= 1e-10
+    dx = float(np.abs(x - st["x"]).max())
+    say(f"   rel obj={rel:.2e} max|dx|={dx:.2e} r {info['r']:.6e}/{oinfo['r']:.6e}")
+    assert info["status"] == admm.MAX_ITER and info["iters"] == iters
+    # The horizon sums of (7b) run over n terms in a different order on the
+    # two sides (sequential vs blocked); their FP64 difference is up to
+    # about n eps sum|g|, which over hundreds of iterations moves the
+    # iterates by ~1e-9 when n ~ 1e5.
+    dx_tol = 1e-9 if p.n <= 10000 else 1e-8
+    assert rel <= 1e-9 and dx <= dx_tol
+    for key in ("r", "sigma"):
+        assert abs(info[key] - oinfo[key]) <= 1e-6 * abs(oinfo[key]) + 1e-10, key
+
+
+@pytest.mark.parametrize("launch", list(LAUNCHES))
+def test_launch_path_convergence(ctx, launch):
+    """Same stopping check as the oracle on every launch path, including
+    check_every = 7 (odd: chunks of 42) and iteration caps that end inside
+    a chunk."""
+    for name, ce, cap in (("c1", 10, 100000), ("stress", 7, 100000), ("c1_binding", 10, 37), ("c1", 10, 1)):
+        p = LAUNCH_CASES[name]()
+        s = admm.Settings(rho=tuple(p.rho), max_iter=cap, eps_primal=1e-6, eps_dual=1e-6,
+                          check_every=ce, launch=LAUNCHES[launch])
+        say(f"[launch-converge] {name} {launch} check_every={ce} max_iter={cap}")
+        x, info, _ = ctx.solve(p, s)
+        st, oinfo, _ = oracle.run(p, max_iter=cap, eps_primal=1e-6, eps_dual=1e-6, check_every=ce)
+        say(f"   iters gpu={info['iters']} oracle={oinfo['iters']} status {info['status']}/{oinfo['status']}")
+        assert info["iters"] == oinfo["iters"] or (oinfo["status"] == 0 and abs(info["iters"] - oinfo["iters"]) <= ce)
+        assert (info["status"] == admm.OK) == (oinfo["status"] == 0)
+        assert float(np.abs(x - st["x"]).max()) <= 1e-8
+
+
+def test_chained_resume_is_bit_exact(ctx):
+    p = W.uniform_problem(3, 5000, 12)
+    say("[chained-resume] m=3 n=5000: 300 = 170 + 130")
+    s = lambda it: fixed(p, it, launch=admm.LAUNCH_CHAINED)
+    xa, ia, sa = ctx.solve(p, s(300), want_state=True)
+    xb, ib, sb = ctx.solve(p, s(170), want_state=True)
+    xc, ic, sc = ctx.solve(p, s(130), warm=sb, want_state=True)
+    assert np.array_equal(xa, xc)
+    for k in ("h", "p", "lambda_s", "zoff_s", "s", "mu"):
+        assert np.array_equal(sa[k], sc[k]), k
+
+
+def test_launch_path_unsupported(ctx):
+    for p, launch in ((W.phev_c4(seed=7, q=5, n=60), admm.LAUNCH_CHAINED),
+                      (W.uniform_problem(5, 100, 3), admm.LAUNCH_CHAINED),
+                      (W.uniform_problem(2, 600000, 3), admm.LAUNCH_CHAINED)):
+        with pytest.raises(admm.AdmmError) as e:
+            ctx.solve(p, fixed(p, 10, launch=launch))
+        assert e.value.status == admm.E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("prec", [admm.F32_MIXED, admm.F32])

@@ -97,3 +97,36 @@ def test_device_quartic_f32(ctx, kind):
     tol = 2e-5 * (1 + np.abs(xo) + b3)
     print(f"   max err/tol {np.max(err[firm_b] / tol[firm_b]):.3f}", flush=True)
     assert np.all((err <= tol) | ~firm_b)
+
+
+def test_device_arrays_match_host_arrays(ctx):
+    """The minimiser on torch device arrays (in place, no copies) gives the
+    host-array results bit for bit, at a size spanning many blocks with a
+    ragged tail."""
+    import torch
+    rng = np.random.default_rng(94)
+    N = 1_000_003
+    A, B, C, D, lo, hi = _random_quartics(rng, N, "stress")
+    xh, ch, _ = admm.minimize_quartics(ctx, A, B, C, D, lo, hi)
+    dev = torch.device("cuda:0")
+    td = [torch.from_numpy(np.ascontiguousarray(v)).to(dev) for v in (A, B, C, D, lo, hi)]
+    xd, cd, ms = admm.minimize_quartics(ctx, *td)
+    torch.cuda.synchronize()
+    assert np.array_equal(xh, xd.cpu().numpy()) and np.array_equal(ch, cd.cpu().numpy())
+    assert ms > 0.0
+
+
+def test_minimiser_rejects_out_of_domain(ctx):
+    A = np.array([1.0, -1.0, 0.0, 1.0, 1.0])
+    B = np.zeros(5)
+    C = np.array([1.0, 1.0, -1.0, 1.0, 1.0])
+    D = np.array([0.5, 0.5, 0.5, np.nan, 0.5])
+    lo = np.array([-1.0, -1.0, -1.0, -1.0, 2.0])
+    hi = np.array([1.0, 1.0, 1.0, 1.0, 1.0])
+    with pytest.raises(admm.AdmmError) as e:
+        admm.minimize_quartics(ctx, A, B, C, D, lo, hi)
+    assert e.value.status == admm.E_INVALID_ARG
+    # the valid element alone succeeds; infinite bounds are allowed
+    x, c, _ = admm.minimize_quartics(ctx, A[:1], B[:1], C[:1], D[:1], np.array([-np.inf]), np.array([np.inf]))
+    xo, co, _ = oracle.quartic_min(A[:1], B[:1], C[:1], D[:1], np.array([-np.inf]), np.array([np.inf]))
+    assert abs(x[0] - xo[0]) <= 1e-14 and c[0] // 3 == co[0] // 3
