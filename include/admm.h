@@ -131,6 +131,16 @@ typedef struct {
     int32_t debug_branch_codes;      /* record per-element branch codes of the last x-step */
     int32_t rho2_per_step;           /* 1: the capacity block uses rho_2 / n (default 0) */
     admm_launch launch;              /* admm_solve's launch path (default AUTO) */
+    /* Adaptive rho (Sec. IV-A, residual balancing): at a check iteration
+     * that does not stop, every rho_i is multiplied by tau when r / sigma >
+     * band_hi * eps_primal / eps_dual and divided by tau when r / sigma <
+     * band_lo * eps_primal / eps_dual (ratio target 1 if a threshold is 0);
+     * the scaled duals mu, lambda, nu, p are divided by the same factor, so
+     * the unscaled multipliers do not change.  admm_solve only (batched
+     * instances with it run through admm_solve; admm_submit refuses it).
+     * Defaults 0, 1.1, 1.2, 0.8; tau > 1, 0 < band_lo <= band_hi. */
+    int32_t adaptive_rho;
+    double tau, band_hi, band_lo;
 } admm_settings;
 
 /* Iterate of (7a)-(7i), in the paper's variables, host doubles.  Any NULL
@@ -157,11 +167,13 @@ typedef struct {
     double objective;                /* (1/q) sum f(x), f0 included */
     int64_t branch_count[15];        /* 3*branch + clamp, last x-step; debug only */
     double device_ms, total_ms;      /* iteration time on device; whole call */
+    double rho[4];                   /* rho_1..rho_4 at the end (rho_2 / n when rho2_per_step;
+                                      * changed by adaptive rho); resume a solve with these */
 } admm_info;
 
 /* Defaults: rho = 1, eps = 1e-6, max_iter = 10000, check_every = 10, F64,
  * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes,
- * rho2_per_step = 0, launch AUTO.  rho2_per_step scales the penalty of the capacity
+ * rho2_per_step = 0, launch AUTO, adaptive_rho = 0 (tau 1.1, bands 1.2 / 0.8).  rho2_per_step scales the penalty of the capacity
  * constraint sum_k z_k = h (one constraint over n terms) by 1/n per
  * instance; with rho_2 = rho_1 the iteration count grows about linearly in
  * n, with rho_2 = rho_1 / n it stays near a hundred for any n. */

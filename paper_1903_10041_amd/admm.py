@@ -53,7 +53,8 @@ class admm_settings(C.Structure):
                 ("check_every", C.c_int32), ("precision", C.c_int),
                 ("xstep", C.c_int), ("sweep", C.c_int), ("consensus_q1", C.c_int32),
                 ("debug_branch_codes", C.c_int32), ("rho2_per_step", C.c_int32),
-                ("launch", C.c_int)]
+                ("launch", C.c_int), ("adaptive_rho", C.c_int32), ("tau", C.c_double),
+                ("band_hi", C.c_double), ("band_lo", C.c_double)]
 
 
 class admm_state(C.Structure):
@@ -65,7 +66,7 @@ class admm_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("r", C.c_double),
                 ("sigma", C.c_double), ("objective", C.c_double),
                 ("branch_count", C.c_int64 * 15), ("device_ms", C.c_double),
-                ("total_ms", C.c_double)]
+                ("total_ms", C.c_double), ("rho", C.c_double * 4)]
 
 
 _lib = None
@@ -136,6 +137,10 @@ class Settings:
     debug_branch_codes: bool = False
     rho2_per_step: bool = False
     launch: int = LAUNCH_AUTO
+    adaptive_rho: bool = False
+    tau: float = 1.1
+    band_hi: float = 1.2
+    band_lo: float = 0.8
 
     def to_c(self) -> admm_settings:
         return admm_settings((C.c_double * 4)(*[float(r) for r in self.rho]),
@@ -143,7 +148,8 @@ class Settings:
                              int(self.check_every), int(self.precision), int(self.xstep),
                              int(self.sweep), int(bool(self.consensus_q1)),
                              int(bool(self.debug_branch_codes)), int(bool(self.rho2_per_step)),
-                             int(self.launch))
+                             int(self.launch), int(bool(self.adaptive_rho)), float(self.tau),
+                             float(self.band_hi), float(self.band_lo))
 
 
 def _is_torch(a) -> bool:
@@ -219,7 +225,7 @@ def _state_struct(d: Optional[dict], keep: list):
 def info_dict(inf: admm_info) -> dict:
     return {"status": inf.status, "iters": inf.iters, "r": inf.r, "sigma": inf.sigma,
             "objective": inf.objective, "branch_count": np.array(list(inf.branch_count)),
-            "device_ms": inf.device_ms, "total_ms": inf.total_ms}
+            "device_ms": inf.device_ms, "total_ms": inf.total_ms, "rho": tuple(inf.rho)}
 
 
 class Context:

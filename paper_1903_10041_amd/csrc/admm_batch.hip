@@ -356,6 +356,7 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
         inf.objective = I.objective;
         inf.device_ms = ms;
         inf.total_ms = total;
+        for (int k = 0; k < 4; ++k) inf.rho[k] = I.rho[k];
     }
     BCHK(hipEventRecord(ctx->join, s));
     BCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
@@ -384,11 +385,11 @@ extern "C" admm_status admm_solve_batch(admm_context *ctx, int32_t count, const 
             return fail(ADMM_E_INVALID_ARG, "all batch instances must share one memspace and dtype");
     }
     // instances outside the batched kernel (q > 1, g0/f0, per-step bounds,
-    // warm states) are solved one by one through the plain path
+    // warm states, adaptive rho) are solved one by one through the plain path
     std::vector<int> in_batch, alone;
     for (int b = 0; b < count; ++b) {
         const bool w = warm && warm[b] && warm[b]->x;
-        (batchable(probs[b]) && !w ? in_batch : alone).push_back(b);
+        (batchable(probs[b]) && !w && !S.adaptive_rho ? in_batch : alone).push_back(b);
     }
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -854,6 +855,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
             inf.r = I.r;
             inf.sigma = I.sigma;
             inf.objective = I.objective;
+            for (int k = 0; k < 4; ++k) inf.rho[k] = I.rho[k];
             std::vector<char> xb((size_t)r->m * r->n_pad * T);
             if (!dev_ok(hipMemcpyAsync(xb.data(), base + r->x_b, xb.size(), hipMemcpyDeviceToHost, s), "readback"))
                 return false;
@@ -977,6 +979,7 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     if (prob->mem != ADMM_HOST) return fail(ADMM_E_UNSUPPORTED, "admm_submit takes host arrays");
     if (!batchable(*prob))
         return fail(ADMM_E_UNSUPPORTED, "admm_submit serves q = 1 instances with per-source bounds and no g0/f0");
+    if (S.adaptive_rho) return fail(ADMM_E_UNSUPPORTED, "admm_submit runs with fixed rho");
     const int dtype = (int)S.precision;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);

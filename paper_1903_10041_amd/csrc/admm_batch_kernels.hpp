@@ -62,6 +62,10 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.rho3 = I.rho[2];
     P.rho4 = I.rho[3];
     P.inv_q = 1.0;
+    P.adaptive = 0;
+    P.tau = P.band_hi = P.band_lo = 1.0;
+    P.wdiv = 1.0;
+    P.rho_cur = nullptr;
     P.eps_p = I.eps_p;
     P.eps_d = I.eps_d;
     P.coef = nullptr;
@@ -137,7 +141,7 @@ __device__ __forceinline__ void block_max_rows(int rows, const double *v, double
 template <typename T, int MAXM, int MODE>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
     __shared__ double lds[MAXM + 2][kBlock];
-    __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM];
+    __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM], s_lo[MAXM], s_hi[MAXM];
     __shared__ double s_sum[MAXM], s_max[MAXM + 2], s_min[MAXM];
     __shared__ double s_r, s_sg;
     __shared__ int s_idx, s_stop, s_t;
@@ -161,6 +165,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
             s_h[tid] = P.h[tid];
             s_p[tid] = P.p[tid];
             s_cap[tid] = P.cap[tid];
+            s_lo[tid] = P.slo[tid];
+            s_hi[tid] = P.shi[tid];
         }
         if (tid == 0) {
             s_stop = 0;
@@ -181,6 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
             for (int i = 0; i < MAXM; ++i) {
                 sc.toff[i] = i < m ? s_zoff[i] + s_lam[i] : 0.0;
                 sc.cons[i] = 0.0;
+                sc.lo[i] = s_lo[i < m ? i : 0];
+                sc.hi[i] = s_hi[i < m ? i : 0];
             }
             Acc<MAXM> acc;
             acc.reset();
@@ -188,14 +196,14 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
                 for (int k = tid; k < n; k += kBlock) {
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
-                    col_update<T, MAXM, MODE, true>(P, 0, k, d, sc, acc);
+                    col_update<T, MAXM, MODE, true, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
                     col_store(P, 0, k, d);
                 }
             } else {
                 for (int k = tid; k < n; k += kBlock) {
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
-                    col_update<T, MAXM, MODE, false>(P, 0, k, d, sc, acc);
+                    col_update<T, MAXM, MODE, false, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
                     col_store(P, 0, k, d);
                 }
             }

@@ -46,6 +46,16 @@ __device__ __forceinline__ double group_min(double v, int G) {
 template <typename T>
 __device__ __forceinline__ double st_round(double v) { return (double)(T)v; }
 
+// A value known to be the same in every lane of the wave, moved to scalar
+// registers: block-wide scalars read from LDS or global memory otherwise
+// occupy vector registers for the whole sweep.
+__device__ __forceinline__ double uniform(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // ---------------------------------------------------------------- sweep
 
 // x-step quartic coefficients (7a) in the theta/phi form:
@@ -57,10 +67,24 @@ __device__ __forceinline__ double st_round(double v) { return (double)(T)v; }
 // back to the FP64 closed form near repeated roots and for three real roots.
 enum { MODE_F64 = 0, MODE_MIXED = 1, MODE_F32 = 2 };
 
-template <int MODE>
+// Optional features of the column update.  A kernel compiled without one
+// never reads its launch parameters: fewer live scalar registers and no
+// branches in the x-step chain.  F_ALL decides each at run time.
+enum : int {
+    F_G0 = 1,         // g0 array
+    F_PERSTEP = 2,    // per-step bounds
+    F_CODES = 4,      // branch codes recorded
+    F_JACOBI = 8,     // Jacobi sweep over sources
+    F_PROJECT = 16,   // PAPER_PROJECT box rule
+    F_CONS = 32,      // consensus (x_1 recorded, rho_4 terms)
+    F_ALL = 63
+};
+
+template <int MODE, int FEAT = F_ALL>
 __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double f1, double g2, double g1,
                                         double tg, double phi, bool first_step, double cons,
                                         double lo, double hi, int &code) {
+    const int project = (FEAT & F_PROJECT) ? P.xstep_project : 0;
     if (MODE == MODE_F32) {
         const float r1 = (float)P.rho1, r3 = (float)P.rho3;
         const float g2f = (float)g2, g1f = (float)g1, tgf = (float)tg;
@@ -83,13 +107,13 @@ __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double 
         C += 0.5 * P.rho4;
         D -= P.rho4 * cons;
     }
-    if (MODE == MODE_MIXED) return qmin_mixed(A, B, C, D, lo, hi, P.xstep_project, code);
+    if (MODE == MODE_MIXED) return qmin_mixed(A, B, C, D, lo, hi, project, code);
     if (MODE == MODE_F32) {
-        const QRes r = qmin_f64_call(A, B, C, D, lo, hi, P.xstep_project);
+        const QRes r = qmin_f64_call(A, B, C, D, lo, hi, project);
         code = r.code;
         return r.x;
     }
-    return qmin_f64(A, B, C, D, lo, hi, P.xstep_project, code);
+    return qmin_f64(A, B, C, D, lo, hi, project, code);
 }
 
 // The data of one column (j, k): coefficients and x of every source, y, w.
@@ -145,12 +169,33 @@ __device__ __forceinline__ void col_store(const SolveParams &P, int j, int k, co
         if (i < P.m) X[((size_t)j * P.m + i) * P.n_pad + k] = d.x[i];
 }
 
-// Per-(i, j) scalars the sweep needs: theta_k = g(x_k) + toff, and the
-// consensus target x_1 + nu at k = 1.
+// Adaptive rho: after rho_i *= f the scaled mu is divided by f; mu is the
+// negative part of w = s - mu, so only negative w change.
+template <typename T, int MAXM>
+__device__ __forceinline__ void col_rescale_mu(Col<T, MAXM> &d, double f) {
+    const double w = (double)d.w;
+    if (w < 0.0) d.w = (T)(w / f);
+}
+
+// Per-(i, j) scalars the sweep needs: theta_k = g(x_k) + toff, the
+// consensus target x_1 + nu at k = 1, and the per-source box.  Held in
+// registers for the whole launch: a bound read next to the x-step would be
+// a memory round trip inside each source's dependent chain.
 template <int MAXM>
 struct Scal {
-    double toff[MAXM], cons[MAXM];
+    double toff[MAXM], cons[MAXM], lo[MAXM], hi[MAXM];
 };
+
+// Per-source bounds (used when the problem has no per-step bounds).
+template <int MAXM>
+__device__ __forceinline__ void scal_bounds(const double *slo, const double *shi, int m, Scal<MAXM> &sc) {
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        const int ii = i < m ? i : m - 1;
+        sc.lo[i] = slo[ii];
+        sc.hi[i] = shi[ii];
+    }
+}
 
 template <int MAXM, bool COHERENT>
 __device__ __forceinline__ double ld_scalar(const double *p) {
@@ -170,6 +215,7 @@ __device__ __forceinline__ void scal_load(const SolveParams &P, int j, Scal<MAXM
         sc.toff[i] = i < P.m ? t : 0.0;
         sc.cons[i] = (i < P.m && P.consensus) ? c : 0.0;
     }
+    scal_bounds<MAXM>(P.slo, P.shi, P.m, sc);
 }
 
 // Block-level accumulators of one tile.
@@ -188,7 +234,7 @@ struct Acc {
 // One column: the x-step (7a) for every source in turn (Gauss-Seidel, or
 // Jacobi by flag), then the s- and mu-steps (7e)-(7f) through w = s - mu,
 // accumulating sum_k g(x_k) per source and the residual trackers.
-template <typename T, int MAXM, int MODE, bool CHECK>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT = F_ALL>
 __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, Col<T, MAXM> &d,
                                            const Scal<MAXM> &sc, Acc<MAXM> &acc) {
     const int m = P.m;
@@ -196,7 +242,9 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
     const double w = (double)d.w;
     const double s_old = fmax(w, 0.0), mu_old = fmax(-w, 0.0);
     const double sm = s_old + mu_old;
-    const T *G0 = (const T *)P.g0;
+    const T *G0 = (FEAT & F_G0) ? (const T *)P.g0 : nullptr;
+    const bool jacobi = (FEAT & F_JACOBI) && P.jacobi;
+    const bool cons = (FEAT & F_CONS) && P.consensus;
     double xo[MAXM], xc[MAXM];
     double sum_old = 0.0;
 #pragma unroll
@@ -212,27 +260,27 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
             const size_t e = ((size_t)j * m + i) * P.n_pad + k;
             const double g0 = G0 ? (double)G0[e] : 0.0;
             double lo, hi;
-            if (P.blo) {
+            if ((FEAT & F_PERSTEP) && P.blo) {
                 lo = (double)((const T *)P.blo)[(size_t)i * P.n_pad + k];
                 hi = (double)((const T *)P.bhi)[(size_t)i * P.n_pad + k];
             } else {
-                lo = P.slo[i];
-                hi = P.shi[i];
+                lo = sc.lo[i];
+                hi = sc.hi[i];
             }
             const double g_old = (g2 * xo[i] + g1) * xo[i] + g0;
             const double theta = g_old + sc.toff[i];
             double others = 0.0;
 #pragma unroll
             for (int l = 0; l < MAXM; ++l)
-                if (l < m && l != i) others += P.jacobi ? xo[l] : xc[l];
+                if (l < m && l != i) others += jacobi ? xo[l] : xc[l];
             const double phi = sm - others + y;
             int code;
-            const double xn = st_round<T>(xstep<MODE>(P, f2, f1, g2, g1, theta - g0, phi,
-                                                       P.consensus && k == 0, sc.cons[i], lo, hi, code));
+            const double xn = st_round<T>(xstep<MODE, FEAT>(P, f2, f1, g2, g1, theta - g0, phi,
+                                                             cons && k == 0, sc.cons[i], lo, hi, code));
             xc[i] = xn;
             d.x[i] = (T)xn;
-            if (P.want_codes) P.codes[e] = (uint8_t)code;
-            if (k == 0) P.x1[j * m + i] = xn;
+            if ((FEAT & F_CODES) && P.want_codes) P.codes[e] = (uint8_t)code;
+            if ((FEAT & F_CONS) && k == 0) P.x1[j * m + i] = xn;
             const double g_new = (g2 * xn + g1) * xn + g0;
             acc.gsum[i] += g_new;
             if (CHECK) {
@@ -300,6 +348,38 @@ __device__ __forceinline__ void block_partials(const SolveParams &P, size_t tile
         }
     }
     __syncthreads();
+}
+
+// ----------------------------------------------------------- adaptive rho
+
+// The rho_i and the pending mu divisor a kernel runs with (adaptive rho
+// keeps them on the device; otherwise the launch parameters hold them).
+template <bool COHERENT>
+__device__ __forceinline__ void adapt_load(SolveParams &Q, const double *rho, const Ctrl *ctrl) {
+    if (!Q.adaptive) return;
+    if (COHERENT) {
+        Q.rho1 = __hip_atomic_load(rho + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Q.rho2 = __hip_atomic_load(rho + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Q.rho3 = __hip_atomic_load(rho + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Q.rho4 = __hip_atomic_load(rho + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Q.wdiv = __hip_atomic_load(&ctrl->wdiv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        Q.rho1 = rho[0];
+        Q.rho2 = rho[1];
+        Q.rho3 = rho[2];
+        Q.rho4 = rho[3];
+        Q.wdiv = ctrl->wdiv;
+    }
+}
+
+// Residual balancing at a check iteration that does not stop (Sec. IV-A):
+// the factor applied to every rho_i (the scaled duals are divided by it).
+__device__ __forceinline__ double adapt_factor(const SolveParams &P, double r, double sigma) {
+    const double target = (P.eps_p > 0.0 && P.eps_d > 0.0) ? P.eps_p / P.eps_d : 1.0;
+    const double ratio = sigma > 0.0 ? r / sigma : INFINITY;
+    if (ratio > P.band_hi * target) return P.tau;
+    if (ratio < P.band_lo * target) return 1.0 / P.tau;
+    return 1.0;
 }
 
 // ------------------------------------------------------------- finalize
@@ -403,12 +483,30 @@ __device__ inline void finalize_body(const SolveParams &P) {
         }
         r = block_max(r, lds);
         sg = block_max(sg, lds);
+        const bool bad = !(r == r) || !(sg == sg);
+        const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
         if (tid == 0) {
             ctrl->r = r;
             ctrl->sigma = sg;
-            if (!(r == r) || !(sg == sg)) { ctrl->status = -4; ctrl->done = 1; }
-            else if (r < P.eps_p && sg < P.eps_d) { ctrl->status = 0; ctrl->done = 1; }
+            if (bad) { ctrl->status = -4; ctrl->done = 1; }
+            else if (stop) { ctrl->status = 0; ctrl->done = 1; }
         }
+        if (P.adaptive) {
+            // r and sg are the same in every thread: so is f
+            const double f = stop ? 1.0 : adapt_factor(P, r, sg);
+            if (f != 1.0) {
+                for (int pi = tid; pi < M; pi += kBlock) {
+                    P.lam[pi] /= f;
+                    P.p[pi] /= f;
+                    P.nu[pi] /= f;
+                }
+                if (tid == 0)
+                    for (int k = 0; k < 4; ++k) P.rho_cur[k] *= f;
+            }
+            if (tid == 0) ctrl->wdiv = f;
+        }
+    } else if (P.adaptive && tid == 0) {
+        ctrl->wdiv = 1.0;
     }
     __syncthreads();
     if (tid == 0) {

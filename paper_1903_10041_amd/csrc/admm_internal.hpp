@@ -22,7 +22,8 @@ struct Ctrl {
     double objective;
     int32_t pending;    // chained path: the last sweep's scalar steps are still to do
     int32_t pad_i;
-    double pad_[2];
+    double wdiv;        // adaptive rho: divide mu by this before the next sweep reads it
+    double pad_;
 };
 static_assert(sizeof(Ctrl) == 64, "Ctrl is one 64-byte line");
 
@@ -43,6 +44,12 @@ struct SolveParams {
     int32_t check_every, max_iter;
     int32_t xstep_project, jacobi, consensus, want_codes;
     double rho1, rho2, rho3, rho4, inv_q, eps_p, eps_d;
+    // adaptive rho (Sec. IV-A): the current rho_1..4 live in rho_cur ([4],
+    // a second [4] for the chained path's other slot); a kernel copies them
+    // into its own rho1..4 and the pending mu divisor into wdiv
+    int32_t adaptive;
+    double tau, band_hi, band_lo, wdiv;
+    double *rho_cur;
     const void *coef;       // vec4 of T
     const void *g0;         // T or null
     const void *f0;         // T or null (objective only)

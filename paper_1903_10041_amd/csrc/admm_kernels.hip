@@ -30,11 +30,13 @@ namespace admm {
 // selects the variant that also tracks the residual terms; it is used only
 // on check iterations.  Kernels for up to four sources are held to 128
 // VGPRs so that four waves fit on each SIMD.
-template <typename T, int MAXM, int CPT, int MODE, bool CHECK>
+template <typename T, int MAXM, int CPT, int MODE, bool CHECK, int FEAT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 4 ? 4 : 2)))
-void k_sweep(SolveParams P) {
-    Ctrl *ctrl = P.ctrl;
+void k_sweep(SolveParams P0) {
+    Ctrl *ctrl = P0.ctrl;
     if (ctrl->done) return;
+    SolveParams P = P0;
+    adapt_load<false>(P, P0.rho_cur, ctrl);
     const int j = blockIdx.y;
     Scal<MAXM> sc;
     scal_load<MAXM, false>(P, j, sc);
@@ -46,7 +48,8 @@ void k_sweep(SolveParams P) {
         if (k < P.n) {
             Col<T, MAXM> d;
             col_load(P, j, k, d);
-            col_update<T, MAXM, MODE, CHECK>(P, j, k, d, sc, acc);
+            if (P.wdiv != 1.0) col_rescale_mu(d, P.wdiv);
+            col_update<T, MAXM, MODE, CHECK, FEAT>(P, j, k, d, sc, acc);
             col_store(P, j, k, d);
         }
     }
@@ -91,8 +94,10 @@ __global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, 
     if (flag) atomicOr(bad, 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P) {
-    if (P.ctrl->done) return;
+__global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P0) {
+    if (P0.ctrl->done) return;
+    SolveParams P = P0;
+    adapt_load<false>(P, P0.rho_cur, P0.ctrl);
     finalize_body(P);
 }
 
@@ -133,96 +138,149 @@ __device__ __forceinline__ ChainSlot chain_slot(const SolveParams &P, int s) {
 template <int MAXM>
 struct ChainShared {
     double lam[MAXM], zoff[MAXM], h[MAXM], p[MAXM];   // state after the pending steps
-    double gsum[MAXM], dgmax[MAXM], dgmin[MAXM];       // partials summed over blocks
-    double pr[MAXM], ps[MAXM];                         // per-source residual terms
-    double rdem, sig3;
     double r, sigma;
+    double rho[4], f;                                  // rho after the pending steps; its change
     int t, status, done, bad;
 };
 
+// Sum / max / min over the first nb entries (stride `stride`) of one
+// partial column, lane-strided then across the wave.  Every load is issued
+// before the first use (nb <= 64 * kChainLoads), so the reduction costs one
+// memory round trip.  The order is fixed: every block gets the same bits.
+constexpr int kChainLoads = kChainMaxBlocks / 64;
+
+__device__ __forceinline__ double wave_part_sum(const double *col, size_t stride, int nb, int lane) {
+    double v[kChainLoads];
+#pragma unroll
+    for (int u = 0; u < kChainLoads; ++u) {
+        const int b = lane + 64 * u;
+        v[u] = b < nb ? col[(size_t)b * stride] : 0.0;
+    }
+#pragma unroll
+    for (int w = 1; w < kChainLoads; w *= 2)
+#pragma unroll
+        for (int u = 0; u < kChainLoads; u += 2 * w) v[u] += v[u + w];
+    return wave_sum(v[0]);
+}
+
+__device__ __forceinline__ double wave_part_max(const double *col, size_t stride, int nb, int lane, double init) {
+    double v = init;
+#pragma unroll
+    for (int u = 0; u < kChainLoads; ++u) {
+        const int b = lane + 64 * u;
+        if (b < nb) v = fmax(v, col[(size_t)b * stride]);
+    }
+    return wave_max(v);
+}
+
+__device__ __forceinline__ double wave_part_min(const double *col, size_t stride, int nb, int lane) {
+    double v = DBL_MAX;
+#pragma unroll
+    for (int u = 0; u < kChainLoads; ++u) {
+        const int b = lane + 64 * u;
+        if (b < nb) v = fmin(v, col[(size_t)b * stride]);
+    }
+    return wave_min(v);
+}
+
 // Completes the pending iteration (if any) from slot rs and partial buffer
-// rs ^ 1 into `sh`.  Ends with a block barrier.
+// rs ^ 1 into `sh`.  Wave i < m reduces source i's partials (and the last
+// wave the residual maxima); after one barrier the first wave's lane i
+// updates source i and the whole wave takes the stop decision; a second
+// barrier publishes `sh`.
 template <int MAXM, int NT>
 __device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, ChainShared<MAXM> &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = P.m, nb = P.nblk;
     const ChainSlot in = chain_slot(P, rs);
     const double *part = rs ? P.part : P.part1;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = P.m, nb = P.nblk;
     const Ctrl *c = in.ctrl;
     const int t = c->t, pending = c->pending, done = c->done;
     const bool fin = pending && !done;
     const bool chk = fin && (t % P.check_every) == 0;
     const size_t slab = (size_t)nb * m;
+    // the per-source state, read early by the lanes that update it
+    const int li = lane < m ? lane : 0;
+    double lam = 0.0, zoff = 0.0, h = 0.0, p = 0.0;
+    if (wv == 0) { lam = in.lam[li]; zoff = in.zoff[li]; h = in.h[li]; p = in.p[li]; }
+    __shared__ double red[MAXM][3];
+    __shared__ double rres[2];
     if (fin) {
         if (wv < m) {
-            const int i = wv;
-            double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
-            for (int b = lane; b < nb; b += 64) {
-                s += part[(size_t)b * m + i];
-                if (chk) {
-                    mx = fmax(mx, part[slab + (size_t)b * m + i]);
-                    mn = fmin(mn, part[2 * slab + (size_t)b * m + i]);
-                }
+            const double sum = wave_part_sum(part + wv, m, nb, lane);
+            double mx = 0.0, mn = 0.0;
+            if (chk) {
+                mx = wave_part_max(part + slab + wv, m, nb, lane, -DBL_MAX);
+                mn = wave_part_min(part + 2 * slab + wv, m, nb, lane);
             }
-            s = wave_sum(s);
-            if (chk) { mx = wave_max(mx); mn = wave_min(mn); }
-            if (lane == 0) { sh.gsum[i] = s; sh.dgmax[i] = mx; sh.dgmin[i] = mn; }
+            if (lane == 0) { red[wv][0] = sum; red[wv][1] = mx; red[wv][2] = mn; }
         } else if (wv == NT / 64 - 1 && chk) {
-            double r = 0.0, sg = 0.0;
-            for (int b = lane; b < nb; b += 64) {
-                r = fmax(r, part[3 * slab + 2 * (size_t)b]);
-                sg = fmax(sg, part[3 * slab + 2 * (size_t)b + 1]);
-            }
-            r = wave_max(r);
-            sg = wave_max(sg);
-            if (lane == 0) { sh.rdem = r; sh.sig3 = sg; }
+            const double a = wave_part_max(part + 3 * slab, 2, nb, lane, 0.0);
+            const double b = wave_part_max(part + 3 * slab + 1, 2, nb, lane, 0.0);
+            if (lane == 0) { rres[0] = a; rres[1] = b; }
         }
     }
     __syncthreads();
-    if (tid < m) {
-        const int i = tid;
-        double lam = in.lam[i], zoff = in.zoff[i], h = in.h[i], p = in.p[i];
+    if (wv == 0) {
+        double rho[4] = {P.rho1, P.rho2, P.rho3, P.rho4};
+        if (P.adaptive)
+            for (int k = 0; k < 4; ++k) rho[k] = P.rho_cur[4 * rs + k];
         double pr = 0.0, ps = 0.0;
-        if (fin) {
+        if (fin && lane < m) {
             const double nd = (double)P.n;
-            const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
-            const double W = sh.gsum[i] - nd * lam;          // 1'(g(x) - lambda)
+            const double kfac = rho[1] / (rho[0] + nd * rho[1]);
+            const double W = red[lane][0] - nd * lam;        // 1'(g(x) - lambda)
             const double kap = kfac * (h + p - W);
             const double sumz = W + nd * kap;                // 1'z
             const double zn = kap - lam;                     // z - g(x)
-            const double hn = fmin(P.cap[i], sumz - p);
+            const double hn = fmin(P.cap[lane], sumz - p);
             const double pn = p + hn - sumz;
             if (chk) {
                 const double cz = zn - zoff;
                 pr = fmax(fabs(zn), fabs(hn - sumz));
-                ps = fmax(P.rho1 * fmax(fabs(sh.dgmax[i] + cz), fabs(sh.dgmin[i] + cz)), P.rho2 * fabs(hn - h));
+                ps = fmax(rho[0] * fmax(fabs(red[lane][1] + cz), fabs(red[lane][2] + cz)),
+                          rho[1] * fabs(hn - h));
             }
             lam = kap;
             zoff = zn;
             h = hn;
             p = pn;
         }
-        sh.lam[i] = lam; sh.zoff[i] = zoff; sh.h[i] = h; sh.p[i] = p;
-        sh.pr[i] = pr; sh.ps[i] = ps;
-    }
-    if (tid == 0) {
-        sh.t = t;
-        sh.status = c->status;
-        sh.done = done;
-        sh.bad = c->bad_input;
-        sh.r = c->r;
-        sh.sigma = c->sigma;
-    }
-    __syncthreads();
-    if (tid == 0 && fin) {
-        if (chk) {
-            double r = sh.rdem, sg = P.rho3 * sh.sig3;
-            for (int i = 0; i < m; ++i) { r = fmax(r, sh.pr[i]); sg = fmax(sg, sh.ps[i]); }
+        // the stop decision and the rho change, the same in every lane
+        int status = c->status, dn = done;
+        double r = c->r, sg = c->sigma, f = 1.0;
+        if (fin) {
+            if (chk) {
+                r = fmax(rres[0], wave_max(pr));
+                sg = fmax(rho[2] * rres[1], wave_max(ps));
+                const bool bad = !(r == r) || !(sg == sg);
+                const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
+                if (bad) { status = -4; dn = 1; }
+                else if (stop) { status = 0; dn = 1; }
+                if (P.adaptive && !stop) f = adapt_factor(P, r, sg);
+            }
+            if (!dn && t >= P.max_iter) { status = 2; dn = 1; }
+        }
+        if (f != 1.0) {
+            // the scaled duals follow the change of rho (mu on its next read)
+            lam /= f;
+            p /= f;
+        }
+        if (lane < m) {
+            sh.lam[lane] = lam;
+            sh.zoff[lane] = zoff;
+            sh.h[lane] = h;
+            sh.p[lane] = p;
+        }
+        if (lane < 4) sh.rho[lane] = rho[lane] * f;
+        if (lane == 0) {
+            sh.t = t;
+            sh.status = status;
+            sh.done = dn;
+            sh.bad = c->bad_input;
             sh.r = r;
             sh.sigma = sg;
-            if (!(r == r) || !(sg == sg)) { sh.status = -4; sh.done = 1; }
-            else if (r < P.eps_p && sg < P.eps_d) { sh.status = 0; sh.done = 1; }
+            sh.f = f;
         }
-        if (!sh.done && t >= P.max_iter) { sh.status = 2; sh.done = 1; }
     }
     __syncthreads();
 }
@@ -230,7 +288,7 @@ __device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, Cha
 // Writes the state in `sh` into slot `ws` (one block).
 template <int MAXM>
 __device__ __forceinline__ void chain_store(const SolveParams &P, int ws, const ChainShared<MAXM> &sh,
-                                            int t, int pending, int bad) {
+                                            int t, int pending, int bad, double wdiv) {
     const ChainSlot o = chain_slot(P, ws);
     const int tid = threadIdx.x;
     if (tid < P.m) {
@@ -239,7 +297,9 @@ __device__ __forceinline__ void chain_store(const SolveParams &P, int ws, const 
         o.h[tid] = sh.h[tid];
         o.p[tid] = sh.p[tid];
     }
+    if (P.adaptive && tid < 4) P.rho_cur[4 * ws + tid] = sh.rho[tid];
     if (tid == 0) {
+        o.ctrl->wdiv = wdiv;
         Ctrl *c = o.ctrl;
         c->t = t;
         c->status = sh.status;
@@ -294,7 +354,7 @@ __device__ __forceinline__ void chain_partials(const SolveParams &P, double *par
     }
 }
 
-template <typename T, int MAXM, int MODE, bool CHECK>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT>
 __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     const int ws = rs ^ 1;
     __shared__ ChainShared<MAXM> sh;
@@ -303,7 +363,7 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     if (cin->done) {
         // stopped earlier: carry the final state into the other slot
         chain_prologue<MAXM, kChainBlock>(P, rs, sh);
-        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad);
+        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad, cin->wdiv);
         return;
     }
     // the column loads do not depend on the scalars: issue them first so
@@ -314,8 +374,17 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     if (live) col_load(P, 0, k, d);
     chain_prologue<MAXM, kChainBlock>(P, rs, sh);
     if (sh.done) {
-        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad);
+        // a mu divisor decided here stays pending for the export
+        if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad, sh.f);
         return;
+    }
+    SolveParams Q = P;
+    if (P.adaptive) {
+        Q.rho1 = uniform(sh.rho[0]);
+        Q.rho2 = uniform(sh.rho[1]);
+        Q.rho3 = uniform(sh.rho[2]);
+        Q.rho4 = uniform(sh.rho[3]);
+        Q.wdiv = uniform(sh.f);
     }
     Scal<MAXM> sc;
 #pragma unroll
@@ -324,17 +393,19 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
         sc.toff[i] = i < P.m ? sh.zoff[ii] + sh.lam[ii] : 0.0;
         sc.cons[i] = 0.0;
     }
+    scal_bounds<MAXM>(P.slo, P.shi, P.m, sc);
     Acc<MAXM> acc;
     acc.reset();
     if (live) {
-        col_update<T, MAXM, MODE, CHECK>(P, 0, k, d, sc, acc);
-        col_store(P, 0, k, d);
+        if (Q.wdiv != 1.0) col_rescale_mu(d, Q.wdiv);
+        col_update<T, MAXM, MODE, CHECK, FEAT>(Q, 0, k, d, sc, acc);
+        col_store(Q, 0, k, d);
     }
     chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red);
     if (blockIdx.x == 0) {
         const int t1 = sh.t + 1;
         const int bad = sh.bad | (((t1 % P.check_every) == 0) != CHECK ? 2 : 0);
-        chain_store<MAXM>(P, ws, sh, t1, 1, bad);
+        chain_store<MAXM>(P, ws, sh, t1, 1, bad, 1.0);
     }
 }
 
@@ -343,8 +414,10 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
 template <int MAXM>
 __global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P) {
     __shared__ ChainShared<MAXM> sh;
+    const double wd = P.ctrl->wdiv;
     chain_prologue<MAXM, kChainBlock>(P, 0, sh);
-    chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad);
+    // a divisor decided here (or left by a launch that stopped) is pending
+    chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad, sh.f != 1.0 ? sh.f : wd);
 }
 
 // ---------------------------------------------------- persistent resident
@@ -422,22 +495,28 @@ __global__ __launch_bounds__(kBlock) void k_persist(SolveParams P, uint32_t *bar
         if (__hip_atomic_load(&P.ctrl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         const int t1 = __hip_atomic_load(&P.ctrl->t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
         const bool check = (t1 % P.check_every) == 0;
+        SolveParams Q = P;
+        adapt_load<true>(Q, P.rho_cur, P.ctrl);
+        if (Q.wdiv != 1.0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) col_rescale_mu(d[r], Q.wdiv);
+        }
         Scal<MAXM> sc;
-        scal_load<MAXM, true>(P, j, sc);
+        scal_load<MAXM, true>(Q, j, sc);
         Acc<MAXM> acc;
         acc.reset();
         if (check) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (kk[r] < P.n) col_update<T, MAXM, MIXED, true>(P, j, kk[r], d[r], sc, acc);
+                if (kk[r] < P.n) col_update<T, MAXM, MIXED, true>(Q, j, kk[r], d[r], sc, acc);
         } else {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (kk[r] < P.n) col_update<T, MAXM, MIXED, false>(P, j, kk[r], d[r], sc, acc);
+                if (kk[r] < P.n) col_update<T, MAXM, MIXED, false>(Q, j, kk[r], d[r], sc, acc);
         }
-        block_partials<MAXM>(P, (size_t)tile, acc, check, lds);
+        block_partials<MAXM>(Q, (size_t)tile, acc, check, lds);
         if (grid_arrive(bar, gridDim.x)) {
-            finalize_body(P);
+            finalize_body(Q);
             grid_release(bar);
         }
         ++gen;
@@ -594,6 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_init_final(SolveParams P) {
         P.ctrl->status = P.max_iter > 0 ? -1 : 2;
         P.ctrl->done = P.max_iter > 0 ? 0 : 1;
         P.ctrl->pending = 0;
+        P.ctrl->wdiv = 1.0;
     }
 }
 
@@ -694,20 +774,27 @@ hipError_t launch_copy_calib(const void *src, void *dst, size_t bytes, hipStream
 
 int max_m_supported() { return 8; }
 
-template <typename T, int MODE, int CPT, bool CHECK>
+template <typename T, int MODE, int CPT, bool CHECK, int FEAT>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
-    else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
-    else k_sweep<T, 8, CPT, MODE, CHECK><<<grid, kBlock, 0, s>>>(P);
+    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
+    else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
+    else k_sweep<T, 8, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
 }
 
+// One column per thread without the optional features (no g0, per-source
+// bounds, no branch codes, Gauss-Seidel, EXACT_BOX, no consensus) is the
+// common case and gets its own kernel; everything else the general one.
 template <typename T, int MODE, bool CHECK>
 static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
+    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project && !P.consensus;
     switch (P.cpt) {
-    case 1: launch_sweep_c<T, MODE, 1, CHECK>(P, s); break;
-    case 2: launch_sweep_c<T, MODE, 2, CHECK>(P, s); break;
-    default: launch_sweep_c<T, MODE, 4, CHECK>(P, s); break;
+    case 1:
+        if (plain) launch_sweep_c<T, MODE, 1, CHECK, 0>(P, s);
+        else launch_sweep_c<T, MODE, 1, CHECK, F_ALL>(P, s);
+        break;
+    case 2: launch_sweep_c<T, MODE, 2, CHECK, F_ALL>(P, s); break;
+    default: launch_sweep_c<T, MODE, 4, CHECK, F_ALL>(P, s); break;
     }
 }
 
@@ -768,11 +855,20 @@ hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int ch
     return hipLaunchCooperativeKernel(fn, dim3(P.nblk * P.q), dim3(kBlock), args, 0, s);
 }
 
+template <typename T, int MODE, bool CHECK, int FEAT>
+static void launch_chain_f(const SolveParams &P, int rs, hipStream_t s) {
+    const dim3 grid(P.nblk);
+    if (P.m <= 2) k_chain<T, 2, MODE, CHECK, FEAT><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else k_chain<T, 4, MODE, CHECK, FEAT><<<grid, kChainBlock, 0, s>>>(P, rs);
+}
+
+// The common case (no g0, per-source bounds, no branch codes, Gauss-Seidel,
+// EXACT_BOX) runs a kernel compiled without those features.
 template <typename T, int MODE, bool CHECK>
 static void launch_chain_k(const SolveParams &P, int rs, hipStream_t s) {
-    const dim3 grid(P.nblk);
-    if (P.m <= 2) k_chain<T, 2, MODE, CHECK><<<grid, kChainBlock, 0, s>>>(P, rs);
-    else k_chain<T, 4, MODE, CHECK><<<grid, kChainBlock, 0, s>>>(P, rs);
+    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project && !P.consensus;
+    if (plain) launch_chain_f<T, MODE, CHECK, 0>(P, rs, s);
+    else launch_chain_f<T, MODE, CHECK, F_ALL>(P, rs, s);
 }
 
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {

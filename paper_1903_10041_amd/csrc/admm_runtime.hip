@@ -92,6 +92,10 @@ admm_status validate_settings(const admm_settings *s) {
         return fail(ADMM_E_INVALID_ARG, "unknown sweep");
     if (s->launch < ADMM_LAUNCH_AUTO || s->launch > ADMM_LAUNCH_RESIDENT)
         return fail(ADMM_E_INVALID_ARG, "unknown launch path");
+    if (s->adaptive_rho &&
+        (!(s->tau > 1.0) || !std::isfinite(s->tau) || !(s->band_lo > 0.0) || !(s->band_hi >= s->band_lo) ||
+         !std::isfinite(s->band_hi)))
+        return fail(ADMM_E_INVALID_ARG, "adaptive rho needs tau > 1 and 0 < band_lo <= band_hi");
     return ADMM_OK;
 }
 
@@ -146,6 +150,10 @@ extern "C" void admm_default_settings(admm_settings *s) {
     s->xstep = ADMM_XSTEP_EXACT_BOX;
     s->sweep = ADMM_SWEEP_GAUSS_SEIDEL;
     s->launch = ADMM_LAUNCH_AUTO;
+    s->adaptive_rho = 0;
+    s->tau = 1.1;
+    s->band_hi = 1.2;
+    s->band_lo = 0.8;
 }
 
 extern "C" admm_status admm_create(admm_context **out, int device, size_t budget,
@@ -350,13 +358,20 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.inv_q = 1.0 / q;
     P.eps_p = s->eps_primal;
     P.eps_d = s->eps_dual;
+    P.adaptive = s->adaptive_rho ? 1 : 0;
+    P.tau = s->tau;
+    P.band_hi = s->band_hi;
+    P.band_lo = s->band_lo;
+    P.wdiv = 1.0;
     admm_status st;
 #define ENS(buf, bytes) if ((st = A.ensure(buf, bytes)) != ADMM_OK) return st
     ENS(W.coef, E * 4 * T);
     ENS(W.x, E * T);
     ENS(W.y, K * T);
     ENS(W.w, K * T);
-    ENS(W.scal, (7 * M + m + 3 * (size_t)m) * sizeof(double) + 2 * M * sizeof(double) + 4 * M * sizeof(double));
+    // lam zoff h p nu x1 pair_r pair_s [M each], xbar1 slo shi cap [m each],
+    // the chained path's second scalar slot [4m], rho_cur [2][4]
+    ENS(W.scal, (8 * M + 8 * (size_t)m + 8) * sizeof(double));
     ENS(W.part, (chain ? 2 : 1) * part_doubles(m, q, nblk) * sizeof(double));
     ENS(W.ctrl, 2 * sizeof(Ctrl) + 64);
     ENS(W.obj, 1024 * sizeof(double));
@@ -379,6 +394,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.ctrl = (Ctrl *)W.ctrl.p;
     P.bar = (uint32_t *)((char *)W.ctrl.p + sizeof(Ctrl));
     P.scal1 = sc + 8 * M + 4 * m;
+    P.rho_cur = sc + 8 * M + 8 * m;
     P.ctrl1 = (Ctrl *)((char *)W.ctrl.p + sizeof(Ctrl) + 64);
     P.part1 = chain ? P.part + part_doubles(m, q, nblk) : nullptr;
     return ADMM_OK;
@@ -419,6 +435,8 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
     std::memcpy(hb.data() + m, shi.data(), m * sizeof(double));
     std::memcpy(hb.data() + 2 * m, pr->c, m * sizeof(double));
     HIPCHK(hipMemcpyAsync((void *)P.slo, hb.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
+    const double rho0[8] = {P.rho1, P.rho2, P.rho3, P.rho4, P.rho1, P.rho2, P.rho3, P.rho4};
+    HIPCHK(hipMemcpyAsync(P.rho_cur, rho0, sizeof rho0, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl) + 16, s));
 
     const void *f2 = pr->f2, *f1 = pr->f1, *g2 = pr->g2, *g1 = pr->g1, *g0 = pr->g0, *f0 = pr->f0;
@@ -531,6 +549,7 @@ admm_status load_warm(admm_context *ctx, const admm_problem *pr, const admm_stat
     c0.done = P.max_iter > 0 ? 0 : 1;
     c0.r = INFINITY;
     c0.sigma = INFINITY;
+    c0.wdiv = 1.0;
     *ctx->hctrl = c0;
     HIPCHK(hipMemcpyAsync(P.ctrl, ctx->hctrl, sizeof(Ctrl), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -639,7 +658,7 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
 
 // Expand the device state into the paper's variables.
 admm_status export_state(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
-                         admm_state *out, hipStream_t s) {
+                         double wdiv, admm_state *out, hipStream_t s) {
     const int m = pr->m, n = pr->n, q = pr->q, n_pad = P.n_pad;
     const size_t E = (size_t)q * m * n, Ep = (size_t)q * m * n_pad, K = (size_t)q * n, M = (size_t)q * m;
     const size_t T = dtype == 0 ? 8 : 4;
@@ -670,7 +689,8 @@ admm_status export_state(admm_context *ctx, const admm_problem *pr, const SolveP
         for (int k = 0; k < n; ++k) {
             const double w = rd(wb, (size_t)j * n_pad + k);
             if (out->s) out->s[(size_t)j * n + k] = std::max(w, 0.0);
-            if (out->mu) out->mu[(size_t)j * n + k] = std::max(-w, 0.0);
+            // a rho change at the last check leaves mu /= wdiv to apply here
+            if (out->mu) out->mu[(size_t)j * n + k] = std::max(-w, 0.0) / wdiv;
         }
     (void)K;
     (void)E;
@@ -714,6 +734,7 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     if ((st = iterate(ctx, P, dtype, s, &dev_ms)) != ADMM_OK) return st;
     HIPCHK(launch_objective(P, dtype, (double *)ctx->ws.obj.p, s));
     HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ctx->hctrl + 3, P.rho_cur, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     // x out
     const size_t E = (size_t)pr->q * pr->m * pr->n;
     if (pr->mem == ADMM_DEVICE) {
@@ -725,10 +746,13 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     }
     HIPCHK(hipStreamSynchronize(s));
     const Ctrl c = *ctx->hctrl;
+    double rho_fin[4];
+    std::memcpy(rho_fin, (const void *)(ctx->hctrl + 3), sizeof rho_fin);
     if (c.bad_input & 2) return fail(ADMM_E_DEVICE, "check-iteration schedule out of step");
-    if (state_out && (st = export_state(ctx, pr, P, dtype, state_out, s)) != ADMM_OK) return st;
+    if (state_out && (st = export_state(ctx, pr, P, dtype, c.wdiv, state_out, s)) != ADMM_OK) return st;
     admm_info inf;
     std::memset(&inf, 0, sizeof inf);
+    for (int k = 0; k < 4; ++k) inf.rho[k] = rho_fin[k];
     inf.status = c.status == 0 ? ADMM_OK : (c.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
     inf.iters = c.t;
     inf.r = c.r;

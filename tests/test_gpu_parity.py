@@ -331,3 +331,62 @@ def test_max_iter_zero_returns_cold_start(ctx):
     assert info["iters"] == 0 and info["status"] == admm.MAX_ITER
     assert np.array_equal(x, o["x"])
     assert np.allclose(st["h"], o["h"], rtol=1e-14)
+
+
+# ------------------------------------------------------------ adaptive rho
+@pytest.mark.parametrize("launch", list(LAUNCHES))
+def test_adaptive_rho_follows_oracle(ctx, launch):
+    """Residual balancing (Sec. IV-A, reading R12) on every launch path:
+    the same rho after a fixed number of iterations, the same iterates, and
+    the exported state (mu, lambda, p) rescaled like the oracle's, including
+    a change decided at the last iteration."""
+    for name, iters in (("c1", 300), ("stress", 200), ("c1_binding", 100)):
+        p = LAUNCH_CASES[name]()
+        s = admm.Settings(rho=tuple(p.rho), max_iter=iters, eps_primal=1e-9, eps_dual=1e-9,
+                          adaptive_rho=True, launch=LAUNCHES[launch])
+        say(f"[adaptive] {name} {launch} iters={iters}")
+        x, info, sg = ctx.solve(p, s, want_state=True)
+        so, oinfo, _ = oracle.run(p, max_iter=iters, eps_primal=1e-9, eps_dual=1e-9, adaptive_rho=True)
+        say(f"   rho gpu={info['rho']} oracle={oinfo['rho']} iters {info['iters']}/{oinfo['iters']}")
+        assert info["iters"] == oinfo["iters"]
+        assert np.allclose(info["rho"], oinfo["rho"], rtol=1e-15, atol=0)
+        assert oinfo["rho"][0] != p.rho[0]          # the case does adapt
+        assert float(np.abs(x - so["x"]).max()) <= 1e-9
+        for kg, ko in (("mu", "mu"), ("h", "h"), ("p", "p"), ("lambda_", "lam")):
+            scale = 1 + np.abs(so[ko]).max()
+            assert np.abs(sg[kg] - so[ko]).max() <= 1e-9 * scale, kg
+
+
+@pytest.mark.parametrize("launch", list(LAUNCHES))
+def test_adaptive_rho_convergence(ctx, launch):
+    for name in ("c1", "stress"):
+        p = LAUNCH_CASES[name]()
+        s = admm.Settings(rho=tuple(p.rho), max_iter=100000, eps_primal=1e-6, eps_dual=1e-6,
+                          adaptive_rho=True, launch=LAUNCHES[launch])
+        x, info, _ = ctx.solve(p, s)
+        so, oinfo, _ = oracle.run(p, max_iter=100000, eps_primal=1e-6, eps_dual=1e-6, adaptive_rho=True)
+        say(f"[adaptive-converge] {name} {launch} iters gpu={info['iters']} oracle={oinfo['iters']}")
+        assert info["status"] == admm.OK and oinfo["status"] == 0
+        assert abs(info["iters"] - oinfo["iters"]) <= 10
+        assert abs(info["objective"] - oinfo["objective"]) <= 1e-9 * (1 + abs(oinfo["objective"]))
+
+
+def test_adaptive_rho_fp32_and_robust(ctx):
+    """Mixed precision and the multi-scenario (consensus) path with
+    adaptive rho reach the oracle's objective."""
+    for p, prec in ((W.small_c1(), admm.F32_MIXED), (W.phev_c4(seed=7, q=5, n=60), admm.F64)):
+        s = admm.Settings(rho=tuple(p.rho), max_iter=100000, eps_primal=1e-5, eps_dual=1e-5,
+                          adaptive_rho=True, precision=prec)
+        x, info, _ = ctx.solve(p, s)
+        so, oinfo, _ = oracle.run(p, max_iter=100000, eps_primal=1e-5, eps_dual=1e-5, adaptive_rho=True)
+        rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
+        say(f"[adaptive-misc] m={p.m} q={p.q} prec={prec} iters {info['iters']}/{oinfo['iters']} rel={rel:.2e}")
+        assert info["status"] == admm.OK
+        assert rel <= (1e-4 if prec != admm.F64 else 1e-8)
+
+
+def test_adaptive_rho_rejected_by_submit(ctx):
+    p = W.small_c1()
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.submit(p, admm.Settings(adaptive_rho=True))
+    assert e.value.status == admm.E_UNSUPPORTED
