@@ -253,6 +253,9 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
         xc[i] = xo[i];
         sum_old += xo[i];
     }
+    // Gauss-Seidel: the sum over the other sources is the running total of
+    // the current iterate minus source i (Jacobi: of the previous iterate)
+    double sum_cur = sum_old;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
         if (i < m) {
@@ -269,15 +272,13 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
             }
             const double g_old = (g2 * xo[i] + g1) * xo[i] + g0;
             const double theta = g_old + sc.toff[i];
-            double others = 0.0;
-#pragma unroll
-            for (int l = 0; l < MAXM; ++l)
-                if (l < m && l != i) others += jacobi ? xo[l] : xc[l];
+            const double others = (jacobi ? sum_old : sum_cur) - xo[i];
             const double phi = sm - others + y;
             int code;
             const double xn = st_round<T>(xstep<MODE, FEAT>(P, f2, f1, g2, g1, theta - g0, phi,
                                                              cons && k == 0, sc.cons[i], lo, hi, code));
             xc[i] = xn;
+            sum_cur += xn - xo[i];
             d.x[i] = (T)xn;
             if ((FEAT & F_CODES) && P.want_codes) P.codes[e] = (uint8_t)code;
             if ((FEAT & F_CONS) && k == 0) P.x1[j * m + i] = xn;

@@ -68,11 +68,16 @@ __device__ __forceinline__ double cbrt64(double a) {
 
 __device__ __forceinline__ float rcp32(float a) { return __builtin_amdgcn_rcpf(a); }
 
+// Real cube root in FP32: exp2(log2|a| / 3) with the sign of a (a = 0
+// gives log2 = -inf and exp2(-inf) = 0).
 __device__ __forceinline__ float cbrt32(float a) {
-    const float aa = fabsf(a);
-    const float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(aa) * (1.0f / 3.0f));
-    return aa == 0.0f ? 0.0f : copysignf(y, a);
+    const float y = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(a)) * (1.0f / 3.0f));
+    return copysignf(y, a);
 }
+
+// Hardware square root (about 1 ulp; no correctly-rounded refinement): the
+// FP32 closed form is followed by an FP64 Newton step or is the FP32 path.
+__device__ __forceinline__ float sqrt32(float a) { return __builtin_amdgcn_sqrtf(a); }
 
 __device__ __forceinline__ double qmin_quadratic(double C, double D, double lo, double hi, int &code) {
     const double u = -0.5 * D * rcp64(C);
@@ -161,9 +166,10 @@ __device__ __forceinline__ double qmin_mixed(double A, double B, double C, doubl
     const float R2 = R * R;
     const float Delta = Q3 + R2;
     if (Delta > kMixedDeltaMargin * (fabsf(Q3) + R2)) {
-        const float sq = __builtin_sqrtf(Delta);
+        // Delta > 0 here, so |R| + sqrt(Delta) > 0 and S != 0
+        const float sq = sqrt32(Delta);
         const float S = cbrt32(R + copysignf(sq, R));
-        const float T = (S != 0.0f) ? -Q * rcp32(S) : 0.0f;
+        const float T = -Q * rcp32(S);
         double u = (double)(S + T - b3);
         // one FP64 Newton step on f'(u) = 0
         const double p1 = ((4.0 * A * u + 3.0 * B) * u + 2.0 * C) * u + D;
@@ -200,9 +206,9 @@ __device__ __forceinline__ bool qmin_f32_fast(float A, float B, float C, float D
         const float R2 = R * R;
         const float Delta = Q3 + R2;
         if (!(Delta > kMixedDeltaMargin * (fabsf(Q3) + R2))) return false;
-        const float sq = __builtin_sqrtf(Delta);
+        const float sq = sqrt32(Delta);
         const float S = cbrt32(R + copysignf(sq, R));
-        const float T = (S != 0.0f) ? -Q * rcp32(S) : 0.0f;
+        const float T = -Q * rcp32(S);
         u = S + T - b3;
         code = 3 * BR_CARDANO;
     }
