@@ -143,8 +143,14 @@ __device__ __forceinline__ void opaque(Col<T, MAXM> &d) {
     opaque1(d.w);
 }
 
-template <typename T, int MAXM>
+// ME > 0: the kernel is compiled for exactly ME sources (m == ME), so the
+// per-source guards fold away; ME = 0 reads m from the launch parameters.
+template <int ME>
+__device__ __forceinline__ int src_count(const SolveParams &P) { return ME > 0 ? ME : P.m; }
+
+template <typename T, int MAXM, int ME = 0>
 __device__ __forceinline__ void col_load(const SolveParams &P, int j, int k, Col<T, MAXM> &d) {
+    const int m = src_count<ME>(P);
     const V4<T> *coef = (const V4<T> *)P.coef;
     const T *X = (const T *)P.x;
     const size_t col = (size_t)j * P.n_pad + k;
@@ -152,21 +158,22 @@ __device__ __forceinline__ void col_load(const SolveParams &P, int j, int k, Col
     d.w = ((const T *)P.w)[col];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
-        if (i < P.m) {
-            const size_t e = ((size_t)j * P.m + i) * P.n_pad + k;
+        if (i < m) {
+            const size_t e = ((size_t)j * m + i) * P.n_pad + k;
             d.cf[i] = coef[e];
             d.x[i] = X[e];
         }
     }
 }
 
-template <typename T, int MAXM>
+template <typename T, int MAXM, int ME = 0>
 __device__ __forceinline__ void col_store(const SolveParams &P, int j, int k, const Col<T, MAXM> &d) {
+    const int m = src_count<ME>(P);
     T *X = (T *)P.x;
     ((T *)P.w)[(size_t)j * P.n_pad + k] = d.w;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-        if (i < P.m) X[((size_t)j * P.m + i) * P.n_pad + k] = d.x[i];
+        if (i < m) X[((size_t)j * m + i) * P.n_pad + k] = d.x[i];
 }
 
 // Adaptive rho: after rho_i *= f the scaled mu is divided by f; mu is the
@@ -234,10 +241,10 @@ struct Acc {
 // One column: the x-step (7a) for every source in turn (Gauss-Seidel, or
 // Jacobi by flag), then the s- and mu-steps (7e)-(7f) through w = s - mu,
 // accumulating sum_k g(x_k) per source and the residual trackers.
-template <typename T, int MAXM, int MODE, bool CHECK, int FEAT = F_ALL>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT = F_ALL, int ME = 0>
 __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, Col<T, MAXM> &d,
                                            const Scal<MAXM> &sc, Acc<MAXM> &acc) {
-    const int m = P.m;
+    const int m = src_count<ME>(P);
     const double y = (double)d.y;
     const double w = (double)d.w;
     const double s_old = fmax(w, 0.0), mu_old = fmax(-w, 0.0);

@@ -30,7 +30,7 @@ namespace admm {
 // selects the variant that also tracks the residual terms; it is used only
 // on check iterations.  Kernels for up to four sources are held to 128
 // VGPRs so that four waves fit on each SIMD.
-template <typename T, int MAXM, int CPT, int MODE, bool CHECK, int FEAT>
+template <typename T, int MAXM, int CPT, int MODE, bool CHECK, int FEAT, int ME = 0>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 4 ? 4 : 2)))
 void k_sweep(SolveParams P0) {
     Ctrl *ctrl = P0.ctrl;
@@ -47,10 +47,10 @@ void k_sweep(SolveParams P0) {
         const int k = blockIdx.x * (kBlock * CPT) + cc * kBlock + threadIdx.x;
         if (k < P.n) {
             Col<T, MAXM> d;
-            col_load(P, j, k, d);
+            col_load<T, MAXM, ME>(P, j, k, d);
             if (P.wdiv != 1.0) col_rescale_mu(d, P.wdiv);
-            col_update<T, MAXM, MODE, CHECK, FEAT>(P, j, k, d, sc, acc);
-            col_store(P, j, k, d);
+            col_update<T, MAXM, MODE, CHECK, FEAT, ME>(P, j, k, d, sc, acc);
+            col_store<T, MAXM, ME>(P, j, k, d);
         }
     }
     __shared__ double lds[MAXM + 2][kBlock];
@@ -354,7 +354,7 @@ __device__ __forceinline__ void chain_partials(const SolveParams &P, double *par
     }
 }
 
-template <typename T, int MAXM, int MODE, bool CHECK, int FEAT>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int ME>
 __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     const int ws = rs ^ 1;
     __shared__ ChainShared<MAXM> sh;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     const int k = blockIdx.x * kChainBlock + threadIdx.x;
     const bool live = k < P.n;
     Col<T, MAXM> d;
-    if (live) col_load(P, 0, k, d);
+    if (live) col_load<T, MAXM, ME>(P, 0, k, d);
     chain_prologue<MAXM, kChainBlock>(P, rs, sh);
     if (sh.done) {
         // a mu divisor decided here stays pending for the export
@@ -398,8 +398,8 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     acc.reset();
     if (live) {
         if (Q.wdiv != 1.0) col_rescale_mu(d, Q.wdiv);
-        col_update<T, MAXM, MODE, CHECK, FEAT>(Q, 0, k, d, sc, acc);
-        col_store(Q, 0, k, d);
+        col_update<T, MAXM, MODE, CHECK, FEAT, ME>(Q, 0, k, d, sc, acc);
+        col_store<T, MAXM, ME>(Q, 0, k, d);
     }
     chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red);
     if (blockIdx.x == 0) {
@@ -777,7 +777,9 @@ int max_m_supported() { return 8; }
 template <typename T, int MODE, int CPT, bool CHECK, int FEAT>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
+    if (FEAT == 0 && P.m == 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT, 2><<<grid, kBlock, 0, s>>>(P);
+    else if (FEAT == 0 && P.m == 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT, 4><<<grid, kBlock, 0, s>>>(P);
+    else if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
     else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
     else k_sweep<T, 8, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
 }
@@ -858,8 +860,10 @@ hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int ch
 template <typename T, int MODE, bool CHECK, int FEAT>
 static void launch_chain_f(const SolveParams &P, int rs, hipStream_t s) {
     const dim3 grid(P.nblk);
-    if (P.m <= 2) k_chain<T, 2, MODE, CHECK, FEAT><<<grid, kChainBlock, 0, s>>>(P, rs);
-    else k_chain<T, 4, MODE, CHECK, FEAT><<<grid, kChainBlock, 0, s>>>(P, rs);
+    if (P.m == 2) k_chain<T, 2, MODE, CHECK, FEAT, 2><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else if (P.m == 4) k_chain<T, 4, MODE, CHECK, FEAT, 4><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else if (P.m < 2) k_chain<T, 2, MODE, CHECK, FEAT, 0><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else k_chain<T, 4, MODE, CHECK, FEAT, 0><<<grid, kChainBlock, 0, s>>>(P, rs);
 }
 
 // The common case (no g0, per-source bounds, no branch codes, Gauss-Seidel,
