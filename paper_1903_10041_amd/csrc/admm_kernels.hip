@@ -143,84 +143,117 @@ struct ChainShared {
     int t, status, done, bad;
 };
 
-// Sum / max / min over the first nb entries (stride `stride`) of one
-// partial column, lane-strided then across the wave.  Every load is issued
-// before the first use (nb <= 64 * kChainLoads), so the reduction costs one
-// memory round trip.  The order is fixed: every block gets the same bits.
+// The pending iteration is completed in two parts so that the partial
+// reads are issued before the caller's column loads: chain_load issues
+// them (and the reads of the per-source state), chain_finish reduces them
+// once they arrive, while the column loads are still in flight.
 constexpr int kChainLoads = kChainMaxBlocks / 64;
 
-__device__ __forceinline__ double wave_part_sum(const double *col, size_t stride, int nb, int lane) {
-    double v[kChainLoads];
-#pragma unroll
-    for (int u = 0; u < kChainLoads; ++u) {
-        const int b = lane + 64 * u;
-        v[u] = b < nb ? col[(size_t)b * stride] : 0.0;
-    }
-#pragma unroll
-    for (int w = 1; w < kChainLoads; w *= 2)
-#pragma unroll
-        for (int u = 0; u < kChainLoads; u += 2 * w) v[u] += v[u + w];
-    return wave_sum(v[0]);
-}
+struct ChainLoads {
+    double a[kChainLoads], b[kChainLoads], c[kChainLoads];   // this wave's partial column(s)
+    double lam, zoff, h, p;                                   // source `lane` (first wave)
+};
 
-__device__ __forceinline__ double wave_part_max(const double *col, size_t stride, int nb, int lane, double init) {
-    double v = init;
-#pragma unroll
-    for (int u = 0; u < kChainLoads; ++u) {
-        const int b = lane + 64 * u;
-        if (b < nb) v = fmax(v, col[(size_t)b * stride]);
-    }
-    return wave_max(v);
-}
-
-__device__ __forceinline__ double wave_part_min(const double *col, size_t stride, int nb, int lane) {
-    double v = DBL_MAX;
-#pragma unroll
-    for (int u = 0; u < kChainLoads; ++u) {
-        const int b = lane + 64 * u;
-        if (b < nb) v = fmin(v, col[(size_t)b * stride]);
-    }
-    return wave_min(v);
-}
-
-// Completes the pending iteration (if any) from slot rs and partial buffer
-// rs ^ 1 into `sh`.  Wave i < m reduces source i's partials (and the last
-// wave the residual maxima); after one barrier the first wave's lane i
-// updates source i and the whole wave takes the stop decision; a second
-// barrier publishes `sh`.
-template <int MAXM, int NT>
-__device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, ChainShared<MAXM> &sh) {
+// Wave i < m: source i's sums (a) and, on a check, dg max (b) and min (c);
+// the last wave, on a check, the residual maxima (a, b).  Entries past the
+// last block hold the reduction's identity.
+template <int NT>
+__device__ __forceinline__ void chain_load(const SolveParams &P, int rs, ChainLoads &L) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = P.m, nb = P.nblk;
     const ChainSlot in = chain_slot(P, rs);
     const double *part = rs ? P.part : P.part1;
     const Ctrl *c = in.ctrl;
+    const bool fin = c->pending && !c->done;
+    const bool chk = fin && (c->t % P.check_every) == 0;
+    const size_t slab = (size_t)nb * m;
+    if (fin && wv < m) {
+#pragma unroll
+        for (int u = 0; u < kChainLoads; ++u) {
+            const int b = lane + 64 * u;
+            L.a[u] = b < nb ? part[(size_t)b * m + wv] : 0.0;
+        }
+        if (chk) {
+#pragma unroll
+            for (int u = 0; u < kChainLoads; ++u) {
+                const int b = lane + 64 * u;
+                L.b[u] = b < nb ? part[slab + (size_t)b * m + wv] : -DBL_MAX;
+                L.c[u] = b < nb ? part[2 * slab + (size_t)b * m + wv] : DBL_MAX;
+            }
+        }
+    } else if (chk && wv == NT / 64 - 1) {
+#pragma unroll
+        for (int u = 0; u < kChainLoads; ++u) {
+            const int b = lane + 64 * u;
+            L.a[u] = b < nb ? part[3 * slab + 2 * (size_t)b] : 0.0;
+            L.b[u] = b < nb ? part[3 * slab + 2 * (size_t)b + 1] : 0.0;
+        }
+    }
+    if (wv == 0) {
+        const int li = lane < m ? lane : 0;
+        L.lam = in.lam[li];
+        L.zoff = in.zoff[li];
+        L.h = in.h[li];
+        L.p = in.p[li];
+    }
+}
+
+__device__ __forceinline__ double regs_sum(const double (&v)[kChainLoads]) {
+    double t[kChainLoads];
+#pragma unroll
+    for (int u = 0; u < kChainLoads; ++u) t[u] = v[u];
+#pragma unroll
+    for (int w = 1; w < kChainLoads; w *= 2)
+#pragma unroll
+        for (int u = 0; u < kChainLoads; u += 2 * w) t[u] += t[u + w];
+    return wave_sum(t[0]);
+}
+__device__ __forceinline__ double regs_max(const double (&v)[kChainLoads]) {
+    double t = v[0];
+#pragma unroll
+    for (int u = 1; u < kChainLoads; ++u) t = fmax(t, v[u]);
+    return wave_max(t);
+}
+__device__ __forceinline__ double regs_min(const double (&v)[kChainLoads]) {
+    double t = v[0];
+#pragma unroll
+    for (int u = 1; u < kChainLoads; ++u) t = fmin(t, v[u]);
+    return wave_min(t);
+}
+
+// Completes the pending iteration (if any) from what chain_load read into
+// `sh`.  The sums over blocks run in a fixed order (lane-strided pairwise,
+// then across the wave), so every block derives the same bits.  After one
+// barrier the first wave's lane i updates source i and the whole wave takes
+// the stop decision; a second barrier publishes `sh`.
+template <int MAXM, int NT>
+__device__ __forceinline__ void chain_finish(const SolveParams &P, int rs, const ChainLoads &L,
+                                             ChainShared<MAXM> &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, m = P.m;
+    const ChainSlot in = chain_slot(P, rs);
+    const Ctrl *c = in.ctrl;
     const int t = c->t, pending = c->pending, done = c->done;
     const bool fin = pending && !done;
     const bool chk = fin && (t % P.check_every) == 0;
-    const size_t slab = (size_t)nb * m;
-    // the per-source state, read early by the lanes that update it
-    const int li = lane < m ? lane : 0;
-    double lam = 0.0, zoff = 0.0, h = 0.0, p = 0.0;
-    if (wv == 0) { lam = in.lam[li]; zoff = in.zoff[li]; h = in.h[li]; p = in.p[li]; }
     __shared__ double red[MAXM][3];
     __shared__ double rres[2];
     if (fin) {
         if (wv < m) {
-            const double sum = wave_part_sum(part + wv, m, nb, lane);
+            const double sum = regs_sum(L.a);
             double mx = 0.0, mn = 0.0;
             if (chk) {
-                mx = wave_part_max(part + slab + wv, m, nb, lane, -DBL_MAX);
-                mn = wave_part_min(part + 2 * slab + wv, m, nb, lane);
+                mx = regs_max(L.b);
+                mn = regs_min(L.c);
             }
             if (lane == 0) { red[wv][0] = sum; red[wv][1] = mx; red[wv][2] = mn; }
         } else if (wv == NT / 64 - 1 && chk) {
-            const double a = wave_part_max(part + 3 * slab, 2, nb, lane, 0.0);
-            const double b = wave_part_max(part + 3 * slab + 1, 2, nb, lane, 0.0);
+            const double a = regs_max(L.a);
+            const double b = regs_max(L.b);
             if (lane == 0) { rres[0] = a; rres[1] = b; }
         }
     }
     __syncthreads();
     if (wv == 0) {
+        double lam = L.lam, zoff = L.zoff, h = L.h, p = L.p;
         double rho[4] = {P.rho1, P.rho2, P.rho3, P.rho4};
         if (P.adaptive)
             for (int k = 0; k < 4; ++k) rho[k] = P.rho_cur[4 * rs + k];
@@ -271,8 +304,9 @@ __device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, Cha
             sh.h[lane] = h;
             sh.p[lane] = p;
         }
-        if (lane < 4) sh.rho[lane] = rho[lane] * f;
         if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sh.rho[k] = rho[k] * f;
             sh.t = t;
             sh.status = status;
             sh.done = dn;
@@ -283,6 +317,13 @@ __device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, Cha
         }
     }
     __syncthreads();
+}
+
+template <int MAXM, int NT>
+__device__ __forceinline__ void chain_prologue(const SolveParams &P, int rs, ChainShared<MAXM> &sh) {
+    ChainLoads L;
+    chain_load<NT>(P, rs, L);
+    chain_finish<MAXM, NT>(P, rs, L, sh);
 }
 
 // Writes the state in `sh` into slot `ws` (one block).
@@ -366,13 +407,16 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
         if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad, cin->wdiv);
         return;
     }
-    // the column loads do not depend on the scalars: issue them first so
-    // that their latency overlaps the reads of the partials
+    // the partial reads first, then the column loads (which do not depend
+    // on the scalars): the scalar steps wait only for the former, and each
+    // wave starts its sweep as soon as its own columns arrive
     const int k = blockIdx.x * kChainBlock + threadIdx.x;
     const bool live = k < P.n;
+    ChainLoads L;
+    chain_load<kChainBlock>(P, rs, L);
     Col<T, MAXM> d;
     if (live) col_load<T, MAXM, ME>(P, 0, k, d);
-    chain_prologue<MAXM, kChainBlock>(P, rs, sh);
+    chain_finish<MAXM, kChainBlock>(P, rs, L, sh);
     if (sh.done) {
         // a mu divisor decided here stays pending for the export
         if (blockIdx.x == 0) chain_store<MAXM>(P, ws, sh, sh.t, 0, sh.bad, sh.f);
