@@ -206,6 +206,83 @@ def run_large(args):
             "sweep_bytes": byts, "sweep_gbs": ach, "sweep_hbm_frac": ach / HBM_PEAK_GBS}
 
 
+def run_quartic(args):
+    """The x-step minimiser alone (Alg. 1; the paper's first experiment) on
+    N seeded quartics, N = 10 .. --quartic-max-n: host arrays (copy in,
+    kernel, copy out) and device arrays (kernel only), FP64 and mixed."""
+    import numpy as np
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    ctx = admm.Context(0, hbm_budget_bytes=64 << 30)
+    out = {"workload": "A~U[5e-5,5e-3], B~U[8e-3,0.12], C~U[0.5,2], D~U[-3,3], box [0,2]",
+           "bytes_per_quartic": 60, "rows": []}
+    Nmax = args.quartic_max_n
+    big = W.quartic_batch(Nmax)
+    dev = torch.device("cuda:0")
+    tbig = [torch.from_numpy(getattr(big, k)).to(dev) for k in ("A", "B", "C", "D", "lo", "hi")]
+    admm.minimize_quartics(ctx, *[a[:1000] for a in tbig])           # warm-up
+    N = 10
+    while N <= Nmax:
+        row = {"N": N}
+        for tag, prec in (("f64", admm.F64), ("mixed", admm.F32_MIXED)):
+            h = [np.ascontiguousarray(getattr(big, k)[:N]) for k in ("A", "B", "C", "D", "lo", "hi")]
+            t0 = time.perf_counter()
+            admm.minimize_quartics(ctx, *h, precision=prec, want_codes=False)
+            row[f"{tag}_host_ms"] = 1000.0 * (time.perf_counter() - t0)
+            d = [a[:N] for a in tbig]
+            reps = max(1, min(50, int(2e7 // N)))
+            kms = []
+            for _ in range(reps):
+                _, _, ms = admm.minimize_quartics(ctx, *d, precision=prec, want_codes=True)
+                kms.append(ms)
+            kms.sort()
+            row[f"{tag}_kernel_ms"] = kms[len(kms) // 2]
+            row[f"{tag}_kernel_gqps"] = N / (kms[len(kms) // 2] * 1e-3) / 1e9
+            row[f"{tag}_kernel_hbm_frac"] = 60.0 * N / (kms[len(kms) // 2] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        out["rows"].append(row)
+        N *= 10
+    del tbig
+    ctx.close()
+    return out
+
+
+def run_qsweep(args):
+    """Scenario-count sweep on the robust shape (m = 2, n = 3600, q in
+    --q-list; the paper's second experiment): iterations and solve time to
+    r, sigma < 1e-4 with rho = 1, with rho_2 / n, and with adaptive rho
+    (Sec. IV-A), mixed precision; the FP64 oracle's iteration counts for
+    the smallest q values (rho_2 / n)."""
+    import torch
+    import oracle
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
+    rows = []
+    for q in args.q_list:
+        p = W.phev_c4(q=q)
+        pd = _device_problem(p, torch.float32)
+        row = {"q": q, "elements": p.m * p.n * q}
+        for tag, kw in (("rho1", {}), ("rho2_per_step", {"rho2_per_step": True}),
+                        ("adaptive", {"adaptive_rho": True})):
+            s = admm.Settings(max_iter=args.q_max_iter, eps_primal=1e-4, eps_dual=1e-4,
+                              precision=admm.F32_MIXED, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, _ = ctx.solve(pd, s)
+            torch.cuda.synchronize()
+            row[tag] = {"iters": info["iters"], "status": info["status"],
+                        "solve_ms": 1000.0 * (time.perf_counter() - t0), "objective": info["objective"]}
+        if q <= args.q_oracle_max and not args.no_cpu_baseline:
+            _, oinfo, _ = oracle.run(p, max_iter=args.q_max_iter, eps_primal=1e-4, eps_dual=1e-4,
+                                     rho=(1.0, 1.0 / p.n, 1.0, 1.0), nthreads=16)
+            row["oracle_rho2_per_step_iters"] = oinfo["iters"]
+        rows.append(row)
+    ctx.close()
+    return {"workload": "m=2 n=3600 robust scenario program (engine quadratic, battery quartic, "
+                        "first-step consensus), mixed precision, residual 1e-4", "rows": rows}
+
+
 def _prec(args):
     from paper_1903_10041_amd import admm
     return {"f32": admm.F32, "mixed": admm.F32_MIXED, "f64": admm.F64}[args.precision]
@@ -384,6 +461,11 @@ def cpu_baseline(args):
     it1 = max(1, int(0.4 * iters / nt))
     oracle.run(p, max_iter=it1, state=st, nthreads=1)
     out["single_thread"] = {"value": it1 / (time.perf_counter() - t0), "iterations": it1}
+    # the minimiser alone, one thread
+    qb = W.quartic_batch(1_000_000)
+    t0 = time.perf_counter()
+    oracle.quartic_min(qb.A, qb.B, qb.C, qb.D, qb.lo, qb.hi)
+    out["quartic_single_thread"] = {"quartics_per_s": 1e6 / (time.perf_counter() - t0), "N": 1_000_000}
     # the served request mix through the oracle, one request after another
     import math
     import numpy as np
@@ -436,6 +518,10 @@ def main():
     ap.add_argument("--large-n", type=int, default=1 << 22)
     ap.add_argument("--large-steps", type=int, default=300)
     ap.add_argument("--cpu-serve-requests", type=int, default=24)
+    ap.add_argument("--quartic-max-n", type=int, default=100_000_000)
+    ap.add_argument("--q-list", type=int, nargs="+", default=[5, 10, 20, 50, 100, 200, 500])
+    ap.add_argument("--q-max-iter", type=int, default=50000)
+    ap.add_argument("--q-oracle-max", type=int, default=20)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run the library's plain copy kernel (k_copy_calib) 3 times over this "
                          "many MiB, to scale hardware byte counters")
@@ -471,6 +557,8 @@ def main():
         extras["served"] = run_serve(args)
         extras["robust"] = run_robust(args)
         extras["large"] = run_large(args)
+        extras["quartic"] = run_quartic(args)
+        extras["q_sweep"] = run_qsweep(args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
     storage = {"f32": "f32 storage and x-step arithmetic, f64 reductions",

@@ -203,3 +203,27 @@ def serving_c5(seed: int = 5, rate_hz: float = 2000.0, duration_s: float = 60.0,
                                                   name=f"c5_{idx}")))
         idx += 1
     return out
+
+
+@dataclasses.dataclass
+class QuarticBatch:
+    """N independent box-constrained quartics A x^4 + B x^3 + C x^2 + D x."""
+    A: np.ndarray
+    B: np.ndarray
+    C: np.ndarray
+    D: np.ndarray
+    lo: np.ndarray
+    hi: np.ndarray
+
+
+def quartic_batch(N: int, seed: int = 6) -> QuarticBatch:
+    """Quartics with the magnitudes the x-step produces on the small and
+    bandwidth cases (rho = 1): A ~ U[5e-5, 5e-3], B ~ U[8e-3, 0.12],
+    C ~ U[0.5, 2], D ~ U[-3, 3], box [0, 2].  Drawn directly (no
+    coefficient assembly); draw order A, B, C, D."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(5e-5, 5e-3, N)
+    B = rng.uniform(8e-3, 0.12, N)
+    C = rng.uniform(0.5, 2.0, N)
+    D = rng.uniform(-3.0, 3.0, N)
+    return QuarticBatch(A, B, C, D, np.zeros(N), np.full(N, 2.0))
