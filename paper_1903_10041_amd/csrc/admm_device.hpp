@@ -195,11 +195,13 @@ __device__ __forceinline__ void col_load(const SolveParams &P, int j, int k, Col
 template <typename T, int MAXM, int ME = 0>
 __device__ __forceinline__ void col_store(const SolveParams &P, int j, int k, const Col<T, MAXM> &d) {
     const int m = src_count<ME>(P);
+    // streaming stores: the next reader is the next launch (or iteration
+    // window), after the caches have been written back anyway
     T *X = (T *)P.x;
-    ((T *)P.w)[(size_t)j * P.n_pad + k] = d.w;
+    __builtin_nontemporal_store(d.w, ((T *)P.w) + (size_t)j * P.n_pad + k);
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
-        if (i < m) X[((size_t)j * m + i) * P.n_pad + k] = d.x[i];
+        if (i < m) __builtin_nontemporal_store(d.x[i], X + ((size_t)j * m + i) * P.n_pad + k);
 }
 
 // Adaptive rho: after rho_i *= f the scaled mu is divided by f; mu is the

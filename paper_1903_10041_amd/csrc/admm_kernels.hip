@@ -433,11 +433,11 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     Scal<MAXM> sc;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
-        const int ii = i < P.m ? i : 0;
-        sc.toff[i] = i < P.m ? sh.zoff[ii] + sh.lam[ii] : 0.0;
+        const int ii = i < src_count<ME>(P) ? i : 0;
+        sc.toff[i] = i < src_count<ME>(P) ? sh.zoff[ii] + sh.lam[ii] : 0.0;
         sc.cons[i] = 0.0;
     }
-    scal_bounds<MAXM>(P.slo, P.shi, P.m, sc);
+    scal_bounds<MAXM>(P.slo, P.shi, src_count<ME>(P), sc);
     Acc<MAXM> acc;
     acc.reset();
     if (live) {
