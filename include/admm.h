@@ -89,8 +89,8 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
  *           scalar steps (7b)-(7d), (7g)-(7i), residuals and stop flag.
  * CHAINED   one launch per iteration: each launch first completes the
  *           previous iteration's scalar steps (every block computes them
- *           from the partials), then sweeps.  q = 1 without consensus,
- *           m <= 4 and n <= 524288 only (ADMM_E_UNSUPPORTED otherwise).
+ *           from the partials), then sweeps.  q = 1 without consensus
+ *           and m <= 4 only (ADMM_E_UNSUPPORTED otherwise).
  * RESIDENT  one cooperative launch whose blocks keep their columns in
  *           registers and meet at a grid barrier every iteration; only
  *           when every block fits on the device at once (else

@@ -103,10 +103,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P0) {
 
 // ------------------------------------------------------ chained iteration
 //
-// Single-scenario problems (q = 1, no consensus, m <= 4) whose columns fit
-// in at most kChainMaxBlocks blocks of kChainBlock threads run one launch
-// per iteration (1024-thread blocks cap a kernel at 128 VGPRs, which the
-// column code for up to four sources fits).  Launch t first completes iteration t-1: every block sums the
+// Single-scenario problems (q = 1, no consensus, m <= 4) run one launch per
+// iteration on at most kChainMaxBlocks blocks of kChainBlock threads, each
+// block sweeping `chunks` chunks of kChainBlock columns (1024-thread blocks
+// cap a kernel at 128 VGPRs, which the column code for up to four sources
+// fits).  Launch t first completes iteration t-1: every block sums the
 // block partials that launch t-1 left, in the same fixed order, so every
 // block derives bit-identical scalars (7b)+(7g), (7d)+(7i), residuals and
 // stop decision.  Then it sweeps iteration t with them and leaves its own
@@ -395,7 +396,7 @@ __device__ __forceinline__ void chain_partials(const SolveParams &P, double *par
     }
 }
 
-template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int ME>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int ME, bool MULTI>
 __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     const int ws = rs ^ 1;
     __shared__ ChainShared<MAXM> sh;
@@ -410,12 +411,11 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     // the partial reads first, then the column loads (which do not depend
     // on the scalars): the scalar steps wait only for the former, and each
     // wave starts its sweep as soon as its own columns arrive
-    const int k = blockIdx.x * kChainBlock + threadIdx.x;
-    const bool live = k < P.n;
+    int k = blockIdx.x * kChainBlock * (MULTI ? P.chunks : 1) + threadIdx.x;
     ChainLoads L;
     chain_load<kChainBlock>(P, rs, L);
     Col<T, MAXM> d;
-    if (live) col_load<T, MAXM, ME>(P, 0, k, d);
+    if (k < P.n) col_load<T, MAXM, ME>(P, 0, k, d);
     chain_finish<MAXM, kChainBlock>(P, rs, L, sh);
     if (sh.done) {
         // a mu divisor decided here stays pending for the export
@@ -440,10 +440,25 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     scal_bounds<MAXM>(P.slo, P.shi, src_count<ME>(P), sc);
     Acc<MAXM> acc;
     acc.reset();
-    if (live) {
+    if (k < P.n) {
         if (Q.wdiv != 1.0) col_rescale_mu(d, Q.wdiv);
         col_update<T, MAXM, MODE, CHECK, FEAT, ME>(Q, 0, k, d, sc, acc);
         col_store<T, MAXM, ME>(Q, 0, k, d);
+    }
+    if (MULTI) {
+        // large n: the block's later chunks in turn (chunk 0 was loaded
+        // before the scalar steps); other waves of the SIMD cover each
+        // chunk's load latency
+#pragma nounroll
+        for (int c = 1; c < P.chunks; ++c) {
+            k += kChainBlock;
+            if (k < P.n) {
+                col_load<T, MAXM, ME>(P, 0, k, d);
+                if (Q.wdiv != 1.0) col_rescale_mu(d, Q.wdiv);
+                col_update<T, MAXM, MODE, CHECK, FEAT, ME>(Q, 0, k, d, sc, acc);
+                col_store<T, MAXM, ME>(Q, 0, k, d);
+            }
+        }
     }
     chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red);
     if (blockIdx.x == 0) {
@@ -901,13 +916,19 @@ hipError_t launch_persist(const SolveParams &P, int dtype, uint32_t *bar, int ch
     return hipLaunchCooperativeKernel(fn, dim3(P.nblk * P.q), dim3(kBlock), args, 0, s);
 }
 
+template <typename T, int MODE, bool CHECK, int FEAT, bool MULTI>
+static void launch_chain_m(const SolveParams &P, int rs, hipStream_t s) {
+    const dim3 grid(P.nblk);
+    if (P.m == 2) k_chain<T, 2, MODE, CHECK, FEAT, 2, MULTI><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else if (P.m == 4) k_chain<T, 4, MODE, CHECK, FEAT, 4, MULTI><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else if (P.m < 2) k_chain<T, 2, MODE, CHECK, FEAT, 0, MULTI><<<grid, kChainBlock, 0, s>>>(P, rs);
+    else k_chain<T, 4, MODE, CHECK, FEAT, 0, MULTI><<<grid, kChainBlock, 0, s>>>(P, rs);
+}
+
 template <typename T, int MODE, bool CHECK, int FEAT>
 static void launch_chain_f(const SolveParams &P, int rs, hipStream_t s) {
-    const dim3 grid(P.nblk);
-    if (P.m == 2) k_chain<T, 2, MODE, CHECK, FEAT, 2><<<grid, kChainBlock, 0, s>>>(P, rs);
-    else if (P.m == 4) k_chain<T, 4, MODE, CHECK, FEAT, 4><<<grid, kChainBlock, 0, s>>>(P, rs);
-    else if (P.m < 2) k_chain<T, 2, MODE, CHECK, FEAT, 0><<<grid, kChainBlock, 0, s>>>(P, rs);
-    else k_chain<T, 4, MODE, CHECK, FEAT, 0><<<grid, kChainBlock, 0, s>>>(P, rs);
+    if (P.chunks > 1) launch_chain_m<T, MODE, CHECK, FEAT, true>(P, rs, s);
+    else launch_chain_m<T, MODE, CHECK, FEAT, false>(P, rs, s);
 }
 
 // The common case (no g0, per-source bounds, no branch codes, Gauss-Seidel,

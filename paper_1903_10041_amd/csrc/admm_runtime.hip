@@ -294,10 +294,24 @@ int persist_columns(admm_context *ctx, int dtype, int m, int n, int q, bool forc
 }
 
 // The chained path applies to single-scenario problems of up to four
-// sources whose columns fit in kChainMaxBlocks blocks.
+// sources (no consensus).
 static bool chain_applies(const admm_problem *pr, const admm_settings *s) {
-    return pr->q == 1 && !s->consensus_q1 && pr->m <= 4 &&
-           (pr->n + kChainBlock - 1) / kChainBlock <= kChainMaxBlocks;
+    return pr->q == 1 && !s->consensus_q1 && pr->m <= 4;
+}
+
+// Chained grid: one block per kChainBlock columns while that fits in
+// kChainMaxBlocks blocks; beyond, one block per compute unit, each sweeping
+// its columns in chunks of kChainBlock.
+static void chain_grid(admm_context *ctx, int n, int &nblk, int &chunks) {
+    const int nb1 = (n + kChainBlock - 1) / kChainBlock;
+    if (nb1 <= kChainMaxBlocks) {
+        nblk = nb1;
+        chunks = 1;
+        return;
+    }
+    const int target = std::min(kChainMaxBlocks, std::max(1, ctx->num_cu));
+    chunks = (n + kChainBlock * target - 1) / (kChainBlock * target);
+    nblk = (n + kChainBlock * chunks - 1) / (kChainBlock * chunks);
 }
 
 int finalize_group(int m, int q, int nblk) {
@@ -327,7 +341,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         break;
     case ADMM_LAUNCH_CHAINED:
         if (!chain_applies(pr, s))
-            return fail(ADMM_E_UNSUPPORTED, "the chained launch needs q = 1, no consensus, m <= 4, n <= 524288");
+            return fail(ADMM_E_UNSUPPORTED, "the chained launch needs q = 1, no consensus and m <= 4");
         chain = true;
         break;
     case ADMM_LAUNCH_SPLIT:
@@ -338,12 +352,19 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         break;
     }
     if (R > 0) cpt = R;
-    // the chained grid has kChainBlock columns per block; the cold-start
-    // kernel covers them as kChainBlock / kBlock columns per thread
-    if (chain) cpt = kChainBlock / kBlock;
+    // the chained grid has kChainBlock * chunks columns per block; the
+    // cold-start kernel covers them as kChainBlock / kBlock * chunks
+    // columns per thread
+    int chunks = 1;
+    if (chain) {
+        int nb = 0;
+        chain_grid(ctx, n, nb, chunks);
+        cpt = kChainBlock / kBlock * chunks;
+    }
     const int nblk = (n + kBlock * cpt - 1) / (kBlock * cpt);
     P.persistent = R > 0;
     P.chain = chain ? 1 : 0;
+    P.chunks = chunks;
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     P.group = finalize_group(m, q, nblk);
