@@ -422,6 +422,11 @@ extern "C" admm_status admm_solve_batch(admm_context *ctx, int32_t count, const 
 //      free the memory, publish the result for admm_poll.
 // A request's arithmetic is the batched kernel's, which does not depend on
 // the other residents, so a result is the same alone and in the mix.
+// Requests with n >= big_n (default 8192) instead run on lanes: each lane is
+// a context of its own whose thread solves one request at a time through
+// admm_solve (the chained launch) on its own stream, next to the batched
+// windows; their warm states are kept on the host.  A single block per
+// instance would otherwise hold every window for the largest horizon.
 
 #include <condition_variable>
 #include <deque>
@@ -570,9 +575,29 @@ static void launch_serve_warm(int cls, const BatchParams &B, const WarmSrc *ws, 
 constexpr int kServeMaxSlots = 16384;
 constexpr size_t kServeMaxQueue = 1u << 20;
 
+// Warm state of a request served on a lane: x [m][n] and w = s - mu [n]
+// of its final iterate, lambda and p per source.
+struct HostWarm {
+    int m = 0, n = 0;
+    std::vector<double> x, w, lam, p;
+};
+
+struct ServeLane {
+    admm_context *sub = nullptr;        // own stream, workspace and graphs
+    std::thread th;
+    std::deque<ServeReq *> q;
+};
+
 struct ServeState {
     std::mutex mu;
     std::condition_variable cv;
+    // requests with n >= big_n run on lanes: one plain (chained) solve at a
+    // time per lane, on its own stream, next to the batched windows
+    int big_n = 8192;
+    std::vector<ServeLane *> lanes;
+    std::condition_variable lcv;
+    std::unordered_map<uint64_t, HostWarm> hwarm;
+    size_t lane_budget = 0;
     std::deque<ServeReq *> pending;
     std::vector<ServeReq *> active;
     std::unordered_map<uint64_t, ServeReq *> done;
@@ -609,6 +634,50 @@ static void serve_fail(ServeState *ss, const std::string &msg) {
     ss->failed = true;
     ss->fail_msg = msg;
     ss->cv.notify_all();
+}
+
+// A key last solved on a lane moves to the batched path: its host warm
+// state goes into the arena as a warm entry (storage type, padded rows).
+// Called with ss->mu held; false when nothing was moved.
+static bool adopt_host_warm(ServeState *ss, uint64_t key, size_t T, hipStream_t s) {
+    auto hit = ss->hwarm.find(key);
+    if (hit == ss->hwarm.end()) return false;
+    const HostWarm &hw = hit->second;
+    const size_t n_pad = (size_t)(hw.n + kPad - 1) / kPad * kPad, rows = (size_t)hw.m * n_pad;
+    WarmEntry we;
+    we.m = hw.m;
+    we.n = hw.n;
+    we.n_pad = (int)n_pad;
+    we.bytes = (rows + n_pad) * T;
+    we.off = ss->fl.alloc(we.bytes);
+    if (we.off == SIZE_MAX) {
+        ss->hwarm.erase(hit);
+        return false;
+    }
+    std::vector<char> img(we.bytes, 0);
+    for (int i = 0; i < hw.m; ++i)
+        for (int k = 0; k < hw.n; ++k) {
+            const double v = hw.x[(size_t)i * hw.n + k];
+            if (T == 8) ((double *)img.data())[(size_t)i * n_pad + k] = v;
+            else ((float *)img.data())[(size_t)i * n_pad + k] = (float)v;
+        }
+    for (int k = 0; k < hw.n; ++k) {
+        if (T == 8) ((double *)img.data())[rows + k] = hw.w[k];
+        else ((float *)img.data())[rows + k] = (float)hw.w[k];
+    }
+    char *base = (char *)ss->arena.p;
+    if (hipMemcpyAsync(base + we.off, img.data(), we.bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        ss->fl.release(we.off, we.bytes);
+        ss->hwarm.erase(hit);
+        return false;
+    }
+    we.lam = hw.lam;
+    we.p = hw.p;
+    we.stamp = ++ss->stamp;
+    ss->warm[key] = we;
+    ss->hwarm.erase(hit);
+    return true;
 }
 
 static void evict_warm_lru(ServeState *ss) {
@@ -721,9 +790,19 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
             fi[f] = r->inst;
             const int a = (int)(std::find(ss->active.begin(), ss->active.end(), r) - ss->active.begin());
             const int cls = batch_class(r->m);
-            auto wit = r->key ? ss->warm.find(r->key) : ss->warm.end();
-            if (wit != ss->warm.end() && wit->second.m == r->m) {
-                WarmEntry &we = wit->second;
+            WarmEntry we;
+            bool have = false;
+            if (r->key) {
+                std::lock_guard<std::mutex> lk(ss->mu);
+                auto wit = ss->warm.find(r->key);
+                if (wit == ss->warm.end() && adopt_host_warm(ss, r->key, T, s))
+                    wit = ss->warm.find(r->key);
+                if (wit != ss->warm.end() && wit->second.m == r->m) {
+                    we = wit->second;
+                    have = true;
+                }
+            }
+            if (have) {
                 WarmSrc w;
                 std::memset(&w, 0, sizeof w);
                 w.idx = a;
@@ -873,6 +952,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
             // warm store: x and w of this final iterate, lambda and p
             if (r->key) {
                 std::lock_guard<std::mutex> lk(ss->mu);
+                ss->hwarm.erase(r->key);
                 auto it = ss->warm.find(r->key);
                 if (it != ss->warm.end()) {
                     ss->fl.release(it->second.off, it->second.bytes);
@@ -919,6 +999,184 @@ static void serve_main(admm_context *ctx, ServeState *ss) {
     }
 }
 
+// A lane request's warm start, as the batched path builds it: x and w
+// shifted one step (steps past the old horizon take the cold defaults), x
+// clamped into the new box, lambda and p from the previous solve,
+// z = g(x), h = min(c, sum_k g(x)).
+static void lane_warm_state(const ServeReq *r, const HostWarm &hw, std::vector<double> &x,
+                            std::vector<double> &sv, std::vector<double> &mu, std::vector<double> &h,
+                            std::vector<double> &p, std::vector<double> &nu, std::vector<double> &xbar1,
+                            std::vector<double> &lam, std::vector<double> &zoff) {
+    const int m = r->m, n = r->n;
+    x.assign((size_t)m * n, 0.0);
+    sv.assign(n, 0.0);
+    mu.assign(n, 0.0);
+    h.assign(m, 0.0);
+    p = hw.p;
+    nu.assign(m, 0.0);
+    xbar1.assign(m, 0.0);
+    lam = hw.lam;
+    zoff.assign(m, 0.0);
+    std::vector<double> gs(m, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const bool have = k + 1 < hw.n;
+        double sx = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double lo = r->lo[i], hi = r->hi[i];
+            const double x0 = have ? hw.x[(size_t)i * hw.n + k + 1] : std::min(std::max(0.0, lo), hi);
+            const double xv = std::min(std::max(x0, lo), hi);
+            const size_t e = (size_t)i * n + k;
+            x[e] = xv;
+            gs[i] += (r->g2[e] * xv + r->g1[e]) * xv;
+            sx += xv;
+        }
+        const double wv = have ? hw.w[k + 1] : std::max(0.0, sx - r->y[k]);
+        sv[k] = std::max(wv, 0.0);
+        mu[k] = std::max(-wv, 0.0);
+    }
+    for (int i = 0; i < m; ++i) {
+        h[i] = std::min(r->c[i], gs[i]);
+        xbar1[i] = x[(size_t)i * n];
+    }
+}
+
+static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        ServeReq *r = nullptr;
+        HostWarm hw;
+        WarmEntry dev_we;
+        bool have_warm = false, have_dev = false;
+        {
+            std::unique_lock<std::mutex> lk(ss->mu);
+            ss->lcv.wait(lk, [&] { return ss->stop || !ln->q.empty(); });
+            if (ss->stop) return;
+            r = ln->q.front();
+            ln->q.pop_front();
+            if (r->key) {
+                auto it = ss->hwarm.find(r->key);
+                if (it != ss->hwarm.end() && it->second.m == r->m) {
+                    hw = it->second;
+                    have_warm = true;
+                } else if (it == ss->hwarm.end()) {
+                    // last solved on the batched path: take its entry out of
+                    // the map (the region stays reserved until read back)
+                    auto wit = ss->warm.find(r->key);
+                    if (wit != ss->warm.end()) {
+                        dev_we = wit->second;
+                        ss->warm.erase(wit);
+                        have_dev = true;
+                    }
+                }
+            }
+        }
+        if (have_dev) {
+            const size_t T = ss->dtype == 0 ? 8 : 4, rows = (size_t)dev_we.m * dev_we.n_pad;
+            std::vector<char> img(dev_we.bytes);
+            const char *base = (const char *)ss->arena.p;
+            const bool ok = hipMemcpyAsync(img.data(), base + dev_we.off, dev_we.bytes, hipMemcpyDeviceToHost,
+                                           ln->sub->own) == hipSuccess &&
+                            hipStreamSynchronize(ln->sub->own) == hipSuccess;
+            {
+                std::lock_guard<std::mutex> lk(ss->mu);
+                ss->fl.release(dev_we.off, dev_we.bytes);
+            }
+            if (ok && dev_we.m == r->m) {
+                auto at = [&](size_t e) {
+                    return T == 8 ? ((const double *)img.data())[e] : (double)((const float *)img.data())[e];
+                };
+                hw.m = dev_we.m;
+                hw.n = dev_we.n;
+                hw.x.resize((size_t)hw.m * hw.n);
+                hw.w.resize(hw.n);
+                for (int i = 0; i < hw.m; ++i)
+                    for (int k = 0; k < hw.n; ++k) hw.x[(size_t)i * hw.n + k] = at((size_t)i * dev_we.n_pad + k);
+                for (int k = 0; k < hw.n; ++k) hw.w[k] = at(rows + k);
+                hw.lam = dev_we.lam;
+                hw.p = dev_we.p;
+                have_warm = true;
+            }
+        }
+        admm_problem pr;
+        std::memset(&pr, 0, sizeof pr);
+        pr.m = r->m;
+        pr.n = r->n;
+        pr.q = 1;
+        pr.mem = ADMM_HOST;
+        pr.dtype = ADMM_F64;
+        pr.f2 = r->f2.data();
+        pr.f1 = r->f1.data();
+        pr.g2 = r->g2.data();
+        pr.g1 = r->g1.data();
+        pr.bounds = ADMM_BOUNDS_PER_SOURCE;
+        pr.x_lo = r->lo.data();
+        pr.x_hi = r->hi.data();
+        pr.y = r->y.data();
+        pr.c = r->c.data();
+        std::vector<double> wx, ws_, wmu, wh, wp, wnu, wxb, wlam, wzoff;
+        admm_state warm;
+        std::memset(&warm, 0, sizeof warm);
+        if (have_warm) {
+            lane_warm_state(r, hw, wx, ws_, wmu, wh, wp, wnu, wxb, wlam, wzoff);
+            warm.x = wx.data(); warm.s = ws_.data(); warm.mu = wmu.data(); warm.h = wh.data();
+            warm.p = wp.data(); warm.nu = wnu.data(); warm.xbar1 = wxb.data();
+            warm.lambda_s = wlam.data(); warm.zoff_s = wzoff.data();
+        }
+        r->x.assign((size_t)r->m * r->n, 0.0);
+        std::vector<double> ox, os, omu, oh, op, olam, ozoff;
+        admm_state out;
+        std::memset(&out, 0, sizeof out);
+        if (r->key) {
+            ox.resize((size_t)r->m * r->n);
+            os.resize(r->n);
+            omu.resize(r->n);
+            oh.resize(r->m);
+            op.resize(r->m);
+            olam.resize(r->m);
+            ozoff.resize(r->m);
+            out.x = ox.data(); out.s = os.data(); out.mu = omu.data(); out.h = oh.data(); out.p = op.data();
+            out.lambda_s = olam.data(); out.zoff_s = ozoff.data();
+        }
+        admm_info inf;
+        std::memset(&inf, 0, sizeof inf);
+        const admm_status st = admm_solve(ln->sub, &pr, &r->S, have_warm ? &warm : nullptr, r->x.data(),
+                                          r->key ? &out : nullptr, &inf);
+        if (st < 0) {
+            std::memset(&inf, 0, sizeof inf);
+            inf.status = st;
+        }
+        inf.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r->t_submit).count();
+        r->info = inf;
+        std::lock_guard<std::mutex> lk(ss->mu);
+        if (r->key && st >= 0) {
+            auto wit = ss->warm.find(r->key);
+            if (wit != ss->warm.end()) {
+                ss->fl.release(wit->second.off, wit->second.bytes);
+                ss->warm.erase(wit);
+            }
+            HostWarm nw;
+            nw.m = r->m;
+            nw.n = r->n;
+            nw.x = std::move(ox);
+            nw.w.resize(r->n);
+            for (int k = 0; k < r->n; ++k) nw.w[k] = os[k] - omu[k];
+            nw.lam = std::move(olam);
+            nw.p = std::move(op);
+            ss->hwarm[r->key] = std::move(nw);
+        }
+        r->f2.clear(); r->f1.clear(); r->g2.clear(); r->g1.clear(); r->y.clear();
+        ss->done[r->ticket] = r;
+        ss->cv.notify_all();
+    }
+}
+
+// Device memory a lane request needs in its sub-context (workspace and
+// host-input staging), an upper estimate.
+static size_t lane_request_bytes(int m, int n, size_t T) {
+    const size_t n_pad = (size_t)(n + kPad - 1) / kPad * kPad, E = (size_t)m * n_pad;
+    return E * 5 * T + 2 * n_pad * T + (4 * (size_t)m * n + n) * sizeof(double) + ((size_t)1 << 20);
+}
+
 void serve_shutdown(admm_context *ctx) {
     ServeState *ss = ctx->serve;
     if (!ss) return;
@@ -927,7 +1185,15 @@ void serve_shutdown(admm_context *ctx) {
         ss->stop = true;
         ss->cv.notify_all();
     }
+    ss->lcv.notify_all();
     if (ss->worker.joinable()) ss->worker.join();
+    for (ServeLane *ln : ss->lanes) {
+        if (ln->th.joinable()) ln->th.join();
+        for (ServeReq *r : ln->q) delete r;
+        if (ln->sub) admm_destroy(ln->sub);
+        delete ln;
+    }
+    ss->lanes.clear();
     for (ServeReq *r : ss->pending) delete r;
     for (ServeReq *r : ss->active) delete r;
     for (auto &kv : ss->done) delete kv.second;
@@ -951,10 +1217,16 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
         return fail(ADMM_E_DEVICE, "stream creation failed");
     }
     const size_t left = ctx->arena.budget > ctx->arena.used ? ctx->arena.budget - ctx->arena.used : 0;
-    // at most three quarters of the budget, so plain and batched solves on
-    // the same context keep room for their workspaces
-    size_t bytes = std::min(left, ctx->arena.budget / 4 * 3);
+    // at most five eighths of the budget for the batched residents and one
+    // eighth for the lanes, so plain and batched solves on the same context
+    // keep room for their workspaces
+    size_t bytes = std::min(left, ctx->arena.budget / 8 * 5);
     bytes = std::min(bytes, (size_t)16 << 30) & ~size_t(255);
+    if (const char *e = std::getenv("ADMM_SERVE_BIG_N")) ss->big_n = std::max(0, std::atoi(e));
+    int nlanes = 2;
+    if (const char *e = std::getenv("ADMM_SERVE_LANES")) nlanes = std::max(0, std::min(16, std::atoi(e)));
+    if (ss->big_n == 0) nlanes = 0;
+    ss->lane_budget = nlanes ? ctx->arena.budget / 8 / nlanes : 0;
     admm_status st = ctx->arena.ensure(ss->arena, bytes);
     if (st != ADMM_OK) {
         (void)hipStreamDestroy(ss->s);
@@ -962,8 +1234,19 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
         return st;
     }
     ss->fl.reset(bytes);
+    for (int l = 0; l < nlanes; ++l) {
+        ServeLane *ln = new ServeLane();
+        admm_settings d = ctx->defaults;
+        if (admm_create(&ln->sub, ctx->device, ss->lane_budget, &d) != ADMM_OK) {
+            delete ln;
+            break;
+        }
+        ss->lanes.push_back(ln);
+    }
+    if (ss->lanes.empty()) ss->big_n = 0;
     ctx->serve = ss;
     ss->worker = std::thread(serve_main, ctx, ss);
+    for (ServeLane *ln : ss->lanes) ln->th = std::thread(lane_main, ctx, ss, ln);
     return ADMM_OK;
 }
 
@@ -996,7 +1279,10 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     r->n = prob->n;
     r->n_pad = (prob->n + kPad - 1) / kPad * kPad;
     r->bytes = serve_chunk_bytes(r->m, r->n_pad, T, nullptr);
-    if (r->bytes > ss->fl.total()) {
+    // a long horizon goes to a lane when its solve fits a lane's budget,
+    // else it stays on the batched path
+    const bool big = ss->big_n > 0 && r->n >= ss->big_n && lane_request_bytes(r->m, r->n, T) <= ss->lane_budget;
+    if (!big && r->bytes > ss->fl.total()) {
         delete r;
         return fail(ADMM_E_OUT_OF_BUDGET, "instance larger than the serving arena");
     }
@@ -1037,8 +1323,16 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     }
     r->ticket = ss->next_ticket++;
     ss->issued[r->ticket] = 1;
-    ss->pending.push_back(r);
-    ss->cv.notify_all();
+    if (big) {
+        ServeLane *best = ss->lanes[0];
+        for (ServeLane *ln : ss->lanes)
+            if (ln->q.size() < best->q.size()) best = ln;
+        best->q.push_back(r);
+        ss->lcv.notify_all();
+    } else {
+        ss->pending.push_back(r);
+        ss->cv.notify_all();
+    }
     *ticket = r->ticket;
     return ADMM_OK;
 }
@@ -1076,5 +1370,6 @@ extern "C" admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key) {
         ss->fl.release(it->second.off, it->second.bytes);
         ss->warm.erase(it);
     }
+    ss->hwarm.erase(warm_key);
     return ADMM_OK;
 }

@@ -164,3 +164,60 @@ def test_submit_from_many_threads():
     assert len(set(tickets)) == len(tickets)
     assert all(o[1]["status"] == admm.OK for o in outs)
     ctx.close()
+
+
+def test_long_horizons_on_lanes_equal_plain_solve():
+    """Requests with n >= 8192 run on the serving lanes through admm_solve:
+    a cold one gives exactly what admm_solve gives for it alone, also when
+    it shares the engine with short requests and with other long ones."""
+    ctx = admm.Context(0, hbm_budget_bytes=4 << 30)
+    plain = admm.Context(0, hbm_budget_bytes=1 << 30)
+    s = settings()
+    long_ = [W.uniform_problem(m, n, 4300 + r) for r, (m, n) in
+             enumerate([(4, 8192), (2, 20000), (4, 33333), (3, 12001), (4, 9000)])]
+    short = requests(12, 404, n_hi=2000)
+    print("[serve] 5 long + 12 short requests", flush=True)
+    mix = [(p, ctx.submit(p, s)) for p in (short[:6] + long_ + short[6:])]
+    outs = [(p, wait(ctx, t, p)) for p, t in mix]
+    for p, (x, inf) in outs:
+        assert inf["status"] == admm.OK
+        if p.n >= 8192:
+            xr, ir, _ = plain.solve(p, s)
+            assert np.array_equal(x.reshape(-1), xr.reshape(-1)), p.n
+            assert inf["iters"] == ir["iters"]
+            assert inf["objective"] == ir["objective"]
+        else:
+            xb, ib = ctx.solve_batch([p], s)
+            assert np.array_equal(x, xb[0])
+    plain.close()
+    ctx.close()
+
+
+def test_warm_keys_across_lanes_and_batched_path():
+    """A key whose horizon crosses the lane threshold carries its warm state
+    from one path to the other; the results do not depend on the other
+    streams, and a warm solve reaches the cold optimum."""
+    streams = {
+        1: [W.uniform_problem(2, n, 4400 + r) for r, n in enumerate([8200, 8193, 8191, 8100, 8192, 9000])],
+        2: [W.uniform_problem(4, n, 4410 + r) for r, n in enumerate([8150, 8300, 8250])],
+        3: [W.uniform_problem(4, n, 4420 + r) for r, n in enumerate([500, 700, 650])],
+    }
+    s = settings(precision=admm.F64, eps_primal=1e-6, eps_dual=1e-6)
+    print("[serve] warm keys across lanes, alone vs mix", flush=True)
+    ctx_a = admm.Context(0, hbm_budget_bytes=2 << 30)
+    alone = _run_streams(ctx_a, streams, s, interleave=False)
+    ctx_a.close()
+    ctx_b = admm.Context(0, hbm_budget_bytes=2 << 30)
+    mixed = _run_streams(ctx_b, streams, s, interleave=True)
+    cold = admm.Context(0, hbm_budget_bytes=1 << 30)
+    for key in alone:
+        xa, ia = alone[key]
+        xm, im = mixed[key]
+        assert ia["status"] == admm.OK
+        assert np.array_equal(xa, xm), key
+        assert ia["iters"] == im["iters"], key
+        p = streams[key[0]][key[1]]
+        _, ic, _ = cold.solve(p, s)
+        assert abs(ia["objective"] - ic["objective"]) <= 1e-5 * (1 + abs(ic["objective"])), key
+    cold.close()
+    ctx_b.close()
