@@ -440,7 +440,7 @@ def run_serve(args):
         t = ctx.submit(p, s)
         while ctx.poll(t, p.m, p.n) is None:
             time.sleep(0.001)
-    lat, iters, status = [], [], []
+    lat, iters, status, horizon = [], [], [], []
     submitted = {}
     done_flag = [False]
     lock = threading.Lock()
@@ -455,6 +455,7 @@ def run_serve(args):
                 out = ctx.poll(t, p.m, p.n)
                 if out is not None:
                     lat.append(time.perf_counter() - ts)
+                    horizon.append(p.n)
                     iters.append(out[1]["iters"])
                     status.append(out[1]["status"])
                     with lock:
@@ -481,13 +482,26 @@ def run_serve(args):
     t_all = time.perf_counter() - t0
     ctx.close()
     lat_ms = np.array(lat) * 1000.0
+    hz = np.array(horizon)
+    it = np.array(iters)
+    # requests with n >= 8192 run on the serving lanes (admm_solve), the
+    # rest in the batched windows
+    lanes = hz >= 8192
+
+    def pct(sel):
+        if not sel.any():
+            return None
+        return {"count": int(sel.sum()), "p50_ms": float(np.percentile(lat_ms[sel], 50)),
+                "p99_ms": float(np.percentile(lat_ms[sel], 99)),
+                "iters_p50": float(np.percentile(it[sel], 50)), "iters_p99": float(np.percentile(it[sel], 99))}
     return {"workload": f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, m in {{2,4}}, "
                         f"n log-uniform [100, 50000] (pool of {len(pool)}), 256 warm keys, residual 1e-4, "
                         "f32 storage, rho_2 / n",
             "requests": nreq, "completed": len(lat), "converged": int(sum(st == admm.OK for st in status)),
             "solves_per_s": len(lat) / t_all, "offered_per_s": nreq / t_sub,
             "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-            "max_ms": float(lat_ms.max()), "mean_iters": float(np.mean(iters)), "drain_s": t_all - t_sub}
+            "max_ms": float(lat_ms.max()), "mean_iters": float(np.mean(iters)), "drain_s": t_all - t_sub,
+            "long_n_ge_8192": pct(lanes), "short": pct(~lanes)}
 
 
 def run_robust(args):

@@ -610,6 +610,10 @@ struct ServeState {
     uint64_t next_ticket = 1, stamp = 0;
     int dtype = -1;
     int window = 50;
+    // per-instance window: window * win_ref / (m * columns per thread) when
+    // that is smaller, at least check_every, so one window costs about the
+    // same for every resident and a long horizon does not hold the others
+    int win_ref = 16;
     DevBuf arena, inst, order, next, src, stage, wsrc;
     FreeList fl;
     hipStream_t s = nullptr;
@@ -1211,6 +1215,7 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
     ServeState *ss = new ServeState();
     ss->dtype = dtype;
     if (const char *e = std::getenv("ADMM_SERVE_WINDOW")) ss->window = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("ADMM_SERVE_WINDOW_REF")) ss->win_ref = std::max(0, std::atoi(e));
     DeviceGuard g(ctx->device);
     if (hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) != hipSuccess) {
         delete ss;
@@ -1312,6 +1317,13 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     if (S.rho2_per_step) I.rho[1] = S.rho[1] / (double)r->n;
     I.eps_p = S.eps_primal;
     I.eps_d = S.eps_dual;
+    if (ss->win_ref > 0) {
+        // an instance's window does not change its arithmetic (the state
+        // stays exact between launches), only when it yields
+        const long work = (long)r->m * ((r->n + kBlock - 1) / kBlock);
+        if (work > ss->win_ref)
+            I.window = (int32_t)std::max<long>(S.check_every, (long)ss->window * ss->win_ref / work);
+    }
     std::lock_guard<std::mutex> lk(ss->mu);
     if (ss->failed) {
         delete r;

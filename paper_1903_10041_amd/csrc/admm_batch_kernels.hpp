@@ -16,6 +16,7 @@ namespace admm {
 struct BInst {
     int32_t m, n, n_pad, status;     // status: -1 running, 0 converged, 2 max_iter, -4 numerical
     int32_t t, max_iter, check_every, flags;   // flags: 1 paper_project, 2 jacobi
+    int32_t window, pad_;            // iterations per launch for this instance (0: the launch's)
     int64_t coef_off, x_off, col_off, pool_off, w_off;
     double rho[4];
     double eps_p, eps_d;
@@ -178,7 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
         const double nd = (double)n;
         const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
         int status = -1;
-        for (int wi = 0; wi < B.window; ++wi) {
+        const int win = I.window > 0 ? min(I.window, B.window) : B.window;
+        for (int wi = 0; wi < win; ++wi) {
             const int t1 = s_t + 1;
             if (t1 > P.max_iter) break;
             const bool check = (t1 % P.check_every) == 0;
