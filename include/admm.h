@@ -211,7 +211,20 @@ admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_proble
  * the HBM budget allow, and runs alongside the others already resident.
  * warm_key != 0 warm-starts from the final state of the previous request
  * with the same key (shifted to the new horizon as a receding-horizon
- * re-solve, Alg. 2) and stores this request's final state under it. */
+ * re-solve, Alg. 2) and stores this request's final state under it.
+ * Requests with n >= 8192 run on lanes instead: sub-contexts (each with
+ * 1/16 of this context's budget and its own stream and thread) that solve
+ * one request at a time through admm_solve, so their result equals
+ * admm_solve's.  Environment, read when serving starts on a context:
+ * ADMM_SERVE_BIG_N (8192, 0 = no lanes), ADMM_SERVE_LANES (2),
+ * ADMM_SERVE_WINDOW (50 iterations per window), ADMM_SERVE_WINDOW_REF (16:
+ * requests with m * ceil(n / 256) above it yield after proportionally
+ * fewer iterations; 0 = off).  Two requests with the same key in flight at
+ * once race for its warm state.  Errors: ADMM_E_UNSUPPORTED (device
+ * arrays, q > 1, f0/g0, per-step bounds, adaptive rho),
+ * ADMM_E_OUT_OF_BUDGET (an instance larger than the serving arena),
+ * ADMM_E_QUEUE_FULL, ADMM_E_INVALID_ARG (mixed precisions on one
+ * context, invalid inputs). */
 admm_status admm_submit(admm_context *ctx, const admm_problem *prob,
                         const admm_settings *settings, uint64_t warm_key,
                         uint64_t *ticket);
