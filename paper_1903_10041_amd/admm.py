@@ -322,7 +322,123 @@ class Context:
         return x_out, out, st_out
 
 
+def _np_dtype(struct):
+    """numpy dtype with the field layout of a ctypes Structure (pointers as
+    uint64), for vectorised fills of record arrays."""
+    names, formats, offsets = [], [], []
+    for name, ct in struct._fields_:
+        f = getattr(struct, name)
+        if ct is C.c_void_p:
+            fmt = np.uint64
+        elif ct in (C.c_int32, C.c_int):
+            fmt = np.int32
+        elif ct is C.c_double:
+            fmt = np.float64
+        elif issubclass(ct, C.Array):
+            fmt = (np.dtype({C.c_double: np.float64, C.c_int64: np.int64}[ct._type_]), ct._length_)
+        else:
+            raise TypeError(f"field {name}: {ct}")
+        names.append(name)
+        formats.append(fmt)
+        offsets.append(f.offset)
+    return np.dtype({"names": names, "formats": formats, "offsets": offsets, "itemsize": C.sizeof(struct)})
+
+
+def _records(struct, count):
+    arr = (struct * max(1, count))()
+    return arr, np.frombuffer(memoryview(arr).cast("B"), dtype=_np_dtype(struct))[:count]
+
+
+class BatchPack:
+    """Instances of program (1) (q = 1, per-source bounds, no f0/g0) laid
+    out back to back in flat arrays (torch device tensors or numpy host
+    arrays), with the admm_problem records, the output array and its
+    per-instance pointers built once: a batched call on a pack does no
+    per-instance Python work.  ``x`` is the flat output (instance b's
+    [m][n] block at ``x_off[b]``)."""
+
+    def __init__(self, probs):
+        if not probs:
+            raise ValueError("empty batch")
+        for p in probs:
+            if (p.q != 1 or getattr(p, "f0", None) is not None or getattr(p, "g0", None) is not None
+                    or (p.xlo.dim() if _is_torch(p.xlo) else np.asarray(p.xlo).ndim) != 1):
+                raise ValueError("a pack holds q = 1 instances with per-source bounds and no f0/g0")
+        self.count = len(probs)
+        self.m = np.array([p.m for p in probs], dtype=np.int64)
+        self.n = np.array([p.n for p in probs], dtype=np.int64)
+        e = self.m * self.n
+        self.x_off = np.concatenate(([0], np.cumsum(e)[:-1]))
+        y_off = np.concatenate(([0], np.cumsum(self.n)[:-1]))
+        s_off = np.concatenate(([0], np.cumsum(self.m)[:-1]))
+        dev = _is_torch(probs[0].f2)
+        self.device = dev
+        if dev:
+            import torch
+            dt = probs[0].f2.dtype
+            if dt not in (torch.float64, torch.float32):
+                raise TypeError("device arrays must be float64 or float32")
+
+            def cat(name):
+                return torch.cat([getattr(p, name).reshape(-1).to(dt) for p in probs]).contiguous()
+            self.dtype = F64 if dt == torch.float64 else F32_MIXED
+            esize = 8 if dt == torch.float64 else 4
+            self.x = torch.empty(int(e.sum()), dtype=dt, device=probs[0].f2.device)
+
+            def base(t):
+                return t.data_ptr()
+        else:
+            def cat(name):
+                return np.ascontiguousarray(np.concatenate([np.asarray(getattr(p, name), dtype=np.float64).reshape(-1)
+                                                            for p in probs]))
+            self.dtype = F64
+            esize = 8
+            self.x = np.empty(int(e.sum()))
+
+            def base(a):
+                return a.ctypes.data
+        self.arrays = {k: cat(k) for k in ("f2", "f1", "g2", "g1", "y", "xlo", "xhi")}
+        self.c = np.ascontiguousarray(np.concatenate([np.asarray(p.c, dtype=np.float64).reshape(-1) for p in probs]))
+        self.recs_c, r = _records(admm_problem, self.count)
+        r["m"] = self.m
+        r["n"] = self.n
+        r["q"] = 1
+        r["mem"] = DEVICE if dev else HOST
+        r["dtype"] = self.dtype
+        r["bounds"] = BOUNDS_PER_SOURCE
+        for k in ("f2", "f1", "g2", "g1"):
+            r[k] = base(self.arrays[k]) + self.x_off * esize
+        r["y"] = base(self.arrays["y"]) + y_off * esize
+        r["x_lo"] = base(self.arrays["xlo"]) + s_off * esize
+        r["x_hi"] = base(self.arrays["xhi"]) + s_off * esize
+        r["c"] = self.c.ctypes.data + s_off * 8
+        self.out_c = (C.c_void_p * self.count)()
+        np.frombuffer(memoryview(self.out_c).cast("B"), dtype=np.uint64)[:] = base(self.x) + self.x_off * esize
+        self.info_c, self.info = _records(admm_info, self.count)
+        self.torch_device = probs[0].f2.device if dev else None
+
+    def x_of(self, b):
+        """Instance b's output, shape (1, m, n), a view of ``x``."""
+        o, m, n = int(self.x_off[b]), int(self.m[b]), int(self.n[b])
+        return self.x[o:o + m * n].reshape(1, m, n)
+
+
+def _solve_pack(ctx, pack, settings=None):
+    s = settings.to_c() if settings else None
+    if pack.device:
+        import torch
+        ctx.set_stream(torch.cuda.current_stream(pack.torch_device).cuda_stream)
+    st = lib().admm_solve_batch(ctx.h, pack.count, pack.recs_c, C.byref(s) if s is not None else None, None,
+                                pack.out_c, pack.info_c)
+    _check(st)
+    return pack.x, pack.info
+
+
 def _solve_batch(ctx, probs, settings=None, x_outs=None):
+    if isinstance(probs, BatchPack):
+        if x_outs is not None:
+            raise ValueError("a pack writes its own output array")
+        return _solve_pack(ctx, probs, settings)
     n = len(probs)
     ms = [_Marshal(p) for p in probs]
     arr = (admm_problem * max(1, n))(*[m.st for m in ms])
@@ -345,8 +461,9 @@ def _solve_batch(ctx, probs, settings=None, x_outs=None):
 
 
 def admm_solve_batch(ctx: "Context", probs, settings: Optional[Settings] = None, x_outs=None):
-    """Solve many independent instances in one batched launch.  Returns
-    (list of x, list of info dicts)."""
+    """Solve many independent instances in one batched launch.  With a list
+    of problems returns (list of x, list of info dicts); with a BatchPack
+    returns (the pack's flat x, a numpy record array of admm_info)."""
     return _solve_batch(ctx, probs, settings, x_outs)
 
 

@@ -9,6 +9,8 @@ import subprocess
 import pytest
 
 from paper_1903_10041_amd import admm
+from paper_1903_10041_amd import workloads as W
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "admm.h")
@@ -69,3 +71,27 @@ def test_null_arguments_are_errors_not_crashes():
     L = admm.lib()
     assert L.admm_solve(None, None, None, None, None, None, None) == admm.E_INVALID_ARG
     assert L.admm_poll(None, 1, None, None) in (admm.E_INVALID_ARG, admm.E_UNSUPPORTED)
+
+
+def test_batch_pack_records_point_into_the_flat_arrays():
+    """The pack's admm_problem records (built with vectorised numpy fills)
+    carry each instance's shape and the addresses of its slices."""
+    import ctypes as C
+    probs = [W.uniform_problem(m, n, 900 + m * 10 + n) for m, n in ((2, 5), (3, 64), (1, 1), (8, 33))]
+    pack = admm.BatchPack(probs)
+    e_off = y_off = s_off = 0
+    for b, p in enumerate(probs):
+        r = pack.recs_c[b]
+        assert (r.m, r.n, r.q, r.mem, r.bounds) == (p.m, p.n, 1, admm.HOST, admm.BOUNDS_PER_SOURCE)
+        assert r.f2 == pack.arrays["f2"].ctypes.data + 8 * e_off
+        assert r.g1 == pack.arrays["g1"].ctypes.data + 8 * e_off
+        assert r.y == pack.arrays["y"].ctypes.data + 8 * y_off
+        assert r.x_hi == pack.arrays["xhi"].ctypes.data + 8 * s_off
+        assert r.c == pack.c.ctypes.data + 8 * s_off
+        got = np.ctypeslib.as_array(C.cast(r.f1, C.POINTER(C.c_double)), shape=(p.m * p.n,))
+        assert np.array_equal(got, p.f1.reshape(-1))
+        assert pack.out_c[b] == pack.x.ctypes.data + 8 * e_off
+        e_off += p.m * p.n
+        y_off += p.n
+        s_off += p.m
+    assert admm._np_dtype(admm.admm_info).itemsize == C.sizeof(admm.admm_info)

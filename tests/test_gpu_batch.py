@@ -125,3 +125,31 @@ def test_batch_invalid_instance(ctx):
     with pytest.raises(admm.AdmmError) as e:
         ctx.solve_batch(probs, fixed(10))
     assert e.value.status == admm.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_batch_pack_equals_list_call(ctx, where):
+    """A BatchPack (flat arrays, records built once) gives exactly what the
+    per-problem list call gives."""
+    import torch
+    probs = mixed_batch(40, 307)
+    s = admm.Settings(max_iter=3000, eps_primal=1e-5, eps_dual=1e-5, precision=admm.F32_MIXED,
+                      rho2_per_step=True)
+    if where == "device":
+        dev = torch.device("cuda:0")
+        probs_in = [W.Problem(**{k: (torch.from_numpy(v).to(device=dev, dtype=torch.float32).contiguous()
+                                     if isinstance(v, np.ndarray) and k != "c" else v)
+                                 for k, v in vars(p).items()}) for p in probs]
+    else:
+        probs_in = probs
+    xs, infos = ctx.solve_batch(probs_in, s)
+    pack = admm.BatchPack(probs_in)
+    x_flat, rec = ctx.solve_batch(pack, s)
+    for b, p in enumerate(probs):
+        xa = xs[b].cpu().numpy() if where == "device" else xs[b]
+        xp = pack.x_of(b)
+        xp = xp.cpu().numpy() if where == "device" else xp
+        assert np.array_equal(xa.reshape(-1), xp.reshape(-1)), b
+        assert int(rec["iters"][b]) == infos[b]["iters"]
+        assert int(rec["status"][b]) == infos[b]["status"]
+        assert float(rec["objective"][b]) == infos[b]["objective"]
