@@ -139,8 +139,34 @@ __device__ __forceinline__ void block_max_rows(int rows, const double *v, double
     __syncthreads();
 }
 
+// The descriptor of the block's current instance with every field made
+// wave-uniform: loaded through an index that came from LDS, the fields would
+// otherwise sit in vector registers in every lane.
+__device__ __forceinline__ int32_t uni_i(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni_l(int64_t v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)(uint64_t)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ BInst uniform_inst(const BInst &I) {
+    BInst u;
+    u.m = uni_i(I.m); u.n = uni_i(I.n); u.n_pad = uni_i(I.n_pad); u.status = uni_i(I.status);
+    u.t = uni_i(I.t); u.max_iter = uni_i(I.max_iter); u.check_every = uni_i(I.check_every);
+    u.flags = uni_i(I.flags); u.window = uni_i(I.window); u.pad_ = 0;
+    u.coef_off = uni_l(I.coef_off); u.x_off = uni_l(I.x_off); u.col_off = uni_l(I.col_off);
+    u.pool_off = uni_l(I.pool_off); u.w_off = uni_l(I.w_off);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u.rho[k] = uniform(I.rho[k]);
+    u.eps_p = uniform(I.eps_p); u.eps_d = uniform(I.eps_d);
+    u.r = uniform(I.r); u.sigma = uniform(I.sigma); u.objective = 0.0;
+    return u;
+}
+
+// Occupancy: with the descriptor uniform, the classes fit 3, 2 and 1 waves
+// per SIMD (m <= 2, <= 4, <= 8) without spills.
 template <typename T, int MAXM, int MODE>
-__global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 2 ? 3 : (MAXM <= 4 ? 2 : 1))))
+void k_batch(BatchParams B) {
     __shared__ double lds[MAXM + 2][kBlock];
     __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM], s_lo[MAXM], s_hi[MAXM];
     __shared__ double s_sum[MAXM], s_max[MAXM + 2], s_min[MAXM];
@@ -150,15 +176,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
     for (;;) {
         if (tid == 0) s_idx = atomicAdd(B.next, 1);
         __syncthreads();
-        const int qi = s_idx;
+        const int qi = __builtin_amdgcn_readfirstlane(s_idx);
         if (qi >= B.count) break;
-        BInst &I = B.inst[B.order[qi]];
-        if (I.status != -1) {
+        BInst &I = B.inst[__builtin_amdgcn_readfirstlane(B.order[qi])];
+        const BInst Iu = uniform_inst(I);
+        if (Iu.status != -1) {
             __syncthreads();
             continue;
         }
-        SolveParams P = inst_params<MAXM>(B, I);
-        inst_pointers<T>(B, I, P);
+        SolveParams P = inst_params<MAXM>(B, Iu);
+        inst_pointers<T>(B, Iu, P);
         const int m = P.m, n = P.n;
         if (tid < m) {
             s_lam[tid] = P.lam[tid];
@@ -179,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchParams B) {
         const double nd = (double)n;
         const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
         int status = -1;
-        const int win = I.window > 0 ? min(I.window, B.window) : B.window;
+        const int win = Iu.window > 0 ? min(Iu.window, B.window) : B.window;
         for (int wi = 0; wi < win; ++wi) {
             const int t1 = s_t + 1;
             if (t1 > P.max_iter) break;
