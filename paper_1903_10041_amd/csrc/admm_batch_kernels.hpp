@@ -162,16 +162,18 @@ __device__ __forceinline__ BInst uniform_inst(const BInst &I) {
     return u;
 }
 
-// Occupancy: with the descriptor uniform, the classes fit 3, 2 and 1 waves
-// per SIMD (m <= 2, <= 4, <= 8) without spills.
+// Occupancy: with the descriptor uniform and the per-source scalars read
+// from LDS, the classes m <= 2 and m <= 4 fit 3 and 2 waves per SIMD
+// without spills; m <= 8 is held to 2 waves (256 registers).
 template <typename T, int MAXM, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 2 ? 3 : (MAXM <= 4 ? 2 : 1))))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 2 ? 3 : 2)))
 void k_batch(BatchParams B) {
     __shared__ double lds[MAXM + 2][kBlock];
     __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM], s_lo[MAXM], s_hi[MAXM];
     __shared__ double s_sum[MAXM], s_max[MAXM + 2], s_min[MAXM];
     __shared__ double s_r, s_sg;
     __shared__ int s_idx, s_stop, s_t;
+    __shared__ Scal<MAXM> s_sc;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) s_idx = atomicAdd(B.next, 1);
@@ -211,18 +213,20 @@ void k_batch(BatchParams B) {
             const int t1 = s_t + 1;
             if (t1 > P.max_iter) break;
             const bool check = (t1 % P.check_every) == 0;
-            Scal<MAXM> sc;
-#pragma unroll
-            for (int i = 0; i < MAXM; ++i) {
-                sc.toff[i] = i < m ? s_zoff[i] + s_lam[i] : 0.0;
-                sc.cons[i] = 0.0;
-                sc.lo[i] = s_lo[i < m ? i : 0];
-                sc.hi[i] = s_hi[i < m ? i : 0];
+            if (tid < MAXM) {
+                const int i = tid;
+                s_sc.toff[i] = i < m ? s_zoff[i] + s_lam[i] : 0.0;
+                s_sc.cons[i] = 0.0;
+                s_sc.lo[i] = s_lo[i < m ? i : 0];
+                s_sc.hi[i] = s_hi[i < m ? i : 0];
             }
+            __syncthreads();
+            const Scal<MAXM> &sc = s_sc;
             Acc<MAXM> acc;
             acc.reset();
             if (check) {
                 for (int k = tid; k < n; k += kBlock) {
+                    asm volatile("" ::: "memory");
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
                     col_update<T, MAXM, MODE, true, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
@@ -230,6 +234,7 @@ void k_batch(BatchParams B) {
                 }
             } else {
                 for (int k = tid; k < n; k += kBlock) {
+                    asm volatile("" ::: "memory");
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
                     col_update<T, MAXM, MODE, false, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
