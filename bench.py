@@ -614,6 +614,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--skip-extras", action="store_true", help="only the headline plain-path run")
+    ap.add_argument("--extras", default="batched,served,robust,large,quartic,q_sweep,closed_loop",
+                    help="comma-separated list of the extra legs to run")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -663,13 +665,12 @@ def main():
             variants[other] = run_gpu(a2, other)
     extras = {}
     if not args.skip_extras:
-        extras["batched"] = run_batch(args)
-        extras["served"] = run_serve(args)
-        extras["robust"] = run_robust(args)
-        extras["large"] = run_large(args)
-        extras["quartic"] = run_quartic(args)
-        extras["q_sweep"] = run_qsweep(args)
-        extras["closed_loop"] = run_closed_loop(args)
+        legs = {"batched": run_batch, "served": run_serve, "robust": run_robust, "large": run_large,
+                "quartic": run_quartic, "q_sweep": run_qsweep, "closed_loop": run_closed_loop}
+        for name in args.extras.split(","):
+            if name not in legs:
+                sys.exit(f"bench.py: unknown extra leg {name!r} (one of {', '.join(legs)})")
+            extras[name] = legs[name](args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
 
     storage = {"f32": "f32 storage and x-step arithmetic, f64 reductions",
