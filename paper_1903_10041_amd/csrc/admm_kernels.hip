@@ -72,8 +72,24 @@ __global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, 
                                                     const double *D, const double *lo, const double *hi,
                                                     int project, double *x, int32_t *codes, int32_t *bad) {
     int flag = 0;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N; e += (int64_t)gridDim.x * blockDim.x) {
-        const double a = A[e], b = B[e], c = C[e], d = D[e], l = lo[e], h = hi[e];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    // the next element's six operands are loaded before this one's minimiser
+    // runs, so each wave keeps a full set of loads in flight
+    double na = 0.0, nb = 0.0, nc = 0.0, nd = 0.0, nl = 0.0, nh = 0.0;
+    if (e < N) {
+        na = __builtin_nontemporal_load(A + e); nb = __builtin_nontemporal_load(B + e);
+        nc = __builtin_nontemporal_load(C + e); nd = __builtin_nontemporal_load(D + e);
+        nl = __builtin_nontemporal_load(lo + e); nh = __builtin_nontemporal_load(hi + e);
+    }
+    for (; e < N; e += stride) {
+        const double a = na, b = nb, c = nc, d = nd, l = nl, h = nh;
+        const int64_t en = e + stride;
+        if (en < N) {
+            na = __builtin_nontemporal_load(A + en); nb = __builtin_nontemporal_load(B + en);
+            nc = __builtin_nontemporal_load(C + en); nd = __builtin_nontemporal_load(D + en);
+            nl = __builtin_nontemporal_load(lo + en); nh = __builtin_nontemporal_load(hi + en);
+        }
         int code = -1;
         double v = NAN;
         const bool ok = a >= 0.0 && isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) &&
@@ -88,8 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, 
         } else {
             v = qmin_f64(a, b, c, d, l, h, project, code);
         }
-        x[e] = v;
-        if (codes) codes[e] = code;
+        __builtin_nontemporal_store(v, x + e);
+        if (codes) __builtin_nontemporal_store(code, codes + e);
     }
     if (flag) atomicOr(bad, 1);
 }
