@@ -420,6 +420,7 @@ __device__ __forceinline__ double adapt_factor(const SolveParams &P, double r, d
 
 // ------------------------------------------------------------- finalize
 
+template <int NW = kWaves>
 __device__ __forceinline__ double block_max(double v, double *lds) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     v = wave_max(v);
@@ -428,36 +429,78 @@ __device__ __forceinline__ double block_max(double v, double *lds) {
     __syncthreads();
     double r = lds[0];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) r = fmax(r, lds[w]);
+    for (int w = 1; w < NW; ++w) r = fmax(r, lds[w]);
     return r;
 }
 
-// The scalar steps of one iteration, run by one block of kBlock threads
-// after every tile's partials are written: (7b)+(7g) through kappa, (7d),
-// (7i), the consensus (7c)+(7h), the residuals on check iterations and the
-// stop flag.  Sums over tiles run in a fixed order.
+// The scalar steps of one iteration, run by one block of NT threads after
+// every tile's partials are written: (7b)+(7g) through kappa, (7d), (7i),
+// the consensus (7c)+(7h), the residuals on check iterations and the stop
+// flag.  Sums over tiles run in a fixed order.  With LDS (M <= kFinalLdsPairs)
+// the per-pair values the later phases need (x_1, nu and the residual terms)
+// stay in shared memory, and every global read is issued in the first phase,
+// so the block waits for memory once instead of once per phase.
+constexpr int kFinalLdsPairs = 1024;
+
+template <int NT = kBlock, bool LDS = false>
 __device__ inline void finalize_body(const SolveParams &P) {
     Ctrl *ctrl = P.ctrl;
     const int t1 = ctrl->t + 1;
     const bool check = (t1 % P.check_every) == 0;
     const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group;
-    const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = kBlock / G;
+    const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = NT / G;
     const size_t slab = (size_t)q * nblk * m;
     const double *pg = P.part, *pmax = P.part + slab, *pmin = P.part + 2 * slab;
     const double *pr = P.part + 3 * slab;
     const double nd = (double)P.n;
     const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+    constexpr int SL = LDS ? kFinalLdsPairs : 1;
+    __shared__ double s_x1[SL], s_nu[SL], s_pr[SL], s_ps[SL], s_xb[8];   // m <= 8
+    double *pair_r = LDS ? s_pr : P.pair_r, *pair_s = LDS ? s_ps : P.pair_s;
+
+    // residual partials of the tiles (checks only), read up front
+    const int nres = q * nblk;
+    double ra[4], rc[4];
+    const bool res_here = check && tid < nres;
+    if (res_here) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int bb = tid + u * NT < nres ? tid + u * NT : tid;
+            ra[u] = pr[2 * bb];
+            rc[u] = pr[2 * bb + 1];
+        }
+    }
 
     for (int base = 0; base < M; base += ngroups) {
         const int pi = base + gid;
         const bool active = pi < M;
         const int j = active ? pi / m : 0, i = active ? pi % m : 0;
+        double x1v = 0.0, nuv = 0.0;
+        if (LDS && P.consensus && active && gl == 0) {
+            x1v = P.x1[pi];
+            nuv = P.nu[pi];
+        }
         double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
         if (active) {
-            for (int bb = gl; bb < nblk; bb += G) {
-                const size_t idx = ((size_t)j * nblk + bb) * m + i;
-                s += pg[idx];
-                if (check) { mx = fmax(mx, pmax[idx]); mn = fmin(mn, pmin[idx]); }
+            // eight partials loaded before they are summed, in the same
+            // ascending order, so the loads overlap and the sum is unchanged
+            constexpr int U = 8;
+            for (int b0 = gl; b0 < nblk; b0 += U * G) {
+                double v[U], vx[U], vn[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int bb = b0 + u * G;
+                    const size_t idx = ((size_t)j * nblk + (bb < nblk ? bb : 0)) * m + i;
+                    v[u] = pg[idx];
+                    if (check) { vx[u] = pmax[idx]; vn[u] = pmin[idx]; }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (b0 + u * G < nblk) {
+                        s += v[u];
+                        if (check) { mx = fmax(mx, vx[u]); mn = fmin(mn, vn[u]); }
+                    }
+                }
             }
         }
         s = group_sum(s, G);
@@ -477,48 +520,79 @@ __device__ inline void finalize_body(const SolveParams &P) {
             P.p[pi] = pn;
             if (check) {
                 const double cz = zoff_new - zoff_old;
-                P.pair_r[pi] = fmax(fabs(zoff_new), fabs(hn - sumz));
-                P.pair_s[pi] = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)),
-                                    P.rho2 * fabs(hn - h_old));
+                pair_r[pi] = fmax(fabs(zoff_new), fabs(hn - sumz));
+                pair_s[pi] = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)),
+                                  P.rho2 * fabs(hn - h_old));
+            }
+            if (LDS) {
+                s_x1[pi] = x1v;
+                s_nu[pi] = nuv;
             }
         }
     }
     __syncthreads();
 
     if (P.consensus) {
+        const double *X1 = LDS ? s_x1 : P.x1;
+        double *NU = LDS ? s_nu : P.nu;
+        double *XB = LDS ? s_xb : P.xbar1;
         int G2 = 64;
-        while (G2 > 1 && m * G2 > kBlock) G2 >>= 1;
+        while (G2 > 1 && m * G2 > NT) G2 >>= 1;
         const int g2l = tid & (G2 - 1), g2id = tid / G2;
-        for (int base = 0; base < m; base += kBlock / G2) {
+        for (int base = 0; base < m; base += NT / G2) {
             const int i = base + g2id;
             double s = 0.0;
             if (i < m)
-                for (int jj = g2l; jj < q; jj += G2) s += P.x1[jj * m + i] - P.nu[jj * m + i];
+                for (int jj = g2l; jj < q; jj += G2) s += X1[jj * m + i] - NU[jj * m + i];
             s = group_sum(s, G2);
-            if (i < m && g2l == 0) P.xbar1[i] = s * P.inv_q;
+            if (i < m && g2l == 0) {
+                XB[i] = s * P.inv_q;
+                if (LDS) P.xbar1[i] = s * P.inv_q;
+            }
         }
         __syncthreads();
-        for (int pi = tid; pi < M; pi += kBlock) {
-            const double res = P.xbar1[pi % m] - P.x1[pi];
-            P.nu[pi] += res;
-            if (check) P.pair_r[pi] = fmax(P.pair_r[pi], fabs(res));
+        for (int pi = tid; pi < M; pi += NT) {
+            const double res = XB[pi % m] - X1[pi];
+            const double nn = NU[pi] + res;
+            NU[pi] = nn;
+            if (LDS) P.nu[pi] = nn;
+            if (check) pair_r[pi] = fmax(pair_r[pi], fabs(res));
         }
         __syncthreads();
     }
 
-    __shared__ double lds[kWaves];
+    __shared__ double lds[NT / 64];
     if (check) {
         double r = 0.0, sg = 0.0;
-        for (int pi = tid; pi < M; pi += kBlock) {
-            r = fmax(r, P.pair_r[pi]);
-            sg = fmax(sg, P.pair_s[pi]);
+        for (int pi = tid; pi < M; pi += NT) {
+            r = fmax(r, pair_r[pi]);
+            sg = fmax(sg, pair_s[pi]);
         }
-        for (int bb = tid; bb < q * nblk; bb += kBlock) {
-            r = fmax(r, pr[2 * bb]);
-            sg = fmax(sg, P.rho3 * pr[2 * bb + 1]);
+        if (res_here) {
+            // the first four strides, read above (entries past the end
+            // repeat this thread's first one, which leaves the maximum alone)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                r = fmax(r, ra[u]);
+                sg = fmax(sg, P.rho3 * rc[u]);
+            }
         }
-        r = block_max(r, lds);
-        sg = block_max(sg, lds);
+        for (int b0 = tid + 4 * NT; b0 < nres; b0 += 4 * NT) {
+            double a[4], c[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int bb = b0 + u * NT < nres ? b0 + u * NT : b0;
+                a[u] = pr[2 * bb];
+                c[u] = pr[2 * bb + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                r = fmax(r, a[u]);
+                sg = fmax(sg, P.rho3 * c[u]);
+            }
+        }
+        r = block_max<NT / 64>(r, lds);
+        sg = block_max<NT / 64>(sg, lds);
         const bool bad = !(r == r) || !(sg == sg);
         const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
         if (tid == 0) {
@@ -531,7 +605,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
             // r and sg are the same in every thread: so is f
             const double f = stop ? 1.0 : adapt_factor(P, r, sg);
             if (f != 1.0) {
-                for (int pi = tid; pi < M; pi += kBlock) {
+                for (int pi = tid; pi < M; pi += NT) {
                     P.lam[pi] /= f;
                     P.p[pi] /= f;
                     P.nu[pi] /= f;

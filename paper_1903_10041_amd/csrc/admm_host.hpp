@@ -71,7 +71,7 @@ namespace admm {
 
 admm_status validate_settings(const admm_settings *s);
 admm_status validate_problem_shape(const admm_problem *p);
-int finalize_group(int m, int q, int nblk);
+int finalize_group(int m, int q, int nblk, int threads);
 int sweep_cpt(int n, int q);
 int persist_columns(admm_context *ctx, int dtype, int m, int n, int q);
 admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settings *s, SolveParams &P,

@@ -7,6 +7,7 @@
 namespace admm {
 
 constexpr int kBlock = 256;          // threads per block (4 wave64s)
+constexpr int kFinalBlock = 1024;    // threads of the split path's scalar-step block
 constexpr int kWaves = kBlock / 64;
 constexpr int kPad = 64;             // n is padded to a multiple of this
 constexpr int kChainBlock = 1024;    // threads per block of the chained iteration

@@ -110,11 +110,12 @@ __global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, 
     if (flag) atomicOr(bad, 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(SolveParams P0) {
+__global__ __launch_bounds__(kFinalBlock) void k_finalize(SolveParams P0) {
     if (P0.ctrl->done) return;
     SolveParams P = P0;
     adapt_load<false>(P, P0.rho_cur, P0.ctrl);
-    finalize_body(P);
+    if (P.m * P.q <= kFinalLdsPairs) finalize_body<kFinalBlock, true>(P);
+    else finalize_body<kFinalBlock, false>(P);
 }
 
 // ------------------------------------------------------ chained iteration
@@ -979,7 +980,7 @@ hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
-    k_finalize<<<1, kBlock, 0, s>>>(P);
+    k_finalize<<<1, kFinalBlock, 0, s>>>(P);
     return hipGetLastError();
 }
 

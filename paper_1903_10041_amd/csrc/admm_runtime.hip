@@ -314,8 +314,8 @@ static void chain_grid(admm_context *ctx, int n, int &nblk, int &chunks) {
     nblk = (n + kChainBlock * chunks - 1) / (kChainBlock * chunks);
 }
 
-int finalize_group(int m, int q, int nblk) {
-    int G = pow2_floor(std::max(1, kBlock / (m * q)));
+int finalize_group(int m, int q, int nblk, int threads) {
+    int G = pow2_floor(std::max(1, threads / (m * q)));
     if (G > 64) G = 64;
     while (G > 1 && G / 2 >= nblk) G /= 2;
     return G;
@@ -367,7 +367,9 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.chunks = chunks;
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
-    P.group = finalize_group(m, q, nblk);
+    // lanes per (i,j) pair in the scalar steps: the split path runs them in
+    // one block of kFinalBlock threads, the resident path in one of kBlock
+    P.group = finalize_group(m, q, nblk, P.persistent ? kBlock : kFinalBlock);
     P.check_every = s->check_every;
     P.max_iter = s->max_iter;
     P.xstep_project = s->xstep == ADMM_XSTEP_PAPER_PROJECT;
