@@ -95,6 +95,7 @@ hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
 // Chained path: launch at graph position c reads slot c & 1 (rs).
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s);
 hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s);
+bool chain_q_fits(int m, int q, int n);   // the chained launch with consensus applies
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
 hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,

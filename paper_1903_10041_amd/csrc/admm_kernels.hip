@@ -375,10 +375,9 @@ __device__ __forceinline__ void chain_store(const SolveParams &P, int ws, const 
 // dg-min, then residual maxima [nblk][2].
 template <int MAXM, int NT>
 __device__ __forceinline__ void chain_partials(const SolveParams &P, double *part, int tile, const Acc<MAXM> &acc,
-                                               bool check, double (*red)[3 * MAXM + 2]) {
+                                               bool check, double (*red)[3 * MAXM + 2], size_t slab) {
     constexpr int NW = NT / 64;
     const int m = P.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const size_t slab = (size_t)P.nblk * m;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
         if (i < m) {
@@ -477,7 +476,8 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
             }
         }
     }
-    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red);
+    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red,
+                                      (size_t)P.nblk * P.m);
     if (blockIdx.x == 0) {
         const int t1 = sh.t + 1;
         const int bad = sh.bad | (((t1 % P.check_every) == 0) != CHECK ? 2 : 0);
@@ -494,6 +494,245 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P) {
     chain_prologue<MAXM, kChainBlock>(P, 0, sh);
     // a divisor decided here (or left by a launch that stopped) is pending
     chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad, sh.f != 1.0 ? sh.f : wd);
+}
+
+// ---------------------------------------- chained, several scenarios
+//
+// The chained launch for q > 1 (or the consensus block at q = 1): block
+// (j, b) sweeps columns [b * kChainBlock, (b + 1) * kChainBlock) of
+// scenario j.  Its prologue completes the pending iteration for every
+// (i, j) pair, one thread per pair (M = m q <= kChainBlock), from the tile
+// partials of the previous launch: (7b)+(7g), (7d)+(7i), then the
+// consensus (7c) as a fixed-order sum over the scenarios and (7h), and on
+// check iterations the residuals and the stop decision.  Every block does
+// the same arithmetic in the same order, so all derive the same bits; block
+// 0 stores the state.  A slot holds lam, zoff, h, p, nu, x_1 [M] and
+// x_bar_1 [m]; x_1 is written by the sweep of the launch that writes the
+// slot, since the blocks of one launch still read the other slot's.
+constexpr int kChainQTiles = 8;    // blocks per scenario (n <= 8192)
+
+struct QSlot {
+    double *lam, *zoff, *h, *p, *nu, *x1, *xbar1;
+    Ctrl *ctrl;
+};
+
+__device__ __forceinline__ QSlot qslot(const SolveParams &P, int s) {
+    QSlot c;
+    const int M = P.m * P.q;
+    if (s == 0) {
+        c.lam = P.lam; c.zoff = P.zoff; c.h = P.h; c.p = P.p; c.nu = P.nu; c.x1 = P.x1; c.xbar1 = P.xbar1;
+        c.ctrl = P.ctrl;
+    } else {
+        double *b = P.scal1;
+        c.lam = b; c.zoff = b + M; c.h = b + 2 * M; c.p = b + 3 * M; c.nu = b + 4 * M; c.x1 = b + 5 * M;
+        c.xbar1 = b + 6 * M;
+        c.ctrl = P.ctrl1;
+    }
+    return c;
+}
+
+template <int MAXM>
+struct ChainQShared {
+    double toff[MAXM], cons[MAXM];   // this block's scenario, after the pending steps
+    double xb[MAXM];                 // x_bar_1 after the pending steps
+    double red[kChainBlock / 64][2];
+    double d[kChainBlock];           // x_1 - nu per pair
+};
+
+// Completes the pending iteration of slot rs for pair `tid` (all threads
+// take part; `own` selects the block's scenario for toff/cons).  Returns
+// the control values after the steps in st[] = {t, status, done, bad} and
+// r, sigma; the pair's new state in the references.
+template <int MAXM>
+__device__ __forceinline__ void chainq_steps(const SolveParams &P, int rs, int own, ChainQShared<MAXM> &sh,
+                                             double &lam, double &zoff, double &h, double &p, double &nu,
+                                             double &x1, int *st, double &r, double &sg) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = P.m, q = P.q, M = m * q, nbs = P.nblk;
+    const QSlot in = qslot(P, rs);
+    const Ctrl *c = in.ctrl;
+    const int t = c->t, pending = c->pending, done = c->done;
+    const bool fin = pending && !done;
+    const bool chk = fin && (t % P.check_every) == 0;
+    const double *part = rs ? P.part : P.part1;
+    const size_t slab = (size_t)q * nbs * m;
+    const bool act = tid < M;
+    const int pj = act ? tid / m : 0, pii = act ? tid - pj * m : 0;
+    lam = zoff = h = p = nu = x1 = 0.0;
+    if (act) {
+        lam = in.lam[tid]; zoff = in.zoff[tid]; h = in.h[tid]; p = in.p[tid]; nu = in.nu[tid]; x1 = in.x1[tid];
+    }
+    double W = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
+    if (fin && act) {
+        double v[kChainQTiles], vx[kChainQTiles], vn[kChainQTiles];
+#pragma unroll
+        for (int u = 0; u < kChainQTiles; ++u) {
+            const size_t idx = ((size_t)pj * nbs + (u < nbs ? u : 0)) * m + pii;
+            v[u] = part[idx];
+            if (chk) { vx[u] = part[slab + idx]; vn[u] = part[2 * slab + idx]; }
+        }
+#pragma unroll
+        for (int u = 0; u < kChainQTiles; ++u) {
+            if (u < nbs) {
+                W += v[u];
+                if (chk) { mx = fmax(mx, vx[u]); mn = fmin(mn, vn[u]); }
+            }
+        }
+    }
+    // residual rows of every tile (checks)
+    double ra = 0.0, rb = 0.0;
+    if (chk)
+        for (int tt = tid; tt < q * nbs; tt += kChainBlock) {
+            ra = fmax(ra, part[3 * slab + 2 * (size_t)tt]);
+            rb = fmax(rb, part[3 * slab + 2 * (size_t)tt + 1]);
+        }
+    double pr = 0.0, ps = 0.0;
+    if (fin && act) {
+        const double nd = (double)P.n;
+        const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+        const double Wd = W - nd * lam;                  // 1'(g(x) - lambda)
+        const double kap = kfac * (h + p - Wd);
+        const double sumz = Wd + nd * kap;               // 1'z
+        const double zn = kap - lam;                     // z - g(x)
+        const double hn = fmin(P.cap[pii], sumz - p);
+        const double pn = p + hn - sumz;
+        if (chk) {
+            const double cz = zn - zoff;
+            pr = fmax(fabs(zn), fabs(hn - sumz));
+            ps = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)), P.rho2 * fabs(hn - h));
+        }
+        lam = kap;
+        zoff = zn;
+        h = hn;
+        p = pn;
+    }
+    // (7c): x_bar_1 = mean over j of (x_1 - nu), wave i for source i, lanes
+    // strided over j and then the wave's fixed-order sum
+    sh.d[tid] = act ? x1 - nu : 0.0;
+    __syncthreads();
+    if (wv < m) {
+        double s = 0.0;
+        for (int jj = lane; jj < q; jj += 64) s += sh.d[jj * m + wv];
+        s = wave_sum(s);
+        if (lane == 0) sh.xb[wv] = fin ? s * P.inv_q : in.xbar1[wv];
+    }
+    __syncthreads();
+    if (fin && act) {
+        const double res = sh.xb[pii] - x1;              // (7h)
+        nu += res;
+        if (chk) pr = fmax(pr, fabs(res));
+    }
+    int status = c->status, dn = done;
+    r = c->r;
+    sg = c->sigma;
+    if (fin) {
+        if (chk) {
+            double a = wave_max(fmax(pr, ra)), b = wave_max(fmax(ps, P.rho3 * rb));
+            if (lane == 0) { sh.red[wv][0] = a; sh.red[wv][1] = b; }
+            __syncthreads();
+            r = sh.red[0][0];
+            sg = sh.red[0][1];
+#pragma unroll
+            for (int w = 1; w < kChainBlock / 64; ++w) { r = fmax(r, sh.red[w][0]); sg = fmax(sg, sh.red[w][1]); }
+            const bool bad = !(r == r) || !(sg == sg);
+            const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
+            if (bad) { status = -4; dn = 1; }
+            else if (stop) { status = 0; dn = 1; }
+        }
+        if (!dn && t >= P.max_iter) { status = 2; dn = 1; }
+    }
+    if (act && pj == own) {
+        sh.toff[pii] = zoff + lam;
+        sh.cons[pii] = sh.xb[pii] + nu;
+    }
+    st[0] = t;
+    st[1] = status;
+    st[2] = dn;
+    st[3] = c->bad_input;
+    __syncthreads();
+}
+
+// Block 0: the state after the steps into slot ws (x_1 too when no sweep
+// follows, so that the slot is complete).
+template <int MAXM>
+__device__ __forceinline__ void chainq_store(const SolveParams &P, int ws, const ChainQShared<MAXM> &sh,
+                                             double lam, double zoff, double h, double p, double nu, double x1,
+                                             bool with_x1, int t, int pending, const int *st, double r,
+                                             double sg) {
+    const QSlot o = qslot(P, ws);
+    const int tid = threadIdx.x;
+    if (tid < P.m * P.q) {
+        o.lam[tid] = lam; o.zoff[tid] = zoff; o.h[tid] = h; o.p[tid] = p; o.nu[tid] = nu;
+        if (with_x1) o.x1[tid] = x1;
+    }
+    if (tid < P.m) o.xbar1[tid] = sh.xb[tid];
+    if (tid == 0) {
+        Ctrl *c = o.ctrl;
+        c->t = t;
+        c->status = st[1];
+        c->done = st[2];
+        c->bad_input = st[3];
+        c->r = r;
+        c->sigma = sg;
+        c->pending = pending;
+        c->wdiv = 1.0;
+    }
+}
+
+template <typename T, int MAXM, int MODE, bool CHECK>
+__global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) {
+    const int ws = rs ^ 1;
+    const int nbs = P.nblk, j = blockIdx.x / nbs, b = blockIdx.x - j * nbs;
+    __shared__ ChainQShared<MAXM> sh;
+    __shared__ double red[kChainBlock / 64][3 * MAXM + 2];
+    const Ctrl *cin = rs ? P.ctrl1 : P.ctrl;
+    const bool stopped = cin->done;
+    const int k = b * kChainBlock + threadIdx.x;
+    Col<T, MAXM> d;
+    if (!stopped && k < P.n) col_load<T, MAXM>(P, j, k, d);
+    double lam, zoff, h, p, nu, x1, r, sg;
+    int st[4];
+    chainq_steps<MAXM>(P, rs, j, sh, lam, zoff, h, p, nu, x1, st, r, sg);
+    if (stopped || st[2]) {
+        // stopped earlier or now: carry the state into the other slot
+        if (blockIdx.x == 0) chainq_store<MAXM>(P, ws, sh, lam, zoff, h, p, nu, x1, true, st[0], 0, st, r, sg);
+        return;
+    }
+    if (blockIdx.x == 0) {
+        // nothing this launch reads is in slot ws, so the state goes there
+        // before the sweep (its x_1 comes from the sweep itself)
+        const int t1 = st[0] + 1;
+        int s2[4] = {st[0], st[1], st[2], st[3] | ((((t1 % P.check_every) == 0) != CHECK) ? 2 : 0)};
+        chainq_store<MAXM>(P, ws, sh, lam, zoff, h, p, nu, x1, false, t1, 1, s2, r, sg);
+    }
+    SolveParams Q = P;
+    Q.x1 = qslot(P, ws).x1;          // this sweep's x_1, read by the next launch
+    Scal<MAXM> sc;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        const int ii = i < P.m ? i : 0;
+        sc.toff[i] = i < P.m ? sh.toff[ii] : 0.0;
+        sc.cons[i] = (i < P.m && P.consensus) ? sh.cons[ii] : 0.0;
+    }
+    scal_bounds<MAXM>(P.slo, P.shi, P.m, sc);
+    Acc<MAXM> acc;
+    acc.reset();
+    if (k < P.n) {
+        col_update<T, MAXM, MODE, CHECK, F_ALL>(Q, j, k, d, sc, acc);
+        col_store<T, MAXM>(Q, j, k, d);
+    }
+    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red,
+                                      (size_t)P.q * nbs * P.m);
+}
+
+// Completes a pending iteration in place in slot 0 (one block).
+template <int MAXM>
+__global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P) {
+    __shared__ ChainQShared<MAXM> sh;
+    double lam, zoff, h, p, nu, x1, r, sg;
+    int st[4];
+    chainq_steps<MAXM>(P, 0, 0, sh, lam, zoff, h, p, nu, x1, st, r, sg);
+    chainq_store<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, false, st[0], 0, st, r, sg);
 }
 
 // ---------------------------------------------------- persistent resident
@@ -957,7 +1196,33 @@ static void launch_chain_k(const SolveParams &P, int rs, hipStream_t s) {
     else launch_chain_f<T, MODE, CHECK, F_ALL>(P, rs, s);
 }
 
+template <typename T, int MODE, bool CHECK>
+static void launch_chain_q(const SolveParams &P, int rs, hipStream_t s) {
+    const unsigned g = (unsigned)(P.q * P.nblk);
+    if (P.m <= 2) k_chain_q<T, 2, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
+    else k_chain_q<T, 4, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
+}
+
+bool chain_q_fits(int m, int q, int n) {
+    return m <= 4 && (int64_t)m * q <= kChainBlock && (n + kChainBlock - 1) / kChainBlock <= kChainQTiles;
+}
+
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {
+    if (P.consensus) {
+        if (!chain_q_fits(P.m, P.q, P.n) || P.nblk != (P.n + kChainBlock - 1) / kChainBlock || P.adaptive)
+            return hipErrorInvalidValue;
+        if (dtype == 0) {
+            if (check) launch_chain_q<double, MODE_F64, true>(P, rs, s);
+            else launch_chain_q<double, MODE_F64, false>(P, rs, s);
+        } else if (dtype == 1) {
+            if (check) launch_chain_q<float, MODE_MIXED, true>(P, rs, s);
+            else launch_chain_q<float, MODE_MIXED, false>(P, rs, s);
+        } else {
+            if (check) launch_chain_q<float, MODE_F32, true>(P, rs, s);
+            else launch_chain_q<float, MODE_F32, false>(P, rs, s);
+        }
+        return hipGetLastError();
+    }
     if (P.m > 4 || P.q != 1 || P.nblk > kChainMaxBlocks) return hipErrorInvalidValue;
     if (dtype == 0) {
         if (check) launch_chain_k<double, MODE_F64, true>(P, rs, s);
@@ -974,6 +1239,12 @@ hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hip
 
 hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s) {
     if (P.m > 4) return hipErrorInvalidValue;
+    if (P.consensus) {
+        if ((int64_t)P.m * P.q > kChainBlock) return hipErrorInvalidValue;
+        if (P.m <= 2) k_chain_q_flush<2><<<1, kChainBlock, 0, s>>>(P);
+        else k_chain_q_flush<4><<<1, kChainBlock, 0, s>>>(P);
+        return hipGetLastError();
+    }
     if (P.m <= 2) k_chain_flush<2><<<1, kChainBlock, 0, s>>>(P);
     else k_chain_flush<4><<<1, kChainBlock, 0, s>>>(P);
     return hipGetLastError();

@@ -299,6 +299,13 @@ static bool chain_applies(const admm_problem *pr, const admm_settings *s) {
     return pr->q == 1 && !s->consensus_q1 && pr->m <= 4;
 }
 
+// The chained launch with the consensus block (q > 1, or q = 1 with it
+// kept): one thread per (i, j) pair in the scalar steps and at most
+// kChainQTiles blocks per scenario; fixed rho.
+static bool chain_q_applies(const admm_problem *pr, const admm_settings *s) {
+    return (pr->q > 1 || s->consensus_q1) && !s->adaptive_rho && chain_q_fits(pr->m, pr->q, pr->n);
+}
+
 // Chained grid: one block per kChainBlock columns while that fits in
 // kChainMaxBlocks blocks; beyond, one block per compute unit, each sweeping
 // its columns in chunks of kChainBlock.
@@ -340,8 +347,9 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         if (R == 0) return fail(ADMM_E_UNSUPPORTED, "the resident launch does not fit this problem on the device");
         break;
     case ADMM_LAUNCH_CHAINED:
-        if (!chain_applies(pr, s))
-            return fail(ADMM_E_UNSUPPORTED, "the chained launch needs q = 1, no consensus and m <= 4");
+        if (!chain_applies(pr, s) && !chain_q_applies(pr, s))
+            return fail(ADMM_E_UNSUPPORTED, "the chained launch needs m <= 4 and either q = 1 without "
+                                            "consensus, or m q <= 1024, n <= 8192 and fixed rho");
         chain = true;
         break;
     case ADMM_LAUNCH_SPLIT:
@@ -393,8 +401,9 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     ENS(W.y, K * T);
     ENS(W.w, K * T);
     // lam zoff h p nu x1 pair_r pair_s [M each], xbar1 slo shi cap [m each],
-    // the chained path's second scalar slot [4m], rho_cur [2][4]
-    ENS(W.scal, (8 * M + 8 * (size_t)m + 8) * sizeof(double));
+    // the chained path's second scalar slot (lam zoff h p nu x1 [M each],
+    // xbar1 [m]), rho_cur [2][4]
+    ENS(W.scal, (14 * M + 5 * (size_t)m + 8) * sizeof(double));
     ENS(W.part, (chain ? 2 : 1) * part_doubles(m, q, nblk) * sizeof(double));
     ENS(W.ctrl, 2 * sizeof(Ctrl) + 64);
     ENS(W.obj, 1024 * sizeof(double));
@@ -417,7 +426,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.ctrl = (Ctrl *)W.ctrl.p;
     P.bar = (uint32_t *)((char *)W.ctrl.p + sizeof(Ctrl));
     P.scal1 = sc + 8 * M + 4 * m;
-    P.rho_cur = sc + 8 * M + 8 * m;
+    P.rho_cur = sc + 14 * M + 5 * m;
     P.ctrl1 = (Ctrl *)((char *)W.ctrl.p + sizeof(Ctrl) + 64);
     P.part1 = chain ? P.part + part_doubles(m, q, nblk) : nullptr;
     return ADMM_OK;

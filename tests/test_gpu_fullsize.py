@@ -43,6 +43,13 @@ def c3():
     return probs, pack
 
 
+@pytest.fixture(scope="module")
+def c4_oracle():
+    p = W.phev_c4()
+    st, oi, _ = oracle.run(p, max_iter=20, nthreads=8)
+    return p, st, oi
+
+
 def sample_ids(probs, k=16):
     """Instances spread over the source counts and the horizon range: the
     largest n for each m, then evenly spaced indices."""
@@ -101,17 +108,18 @@ def test_full_size_batch_converged(ctx, c3):
         assert abs(int(rec["iters"][b]) - oi["iters"]) <= 20, b
 
 
+@pytest.mark.parametrize("launch", [admm.LAUNCH_AUTO, admm.LAUNCH_SPLIT, admm.LAUNCH_CHAINED])
 @pytest.mark.parametrize("prec", [admm.F64, admm.F32_MIXED])
-def test_full_size_robust(ctx, prec):
+def test_full_size_robust(ctx, c4_oracle, prec, launch):
     """m = 2, q = 200, n = 3600 (1.44 M quartics, first-step consensus),
-    20 iterations, every element against the oracle: FP64 from host arrays
-    to 1e-9; FP32 storage from device tensors (the benchmark's robust
+    20 iterations on each launch path, every element against the oracle:
+    FP64 from host arrays to 1e-9; FP32 storage from device tensors (the benchmark's robust
     configuration) to 1e-5, the storage-rounding bound above for |x| <= 1.2."""
     import torch
-    p = W.phev_c4()
-    st, oi, _ = oracle.run(p, max_iter=20, nthreads=8)
-    say(f"[full-size robust] m=2 q=200 n=3600 precision={prec}, 20 iterations")
-    s = admm.Settings(rho=tuple(p.rho), max_iter=20, eps_primal=0.0, eps_dual=0.0, precision=prec)
+    p, st, oi = c4_oracle
+    say(f"[full-size robust] m=2 q=200 n=3600 precision={prec} launch={launch}, 20 iterations")
+    s = admm.Settings(rho=tuple(p.rho), max_iter=20, eps_primal=0.0, eps_dual=0.0, precision=prec,
+                      launch=launch)
     if prec == admm.F64:
         x, info, _ = ctx.solve(p, s)
         tol_x, tol_obj = 1e-9, 1e-10

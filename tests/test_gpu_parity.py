@@ -327,11 +327,79 @@ def test_chained_resume_is_bit_exact(ctx):
 
 
 def test_launch_path_unsupported(ctx):
-    for p, launch in ((W.phev_c4(seed=7, q=5, n=60), admm.LAUNCH_CHAINED),
-                      (W.uniform_problem(5, 100, 3), admm.LAUNCH_CHAINED)):
+    for p, launch in ((W.phev_c4(seed=7, q=5, n=9000), admm.LAUNCH_CHAINED),
+                      (W.uniform_problem(5, 100, 3), admm.LAUNCH_CHAINED),
+                      (W.phev_c4(seed=7, q=600, n=50), admm.LAUNCH_CHAINED)):
         with pytest.raises(admm.AdmmError) as e:
             ctx.solve(p, fixed(p, 10, launch=launch))
         assert e.value.status == admm.E_UNSUPPORTED
+    p = W.phev_c4(seed=7, q=5, n=60)
+    with pytest.raises(admm.AdmmError) as e:
+        ctx.solve(p, admm.Settings(rho=tuple(p.rho), max_iter=10, adaptive_rho=True, launch=admm.LAUNCH_CHAINED))
+    assert e.value.status == admm.E_UNSUPPORTED
+
+
+# The chained launch with the consensus block: q > 1 (or q = 1 with it
+# kept), one thread per (i, j) pair in the scalar steps.
+CONS_CASES = {
+    "robust_q5_n60": (lambda: W.phev_c4(seed=7, q=5, n=60), False),
+    "robust_q3_n700": (lambda: W.phev_c4(seed=8, q=3, n=700), False),
+    "robust_q40_n1500": (lambda: W.phev_c4(seed=10, q=40, n=1500), False),
+    "uniform_m4_q2_n8192": (lambda: W.uniform_problem(4, 8192, 14, q=2, cap_fraction=0.4), False),
+    "c1_consensus_q1": (lambda: W.small_c1(), True),
+    "m3_q256_n37": (lambda: W.uniform_problem(3, 37, 15, q=256), False),
+}
+
+
+@pytest.mark.parametrize("name", list(CONS_CASES))
+def test_chained_consensus_trajectory(ctx, name):
+    """Every element against the oracle after 300 iterations (FP64), with
+    the residuals of the last check."""
+    mk, cq1 = CONS_CASES[name]
+    p = mk()
+    say(f"[chained-consensus] {name} m={p.m} q={p.q} n={p.n} consensus_q1={cq1}")
+    x, info, _ = ctx.solve(p, fixed(p, 300, launch=admm.LAUNCH_CHAINED, consensus_q1=cq1))
+    st, oinfo, _ = oracle.run(p, max_iter=300, nthreads=8, consensus_q1=cq1)
+    dx = float(np.abs(x - st["x"]).max())
+    rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
+    say(f"   max|dx|={dx:.2e} rel obj={rel:.2e} r {info['r']:.6e}/{oinfo['r']:.6e}")
+    assert info["status"] == admm.MAX_ITER and info["iters"] == 300
+    # the horizon sums run over n terms in another order on the two sides;
+    # at n = 8192 the iterates then differ by ~1e-10 and the objective, a
+    # sum of m n q = 65536 terms each moved by |f'| dx <= 5 dx, by ~1e-9
+    # relative: the bound is 1e-8 past 20000 elements
+    rel_tol = 1e-9 if p.m * p.n * p.q <= 20000 else 1e-8
+    assert dx <= 1e-9 and rel <= rel_tol
+    for key in ("r", "sigma"):
+        assert abs(info[key] - oinfo[key]) <= 1e-6 * abs(oinfo[key]) + 1e-10, key
+
+
+def test_chained_consensus_convergence(ctx):
+    """The stopping check agrees with the oracle's, also for check_every = 7
+    and a cap that ends inside a chunk."""
+    for name, ce, cap in (("robust_q5_n60", 10, 100000), ("robust_q3_n700", 7, 100000), ("robust_q5_n60", 10, 53)):
+        p = CONS_CASES[name][0]()
+        s = admm.Settings(rho=tuple(p.rho), max_iter=cap, eps_primal=1e-6, eps_dual=1e-6, check_every=ce,
+                          launch=admm.LAUNCH_CHAINED)
+        say(f"[chained-consensus-converge] {name} check_every={ce} max_iter={cap}")
+        x, info, _ = ctx.solve(p, s)
+        st, oinfo, _ = oracle.run(p, max_iter=cap, eps_primal=1e-6, eps_dual=1e-6, check_every=ce)
+        say(f"   iters gpu={info['iters']} oracle={oinfo['iters']} status {info['status']}/{oinfo['status']}")
+        assert info["iters"] == oinfo["iters"] or (oinfo["status"] == 0 and abs(info["iters"] - oinfo["iters"]) <= ce)
+        assert (info["status"] == admm.OK) == (oinfo["status"] == 0)
+        assert float(np.abs(x - st["x"]).max()) <= 1e-8
+
+
+def test_chained_consensus_resume_is_bit_exact(ctx):
+    p = W.phev_c4(seed=9, q=7, n=900)
+    say("[chained-consensus-resume] m=2 q=7 n=900: 300 = 170 + 130")
+    s = lambda it: fixed(p, it, launch=admm.LAUNCH_CHAINED)
+    xa, ia, sa = ctx.solve(p, s(300), want_state=True)
+    xb, ib, sb = ctx.solve(p, s(170), want_state=True)
+    xc, ic, sc = ctx.solve(p, s(130), warm=sb, want_state=True)
+    assert np.array_equal(xa, xc)
+    for k in ("h", "p", "nu", "xbar1", "lambda_s", "zoff_s", "s", "mu"):
+        assert np.array_equal(sa[k], sc[k]), k
 
 
 @pytest.mark.parametrize("prec", [admm.F32_MIXED, admm.F32])
