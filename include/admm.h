@@ -83,14 +83,16 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
 /* How admm_solve issues the iterations on the GPU (results agree to
  * rounding; each path is deterministic on its own).
  * AUTO      RESIDENT when the problem fits in a few co-resident blocks,
- *           else CHAINED when it applies, else SPLIT.
+ *           else CHAINED when it applies (with the consensus block: while
+ *           q ceil(n / 1024) <= twice the compute units), else SPLIT.
  * SPLIT     a captured graph of two launches per iteration: the sweep
  *           (7a), (7e), (7f) with block partials, then one block for the
  *           scalar steps (7b)-(7d), (7g)-(7i), residuals and stop flag.
  * CHAINED   one launch per iteration: each launch first completes the
  *           previous iteration's scalar steps (every block computes them
- *           from the partials), then sweeps.  q = 1 without consensus
- *           and m <= 4 only (ADMM_E_UNSUPPORTED otherwise).
+ *           from the partials), then sweeps.  m <= 4, and either q = 1
+ *           without consensus, or (q > 1 or consensus_q1) with m q <= 1024,
+ *           n <= 8192 and fixed rho (ADMM_E_UNSUPPORTED otherwise).
  * RESIDENT  one cooperative launch whose blocks keep their columns in
  *           registers and meet at a grid barrier every iteration; only
  *           when every block fits on the device at once (else

@@ -42,6 +42,7 @@ struct SolveParams {
     int32_t persistent;     // 1: resident cooperative kernel, 0: graph of launches
     int32_t chain;          // 1: one chained launch per iteration (q = 1), 0: sweep + finalize
     int32_t chunks;         // chained: kChainBlock-column chunks each block sweeps in turn
+    int32_t cgrid;          // chained with consensus: blocks of the launch (tiles are dealt round robin)
     int32_t group;          // finalize: lanes cooperating on one (i,j) pair
     int32_t check_every, max_iter;
     int32_t xstep_project, jacobi, consensus, want_codes;

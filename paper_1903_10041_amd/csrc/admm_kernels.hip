@@ -533,18 +533,18 @@ __device__ __forceinline__ QSlot qslot(const SolveParams &P, int s) {
 
 template <int MAXM>
 struct ChainQShared {
-    double toff[MAXM], cons[MAXM];   // this block's scenario, after the pending steps
-    double xb[MAXM];                 // x_bar_1 after the pending steps
+    double toff[kChainBlock], cons[kChainBlock];   // per pair, after the pending steps
+    double xb[MAXM];                               // x_bar_1 after the pending steps
     double red[kChainBlock / 64][2];
-    double d[kChainBlock];           // x_1 - nu per pair
+    double d[kChainBlock];                         // x_1 - nu per pair
 };
 
 // Completes the pending iteration of slot rs for pair `tid` (all threads
-// take part; `own` selects the block's scenario for toff/cons).  Returns
-// the control values after the steps in st[] = {t, status, done, bad} and
-// r, sigma; the pair's new state in the references.
+// take part).  Returns the control values after the steps in
+// st[] = {t, status, done, bad} and r, sigma; the pair's new state in the
+// references, and every pair's sweep offsets in sh.toff / sh.cons.
 template <int MAXM>
-__device__ __forceinline__ void chainq_steps(const SolveParams &P, int rs, int own, ChainQShared<MAXM> &sh,
+__device__ __forceinline__ void chainq_steps(const SolveParams &P, int rs, ChainQShared<MAXM> &sh,
                                              double &lam, double &zoff, double &h, double &p, double &nu,
                                              double &x1, int *st, double &r, double &sg) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -641,9 +641,9 @@ __device__ __forceinline__ void chainq_steps(const SolveParams &P, int rs, int o
         }
         if (!dn && t >= P.max_iter) { status = 2; dn = 1; }
     }
-    if (act && pj == own) {
-        sh.toff[pii] = zoff + lam;
-        sh.cons[pii] = sh.xb[pii] + nu;
+    if (act) {
+        sh.toff[tid] = zoff + lam;
+        sh.cons[tid] = sh.xb[pii] + nu;
     }
     st[0] = t;
     st[1] = status;
@@ -681,18 +681,22 @@ __device__ __forceinline__ void chainq_store(const SolveParams &P, int ws, const
 
 template <typename T, int MAXM, int MODE, bool CHECK>
 __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) {
-    const int ws = rs ^ 1;
-    const int nbs = P.nblk, j = blockIdx.x / nbs, b = blockIdx.x - j * nbs;
+    const int ws = rs ^ 1, m = P.m;
+    const int nbs = P.nblk, ntile = P.q * nbs;
     __shared__ ChainQShared<MAXM> sh;
     __shared__ double red[kChainBlock / 64][3 * MAXM + 2];
     const Ctrl *cin = rs ? P.ctrl1 : P.ctrl;
     const bool stopped = cin->done;
-    const int k = b * kChainBlock + threadIdx.x;
+    // tiles (scenario j, column block b) are dealt round robin; the first
+    // tile's columns are loaded before the scalar steps
+    int tl = blockIdx.x;
+    int j = tl / nbs, b = tl - j * nbs;
+    int k = b * kChainBlock + threadIdx.x;
     Col<T, MAXM> d;
     if (!stopped && k < P.n) col_load<T, MAXM>(P, j, k, d);
     double lam, zoff, h, p, nu, x1, r, sg;
     int st[4];
-    chainq_steps<MAXM>(P, rs, j, sh, lam, zoff, h, p, nu, x1, st, r, sg);
+    chainq_steps<MAXM>(P, rs, sh, lam, zoff, h, p, nu, x1, st, r, sg);
     if (stopped || st[2]) {
         // stopped earlier or now: carry the state into the other slot
         if (blockIdx.x == 0) chainq_store<MAXM>(P, ws, sh, lam, zoff, h, p, nu, x1, true, st[0], 0, st, r, sg);
@@ -707,22 +711,30 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) 
     }
     SolveParams Q = P;
     Q.x1 = qslot(P, ws).x1;          // this sweep's x_1, read by the next launch
-    Scal<MAXM> sc;
+    for (;;) {
+        Scal<MAXM> sc;
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-        const int ii = i < P.m ? i : 0;
-        sc.toff[i] = i < P.m ? sh.toff[ii] : 0.0;
-        sc.cons[i] = (i < P.m && P.consensus) ? sh.cons[ii] : 0.0;
+        for (int i = 0; i < MAXM; ++i) {
+            const int pi = j * m + (i < m ? i : 0);
+            sc.toff[i] = i < m ? sh.toff[pi] : 0.0;
+            sc.cons[i] = (i < m && P.consensus) ? sh.cons[pi] : 0.0;
+        }
+        scal_bounds<MAXM>(P.slo, P.shi, m, sc);
+        Acc<MAXM> acc;
+        acc.reset();
+        if (k < P.n) {
+            col_update<T, MAXM, MODE, CHECK, F_ALL>(Q, j, k, d, sc, acc);
+            col_store<T, MAXM>(Q, j, k, d);
+        }
+        chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, tl, acc, CHECK, red, (size_t)ntile * m);
+        tl += gridDim.x;
+        if (tl >= ntile) break;
+        __syncthreads();             // red is reused by the next tile
+        j = tl / nbs;
+        b = tl - j * nbs;
+        k = b * kChainBlock + threadIdx.x;
+        if (k < P.n) col_load<T, MAXM>(P, j, k, d);
     }
-    scal_bounds<MAXM>(P.slo, P.shi, P.m, sc);
-    Acc<MAXM> acc;
-    acc.reset();
-    if (k < P.n) {
-        col_update<T, MAXM, MODE, CHECK, F_ALL>(Q, j, k, d, sc, acc);
-        col_store<T, MAXM>(Q, j, k, d);
-    }
-    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red,
-                                      (size_t)P.q * nbs * P.m);
 }
 
 // Completes a pending iteration in place in slot 0 (one block).
@@ -731,7 +743,7 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P) {
     __shared__ ChainQShared<MAXM> sh;
     double lam, zoff, h, p, nu, x1, r, sg;
     int st[4];
-    chainq_steps<MAXM>(P, 0, 0, sh, lam, zoff, h, p, nu, x1, st, r, sg);
+    chainq_steps<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, st, r, sg);
     chainq_store<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, false, st[0], 0, st, r, sg);
 }
 
@@ -1198,7 +1210,7 @@ static void launch_chain_k(const SolveParams &P, int rs, hipStream_t s) {
 
 template <typename T, int MODE, bool CHECK>
 static void launch_chain_q(const SolveParams &P, int rs, hipStream_t s) {
-    const unsigned g = (unsigned)(P.q * P.nblk);
+    const unsigned g = (unsigned)(P.cgrid > 0 ? P.cgrid : P.q * P.nblk);
     if (P.m <= 2) k_chain_q<T, 2, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
     else k_chain_q<T, 4, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
 }

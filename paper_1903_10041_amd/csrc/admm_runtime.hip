@@ -356,7 +356,13 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         break;
     default:
         R = persist_columns(ctx, dtype, m, n, q, false);
-        chain = R == 0 && chain_applies(pr, s);
+        // with consensus the chained launch wins while its tiles fit about
+        // two per compute unit (measured: q = 100, n = 3600 faster than
+        // split, q = 200 slower): past that every block's pass over all
+        // m q pairs and its tiles in series cost more than the second launch
+        chain = R == 0 && (chain_applies(pr, s) ||
+                           (chain_q_applies(pr, s) &&
+                            (int64_t)q * ((n + kChainBlock - 1) / kChainBlock) <= 2 * std::max(1, ctx->num_cu)));
         break;
     }
     if (R > 0) cpt = R;
@@ -373,6 +379,10 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.persistent = R > 0;
     P.chain = chain ? 1 : 0;
     P.chunks = chunks;
+    // chained with consensus: at most one block per compute unit, each
+    // sweeping its share of the q * nblk column tiles in turn
+    if (chain && (q > 1 || s->consensus_q1))
+        P.cgrid = std::min(q * ((n + kChainBlock - 1) / kChainBlock), std::max(1, ctx->num_cu));
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     // lanes per (i,j) pair in the scalar steps: the split path runs them in
