@@ -433,7 +433,9 @@ def run_serve(args):
     --serve-seconds: requests with m in {2, 4}, n log-uniform [100, 50000],
     256 warm-start keys, residual 1e-4, f32 storage.  Instances come from a
     pool of --serve-pool seeded problems reused round-robin (generating
-    every request's arrays would cost more host time than the solves)."""
+    every request's arrays would cost more host time than the solves).
+    Then the first --serve-plain-sample requests of the same stream one
+    after another through admm_solve, cold."""
     import math
     import threading
     import numpy as np
@@ -478,6 +480,7 @@ def run_serve(args):
                         del submitted[t]
             time.sleep(0.0002)
 
+    depth = 0
     th = threading.Thread(target=poller)
     th.start()
     t0 = time.perf_counter()
@@ -492,10 +495,19 @@ def run_serve(args):
         t = ctx.submit(p, s, warm_key=int(keys[r]))
         with lock:
             submitted[t] = (p, ts)
+            depth = max(depth, len(submitted))
     t_sub = time.perf_counter() - t0
     done_flag[0] = True
     th.join()
     t_all = time.perf_counter() - t0
+    # the same request stream, one request after another through the plain
+    # per-instance admm_solve (cold starts), on a sample
+    plain_ms = []
+    for r in range(min(args.serve_plain_sample, nreq)):
+        p = pool[r % len(pool)]
+        tp = time.perf_counter()
+        ctx.solve(p, s)
+        plain_ms.append((time.perf_counter() - tp) * 1000.0)
     ctx.close()
     lat_ms = np.array(lat) * 1000.0
     hz = np.array(horizon)
@@ -517,7 +529,10 @@ def run_serve(args):
             "solves_per_s": len(lat) / t_all, "offered_per_s": nreq / t_sub,
             "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
             "max_ms": float(lat_ms.max()), "mean_iters": float(np.mean(iters)), "drain_s": t_all - t_sub,
-            "long_n_ge_8192": pct(lanes), "short": pct(~lanes)}
+            "long_n_ge_8192": pct(lanes), "short": pct(~lanes), "max_outstanding": depth,
+            "plain_path": {"requests": len(plain_ms), "solves_per_s": len(plain_ms) / (sum(plain_ms) / 1000.0),
+                           "p50_ms": float(np.percentile(plain_ms, 50)),
+                           "p99_ms": float(np.percentile(plain_ms, 99))} if plain_ms else None}
 
 
 def run_robust(args):
@@ -543,6 +558,14 @@ def run_robust(args):
         out[tag] = {"status": info["status"], "iters": info["iters"], "solve_ms": dt * 1000,
                     "iters_per_s": info["iters"] / dt, "r": info["r"], "sigma": info["sigma"],
                     "objective": info["objective"]}
+    # per-iteration time of the launch path AUTO takes (captured graph, no
+    # stop test) and its algorithmic traffic: 6 words per element, 3 per column
+    prof = admm._profile(ctx, pd, admm.Settings(max_iter=1 << 30, eps_primal=0.0, eps_dual=0.0,
+                                                precision=_prec(args)), 400)
+    byts = sweep_bytes(p.m, p.n, p.q, 8 if args.precision == "f64" else 4)
+    out["iteration"] = {"launch": prof["launch"], "us": prof["graph_iter_us"], "bytes": byts,
+                        "gbs": byts / prof["graph_iter_us"] / 1e3,
+                        "hbm_frac": byts / prof["graph_iter_us"] / 1e3 / HBM_PEAK_GBS}
     ctx.close()
     return out
 
@@ -621,6 +644,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-pool", type=int, default=384)
+    ap.add_argument("--serve-plain-sample", type=int, default=200,
+                    help="requests of the served stream also run one by one through admm_solve")
     ap.add_argument("--robust-max-iter", type=int, default=100000)
     ap.add_argument("--repeats", type=int, default=10, help="repeated timed solves for the spread")
     ap.add_argument("--repeat-steps", type=int, default=1000)

@@ -1246,6 +1246,9 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
             delete ln;
             break;
         }
+        // a lane orders its solves after nothing but its own stream (not the
+        // null stream, which other work on the device may be using)
+        ln->sub->user = ln->sub->own;
         ss->lanes.push_back(ln);
     }
     if (ss->lanes.empty()) ss->big_n = 0;
