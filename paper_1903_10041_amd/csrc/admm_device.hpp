@@ -456,6 +456,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
     const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
     constexpr int SL = LDS ? kFinalLdsPairs : 1;
     __shared__ double s_x1[SL], s_nu[SL], s_pr[SL], s_ps[SL], s_xb[8];   // m <= 8
+    __shared__ double s_gw[NT / 64][3];
     double *pair_r = LDS ? s_pr : P.pair_r, *pair_s = LDS ? s_ps : P.pair_s;
 
     // residual partials of the tiles (checks only), read up front
@@ -503,8 +504,25 @@ __device__ inline void finalize_body(const SolveParams &P) {
                 }
             }
         }
-        s = group_sum(s, G);
-        if (check) { mx = group_max(mx, G); mn = group_min(mn, G); }
+        if (G <= 64) {
+            s = group_sum(s, G);
+            if (check) { mx = group_max(mx, G); mn = group_min(mn, G); }
+        } else {
+            // a pair spans G / 64 waves: each wave's fixed-order sum, then
+            // the waves' in order through LDS
+            s = group_sum(s, 64);
+            if (check) { mx = group_max(mx, 64); mn = group_min(mn, 64); }
+            const int wv = tid >> 6;
+            __syncthreads();
+            if ((tid & 63) == 0) { s_gw[wv][0] = s; s_gw[wv][1] = mx; s_gw[wv][2] = mn; }
+            __syncthreads();
+            if (gl == 0) {
+                for (int w = 1; w < G / 64; ++w) {
+                    s += s_gw[wv + w][0];
+                    if (check) { mx = fmax(mx, s_gw[wv + w][1]); mn = fmin(mn, s_gw[wv + w][2]); }
+                }
+            }
+        }
         if (active && gl == 0) {
             const double lam_old = P.lam[pi], zoff_old = P.zoff[pi];
             const double h_old = P.h[pi], p_old = P.p[pi];

@@ -969,7 +969,7 @@ __global__ __launch_bounds__(kBlock) void k_init_cols(SolveParams P) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_final(SolveParams P) {
-    const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group;
+    const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group < 64 ? P.group : 64;
     const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = kBlock / G;
     for (int base = 0; base < M; base += ngroups) {
         const int pi = base + gid;
