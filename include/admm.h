@@ -83,8 +83,10 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
 /* How admm_solve issues the iterations on the GPU (results agree to
  * rounding; each path is deterministic on its own).
  * AUTO      RESIDENT when the problem fits in a few co-resident blocks,
- *           else CHAINED when it applies (with the consensus block: while
- *           q ceil(n / 1024) <= twice the compute units), else SPLIT.
+ *           else CHAINED when it applies (q = 1: while one iteration's
+ *           algorithmic traffic fits the 256 MB last-level cache; with the
+ *           consensus block: while q ceil(n / 1024) <= twice the compute
+ *           units), else SPLIT.
  * SPLIT     a captured graph of two launches per iteration: the sweep
  *           (7a), (7e), (7f) with block partials, then one block for the
  *           scalar steps (7b)-(7d), (7g)-(7i), residuals and stop flag.
