@@ -463,7 +463,9 @@ def _solve_batch(ctx, probs, settings=None, x_outs=None):
 def admm_solve_batch(ctx: "Context", probs, settings: Optional[Settings] = None, x_outs=None):
     """Solve many independent instances in one batched launch.  With a list
     of problems returns (list of x, list of info dicts); with a BatchPack
-    returns (the pack's flat x, a numpy record array of admm_info)."""
+    returns (the pack's flat x, a numpy record array of admm_info).  A
+    pack's x and records are its own buffers: the next call on the same
+    pack overwrites them."""
     return _solve_batch(ctx, probs, settings, x_outs)
 
 
