@@ -570,6 +570,39 @@ def run_robust(args):
     return out
 
 
+def run_readings(args):
+    """The paper's open readings on three workloads, solved to r, sigma <
+    1e-4: Gauss-Seidel vs Jacobi over the sources in (7a) (R3), and the
+    box-constrained minimiser vs the projected unconstrained one (R5).
+    Iterations, status and objective per combination."""
+    import torch
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    ctx = admm.Context(0, hbm_budget_bytes=8 << 30)
+    cases = (("m=4 n=262144, rho_2 / n, mixed", W.large_c2(), True, admm.F32_MIXED),
+             ("m=2 q=200 n=3600 robust, rho_2 / n, mixed", W.phev_c4(), True, admm.F32_MIXED),
+             ("m=2 n=100, rho_1 = 10, weak cost (three-root x-steps), f64", W.stress(), False, admm.F64))
+    combos = (("gauss_seidel+exact_box", admm.SWEEP_GAUSS_SEIDEL, admm.XSTEP_EXACT_BOX),
+              ("jacobi+exact_box", admm.SWEEP_JACOBI, admm.XSTEP_EXACT_BOX),
+              ("gauss_seidel+paper_project", admm.SWEEP_GAUSS_SEIDEL, admm.XSTEP_PAPER_PROJECT))
+    out = {"workload": "solves to r, sigma < 1e-4 (cap 100000 iterations) under each reading", "rows": []}
+    for name, p, r2, prec in cases:
+        prob = to_device(p, torch.float32) if prec != admm.F64 else p
+        row = {"case": name}
+        for tag, sweep, xs in combos:
+            st = admm.Settings(rho=tuple(p.rho), max_iter=100000, eps_primal=1e-4, eps_dual=1e-4, precision=prec,
+                               rho2_per_step=r2, sweep=sweep, xstep=xs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info, _ = ctx.solve(prob, st)
+            torch.cuda.synchronize()
+            row[tag] = {"iters": info["iters"], "status": info["status"], "objective": info["objective"],
+                        "solve_ms": (time.perf_counter() - t0) * 1000.0}
+        out["rows"].append(row)
+    ctx.close()
+    return out
+
+
 def cpu_baseline(args):
     import oracle
     from paper_1903_10041_amd import workloads as W
@@ -637,7 +670,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--skip-extras", action="store_true", help="only the headline plain-path run")
-    ap.add_argument("--extras", default="batched,served,robust,large,quartic,q_sweep,closed_loop",
+    ap.add_argument("--extras", default="batched,served,robust,large,quartic,q_sweep,closed_loop,readings",
                     help="comma-separated list of the extra legs to run")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--plain-sample", type=int, default=64)
@@ -691,7 +724,8 @@ def main():
     extras = {}
     if not args.skip_extras:
         legs = {"batched": run_batch, "served": run_serve, "robust": run_robust, "large": run_large,
-                "quartic": run_quartic, "q_sweep": run_qsweep, "closed_loop": run_closed_loop}
+                "quartic": run_quartic, "q_sweep": run_qsweep, "closed_loop": run_closed_loop,
+                "readings": run_readings}
         for name in args.extras.split(","):
             if name not in legs:
                 sys.exit(f"bench.py: unknown extra leg {name!r} (one of {', '.join(legs)})")
