@@ -125,10 +125,13 @@ __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double 
         double x;
         if (qmin_f32_fast(A, B, C, D, (float)lo, (float)hi, x, code)) return x;
     }
-    const double A = 0.5 * P.rho1 * g2 * g2;
-    const double B = P.rho1 * g2 * g1;
-    double C = f2 * P.inv_q + P.rho1 * (0.5 * g1 * g1 - g2 * tg) + 0.5 * P.rho3;
-    double D = f1 * P.inv_q - P.rho1 * g1 * tg - P.rho3 * phi;
+    // the same coefficients, grouped so that rho1 g1 and rho1 g2 are
+    // shared and the products fuse (12 operations rather than 15)
+    const double rg1 = P.rho1 * g1, rg2 = P.rho1 * g2;
+    const double A = (0.5 * rg2) * g2;
+    const double B = rg1 * g2;
+    double C = fma(-rg2, tg, fma(f2, P.inv_q, fma(0.5 * rg1, g1, 0.5 * P.rho3)));
+    double D = fma(-rg1, tg, fma(f1, P.inv_q, -P.rho3 * phi));
     if (first_step) {
         C += 0.5 * P.rho4;
         D -= P.rho4 * cons;

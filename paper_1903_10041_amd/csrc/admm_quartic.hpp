@@ -172,8 +172,11 @@ __device__ __forceinline__ double qmin_mixed(double A, double B, double C, doubl
         const float T = -Q * rcp32(S);
         double u = (double)(S + T - b3);
         // one FP64 Newton step on f'(u) = 0
-        const double p1 = ((4.0 * A * u + 3.0 * B) * u + 2.0 * C) * u + D;
-        const double p2 = (12.0 * A * u + 6.0 * B) * u + 2.0 * C;
+        // f' = ((4A u + 3B) u + 2C) u + D and f'' = 3 (4A u + 2B) u + 2C,
+        // sharing 4A u and 2C
+        const double a4u = (4.0 * A) * u, c2 = 2.0 * C;
+        const double p1 = fma(fma(fma(3.0, B, a4u), u, c2), u, D);
+        const double p2 = fma(3.0 * fma(2.0, B, a4u), u, c2);
         const double step = (double)((float)p1 * rcp32((float)p2));
         if (p2 > 0.0 && fabs(step) <= 1e-3 * (1.0 + fabs(u))) {
             u -= step;
