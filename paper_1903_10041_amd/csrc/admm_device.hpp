@@ -279,18 +279,19 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
     const double y = (double)d.y;
     const double w = (double)d.w;
     const double s_old = fmax(w, 0.0), mu_old = fmax(-w, 0.0);
-    const double sm = s_old + mu_old;
+    const double sm = fabs(w);                       // s_old + mu_old, one of them 0
     const T *G0 = (FEAT & F_G0) ? (const T *)P.g0 : nullptr;
     const bool jacobi = (FEAT & F_JACOBI) && P.jacobi;
     const bool cons = (FEAT & F_CONS) && P.consensus;
     double xo[MAXM], xc[MAXM];
-    double sum_old = 0.0;
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) {
         xo[i] = (i < m) ? (double)d.x[i] : 0.0;
         xc[i] = xo[i];
-        sum_old += xo[i];
     }
+    double sum_old = xo[0];
+#pragma unroll
+    for (int i = 1; i < MAXM; ++i) sum_old += xo[i];
     // Gauss-Seidel: the sum over the other sources is the running total of
     // the current iterate minus source i (Jacobi: of the previous iterate)
     double sum_cur = sum_old;
