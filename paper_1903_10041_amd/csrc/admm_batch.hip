@@ -883,19 +883,14 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                 insts[a].status = -1000;   // invalid input: retired below without running
             }
     }
-    // one window for every resident instance, per class, longest first
+    // one window for every resident instance, per class, longest first.
+    // Every resident still runs (finished ones were retired with the last
+    // window's readback, fresh ones start running); the kernel skips any
+    // whose start left another status (max_iter = 0), so the order needs
+    // no readback of the descriptors.
     std::vector<int32_t> order[3];
-    {
-        std::vector<BInst> cur(na);
-        if (!dev_ok(hipMemcpyAsync(cur.data(), ss->inst.p, na * sizeof(BInst), hipMemcpyDeviceToHost, s), "readback") ||
-            !dev_ok(hipStreamSynchronize(s), "readback"))
-            return false;
-        for (int a = 0; a < na; ++a) {
-            if (insts[a].status == -1000) cur[a].status = -1000;
-            insts[a] = cur[a];
-            if (cur[a].status == -1) order[batch_class(cur[a].m)].push_back(a);
-        }
-    }
+    for (int a = 0; a < na; ++a)
+        if (insts[a].status != -1000) order[batch_class(insts[a].m)].push_back(a);
     for (auto &o : order)
         std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
             return (double)insts[a].m * insts[a].n > (double)insts[b].m * insts[b].n;
