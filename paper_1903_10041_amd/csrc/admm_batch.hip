@@ -615,6 +615,9 @@ struct ServeState {
     // same for every resident and a long horizon does not hold the others
     int win_ref = 16;
     DevBuf arena, inst, order, next, src, stage, wsrc;
+    // pinned host staging for the results of the instances a window retires
+    char *hres = nullptr;
+    size_t hres_bytes = 0;
     FreeList fl;
     hipStream_t s = nullptr;
 };
@@ -921,7 +924,40 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
         if (insts[a].status == -1000) r->inst.status = -1000;
         (r->inst.status == -1 ? still : finished).push_back(r);
     }
-    for (ServeReq *r : finished) {
+    // results of every finished instance into pinned staging, one wait
+    std::vector<size_t> hoff(finished.size(), 0);
+    {
+        size_t need = 0;
+        for (size_t f = 0; f < finished.size(); ++f) {
+            const ServeReq *r = finished[f];
+            if (r->inst.status == -1000) continue;
+            hoff[f] = need;
+            need += ((size_t)r->m * r->n_pad * T + kPoolPerSource * (size_t)r->m * sizeof(double) + 255) & ~size_t(255);
+        }
+        if (need > ss->hres_bytes) {
+            const size_t bytes = std::max(need, ss->hres_bytes * 2);
+            if (ss->hres) (void)hipHostFree(ss->hres);
+            ss->hres = nullptr;
+            ss->hres_bytes = 0;
+            if (!dev_ok(hipHostMalloc((void **)&ss->hres, bytes, hipHostMallocDefault), "pinned staging"))
+                return false;
+            ss->hres_bytes = bytes;
+        }
+        for (size_t f = 0; f < finished.size(); ++f) {
+            const ServeReq *r = finished[f];
+            if (r->inst.status == -1000) continue;
+            const size_t xbytes = (size_t)r->m * r->n_pad * T;
+            if (!dev_ok(hipMemcpyAsync(ss->hres + hoff[f], base + r->x_b, xbytes, hipMemcpyDeviceToHost, s),
+                        "readback") ||
+                !dev_ok(hipMemcpyAsync(ss->hres + hoff[f] + xbytes, base + r->pool_b,
+                                       kPoolPerSource * (size_t)r->m * sizeof(double), hipMemcpyDeviceToHost, s),
+                        "readback"))
+                return false;
+        }
+        if (!finished.empty() && !dev_ok(hipStreamSynchronize(s), "readback")) return false;
+    }
+    for (size_t f = 0; f < finished.size(); ++f) {
+        ServeReq *r = finished[f];
         admm_info &inf = r->info;
         std::memset(&inf, 0, sizeof inf);
         const BInst &I = r->inst;
@@ -934,19 +970,13 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
             inf.sigma = I.sigma;
             inf.objective = I.objective;
             for (int k = 0; k < 4; ++k) inf.rho[k] = I.rho[k];
-            std::vector<char> xb((size_t)r->m * r->n_pad * T);
-            if (!dev_ok(hipMemcpyAsync(xb.data(), base + r->x_b, xb.size(), hipMemcpyDeviceToHost, s), "readback"))
-                return false;
-            std::vector<double> pool((size_t)kPoolPerSource * r->m);
-            if (!dev_ok(hipMemcpyAsync(pool.data(), base + r->pool_b, pool.size() * sizeof(double),
-                                       hipMemcpyDeviceToHost, s), "readback") ||
-                !dev_ok(hipStreamSynchronize(s), "readback"))
-                return false;
+            const char *xb = ss->hres + hoff[f];
+            const double *pool = (const double *)(xb + (size_t)r->m * r->n_pad * T);
             r->x.resize((size_t)r->m * r->n);
             for (int i = 0; i < r->m; ++i)
                 for (int k = 0; k < r->n; ++k) {
                     const size_t e = (size_t)i * r->n_pad + k;
-                    r->x[(size_t)i * r->n + k] = T == 8 ? ((double *)xb.data())[e] : (double)((float *)xb.data())[e];
+                    r->x[(size_t)i * r->n + k] = T == 8 ? ((const double *)xb)[e] : (double)((const float *)xb)[e];
                 }
             // warm store: x and w of this final iterate, lambda and p
             if (r->key) {
@@ -968,8 +998,8 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                                          hipMemcpyDeviceToDevice, s);
                     (void)hipMemcpyAsync(base + we.off + (size_t)r->m * r->n_pad * T, base + r->w_b, r->n_pad * T,
                                          hipMemcpyDeviceToDevice, s);
-                    we.lam.assign(pool.begin(), pool.begin() + r->m);
-                    we.p.assign(pool.begin() + 3 * r->m, pool.begin() + 4 * r->m);
+                    we.lam.assign(pool, pool + r->m);
+                    we.p.assign(pool + 3 * r->m, pool + 4 * r->m);
                     we.stamp = ++ss->stamp;
                     ss->warm[r->key] = we;
                 }
@@ -1200,6 +1230,7 @@ void serve_shutdown(admm_context *ctx) {
     for (DevBuf *b : {&ss->arena, &ss->inst, &ss->order, &ss->next, &ss->src, &ss->stage, &ss->wsrc})
         ctx->arena.release(*b);
     if (ss->s) (void)hipStreamDestroy(ss->s);
+    if (ss->hres) (void)hipHostFree(ss->hres);
     delete ss;
     ctx->serve = nullptr;
 }
