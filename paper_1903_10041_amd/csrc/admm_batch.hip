@@ -618,6 +618,9 @@ struct ServeState {
     // pinned host staging for the results of the instances a window retires
     char *hres = nullptr;
     size_t hres_bytes = 0;
+    // pinned host staging for the arrays of the instances a cycle admits
+    char *hup = nullptr;
+    size_t hup_bytes = 0;
     FreeList fl;
     hipStream_t s = nullptr;
 };
@@ -778,7 +781,18 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
             serve_fail(ss, "serving staging does not fit the budget");
             return false;
         }
-        std::vector<double> img(SRC);
+        // the admitted instances' arrays go through pinned staging (the copy
+        // is complete by the window's wait, before the next cycle reuses it)
+        if (SRC * sizeof(double) > ss->hup_bytes) {
+            const size_t bytes = std::max(SRC * sizeof(double), ss->hup_bytes * 2);
+            if (ss->hup) (void)hipHostFree(ss->hup);
+            ss->hup = nullptr;
+            ss->hup_bytes = 0;
+            if (!dev_ok(hipHostMalloc((void **)&ss->hup, bytes, hipHostMallocDefault), "pinned staging"))
+                return false;
+            ss->hup_bytes = bytes;
+        }
+        double *img = (double *)ss->hup;
         std::vector<PackSrc> src(nf);
         std::vector<BInst> fi(nf);
         std::vector<int32_t> cold_idx[3];
@@ -788,7 +802,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
         for (int f = 0; f < nf; ++f) {
             ServeReq *r = fresh[f];
             auto put = [&](const std::vector<double> &v) -> const void * {
-                std::memcpy(img.data() + o, v.data(), v.size() * sizeof(double));
+                std::memcpy(img + o, v.data(), v.size() * sizeof(double));
                 const void *d = sb + o;
                 o += v.size();
                 return d;
@@ -833,7 +847,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
         char *sp = (char *)ss->src.p;
         PackSrc *d_src = (PackSrc *)sp;
         BInst *d_fi = (BInst *)(sp + nf * sizeof(PackSrc));
-        if (!dev_ok(hipMemcpyAsync(sb, img.data(), SRC * sizeof(double), hipMemcpyHostToDevice, s), "upload") ||
+        if (!dev_ok(hipMemcpyAsync(sb, img, SRC * sizeof(double), hipMemcpyHostToDevice, s), "upload") ||
             !dev_ok(hipMemcpyAsync(d_src, src.data(), nf * sizeof(PackSrc), hipMemcpyHostToDevice, s), "upload") ||
             !dev_ok(hipMemcpyAsync(d_fi, fi.data(), nf * sizeof(BInst), hipMemcpyHostToDevice, s), "upload"))
             return false;
@@ -1231,6 +1245,7 @@ void serve_shutdown(admm_context *ctx) {
         ctx->arena.release(*b);
     if (ss->s) (void)hipStreamDestroy(ss->s);
     if (ss->hres) (void)hipHostFree(ss->hres);
+    if (ss->hup) (void)hipHostFree(ss->hup);
     delete ss;
     ctx->serve = nullptr;
 }
