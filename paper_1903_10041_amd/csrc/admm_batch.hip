@@ -860,7 +860,9 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
         if (dtype == 0) k_batch_pack<double, double><<<pg, kBlock, 0, s>>>(Bf, d_src, d_bad);
         else k_batch_pack<float, double><<<pg, kBlock, 0, s>>>(Bf, d_src, d_bad);
         if (!dev_ok(hipGetLastError(), "pack")) return false;
-        // cold and warm starts per class (descriptors of all residents)
+        // cold and warm starts per class (descriptors of all residents);
+        // the index and source buffers are reused from class to class, which
+        // the stream order makes safe without waiting
         for (int c = 0; c < 3; ++c) {
             if (!cold_idx[c].empty()) {
                 if (!dev_ok(hipMemcpyAsync(ss->order.p, cold_idx[c].data(), cold_idx[c].size() * sizeof(int32_t),
@@ -879,7 +881,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                     else if (c == 1) k_batch_init<float, 4><<<g, kBlock, 0, s>>>(Bc);
                     else k_batch_init<float, 8><<<g, kBlock, 0, s>>>(Bc);
                 }
-                if (!dev_ok(hipStreamSynchronize(s), "init")) return false;
+                if (!dev_ok(hipGetLastError(), "init")) return false;
             }
             if (!warm_src[c].empty()) {
                 if (!dev_ok(hipMemcpyAsync(ss->wsrc.p, warm_src[c].data(), warm_src[c].size() * sizeof(WarmSrc),
@@ -887,7 +889,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                     return false;
                 if (dtype == 0) launch_serve_warm<double>(c, B, (const WarmSrc *)ss->wsrc.p, (int)warm_src[c].size(), s);
                 else launch_serve_warm<float>(c, B, (const WarmSrc *)ss->wsrc.p, (int)warm_src[c].size(), s);
-                if (!dev_ok(hipStreamSynchronize(s), "warm init")) return false;
+                if (!dev_ok(hipGetLastError(), "warm init")) return false;
             }
         }
         std::vector<int32_t> bad(nf);
