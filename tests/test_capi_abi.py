@@ -95,3 +95,20 @@ def test_batch_pack_records_point_into_the_flat_arrays():
         y_off += p.n
         s_off += p.m
     assert admm._np_dtype(admm.admm_info).itemsize == C.sizeof(admm.admm_info)
+
+
+def test_batch_pack_refuses_what_the_batched_kernel_does_not_take():
+    """A pack holds q = 1 instances with per-source bounds and no f0/g0."""
+    import pytest
+    ok = W.uniform_problem(2, 10, 1)
+    robust = W.uniform_problem(2, 10, 2, q=3)
+    per_step = W.uniform_problem(2, 10, 3)
+    per_step.xlo = np.zeros((2, 10))
+    per_step.xhi = np.full((2, 10), 2.0)
+    with_g0 = W.uniform_problem(2, 10, 4)
+    with_g0.g0 = np.zeros_like(with_g0.g2)
+    for bad in (robust, per_step, with_g0):
+        with pytest.raises(ValueError):
+            admm.BatchPack([ok, bad])
+    with pytest.raises(ValueError):
+        admm.BatchPack([])
