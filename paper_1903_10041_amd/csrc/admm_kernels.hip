@@ -679,7 +679,7 @@ __device__ __forceinline__ void chainq_store(const SolveParams &P, int ws, const
     }
 }
 
-template <typename T, int MAXM, int MODE, bool CHECK>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT>
 __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) {
     const int ws = rs ^ 1, m = P.m;
     const int nbs = P.nblk, ntile = P.q * nbs;
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) 
         Acc<MAXM> acc;
         acc.reset();
         if (k < P.n) {
-            col_update<T, MAXM, MODE, CHECK, F_ALL>(Q, j, k, d, sc, acc);
+            col_update<T, MAXM, MODE, CHECK, FEAT>(Q, j, k, d, sc, acc);
             col_store<T, MAXM>(Q, j, k, d);
         }
         chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, tl, acc, CHECK, red, (size_t)ntile * m);
@@ -1104,22 +1104,24 @@ int max_m_supported() { return 8; }
 template <typename T, int MODE, int CPT, bool CHECK, int FEAT>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
     const dim3 grid(P.nblk, P.q);
-    if (FEAT == 0 && P.m == 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT, 2><<<grid, kBlock, 0, s>>>(P);
-    else if (FEAT == 0 && P.m == 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT, 4><<<grid, kBlock, 0, s>>>(P);
+    if (FEAT != F_ALL && P.m == 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT, 2><<<grid, kBlock, 0, s>>>(P);
+    else if (FEAT != F_ALL && P.m == 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT, 4><<<grid, kBlock, 0, s>>>(P);
     else if (P.m <= 2) k_sweep<T, 2, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
     else if (P.m <= 4) k_sweep<T, 4, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
     else k_sweep<T, 8, CPT, MODE, CHECK, FEAT><<<grid, kBlock, 0, s>>>(P);
 }
 
 // One column per thread without the optional features (no g0, per-source
-// bounds, no branch codes, Gauss-Seidel, EXACT_BOX, no consensus) is the
-// common case and gets its own kernel; everything else the general one.
+// bounds, no branch codes, Gauss-Seidel, EXACT_BOX) is the common case and
+// gets its own kernels, without or with the consensus block (scenario
+// programs); everything else the general one.
 template <typename T, int MODE, bool CHECK>
 static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
-    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project && !P.consensus;
+    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
     switch (P.cpt) {
     case 1:
-        if (plain) launch_sweep_c<T, MODE, 1, CHECK, 0>(P, s);
+        if (plain && !P.consensus) launch_sweep_c<T, MODE, 1, CHECK, 0>(P, s);
+        else if (plain) launch_sweep_c<T, MODE, 1, CHECK, F_CONS>(P, s);
         else launch_sweep_c<T, MODE, 1, CHECK, F_ALL>(P, s);
         break;
     case 2: launch_sweep_c<T, MODE, 2, CHECK, F_ALL>(P, s); break;
@@ -1211,8 +1213,15 @@ static void launch_chain_k(const SolveParams &P, int rs, hipStream_t s) {
 template <typename T, int MODE, bool CHECK>
 static void launch_chain_q(const SolveParams &P, int rs, hipStream_t s) {
     const unsigned g = (unsigned)(P.cgrid > 0 ? P.cgrid : P.q * P.nblk);
-    if (P.m <= 2) k_chain_q<T, 2, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
-    else k_chain_q<T, 4, MODE, CHECK><<<g, kChainBlock, 0, s>>>(P, rs);
+    // the consensus block alone, or with other optional features
+    const bool cons_only = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
+    if (cons_only) {
+        if (P.m <= 2) k_chain_q<T, 2, MODE, CHECK, F_CONS><<<g, kChainBlock, 0, s>>>(P, rs);
+        else k_chain_q<T, 4, MODE, CHECK, F_CONS><<<g, kChainBlock, 0, s>>>(P, rs);
+    } else {
+        if (P.m <= 2) k_chain_q<T, 2, MODE, CHECK, F_ALL><<<g, kChainBlock, 0, s>>>(P, rs);
+        else k_chain_q<T, 4, MODE, CHECK, F_ALL><<<g, kChainBlock, 0, s>>>(P, rs);
+    }
 }
 
 bool chain_q_fits(int m, int q, int n) {
