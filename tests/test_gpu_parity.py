@@ -6,8 +6,10 @@ Tolerances (FP64 path):
     outside the near-tie margins; x equal to 1e-12 absolute (x is O(1)).
   - trajectory (fixed iteration counts): relative objective <= 1e-9;
     max |x_gpu - x_oracle| <= 1e-9; residuals r, sigma within 1e-6
-    relative (they are differences of iterates, so their relative error
-    is larger than the iterates').
+    relative plus their rounding radius (residual_tol below): each is a
+    difference of sums over n horizon terms that the two sides add in
+    different orders, so below about 4 (n + m) eps times the size of those
+    sums no two correct implementations need agree.
   - convergence: the stopping check is the same or one check apart.
 """
 import math
@@ -33,6 +35,21 @@ def ctx():
     c = admm.Context(0)
     yield c
     c.close()
+
+
+EPS = np.finfo(np.float64).eps
+
+
+def residual_tol(p, st, ref):
+    """Tolerance of a GPU residual against the oracle's value `ref` on the
+    oracle state `st`: 1e-6 relative plus the rounding radius of the sums
+    the residuals are made of (1'z over n steps per (i, j), sum_i x per
+    column), 4 (n + m) eps times their magnitude, scaled by the largest rho."""
+    x = st["x"]
+    g = p.g2 * x * x + p.g1 * x
+    scale = (1.0 + np.abs(g).sum(axis=2).max() + np.abs(st["z"]).sum(axis=2).max()
+             + np.abs(st["h"]).max() + np.abs(p.y).max() + p.m * np.abs(x).max())
+    return 1e-6 * abs(ref) + 4 * (p.n + p.m) * EPS * scale * max(1.0, max(p.rho))
 
 
 def fixed(p, iters, **kw):
@@ -84,7 +101,20 @@ def test_trajectory_parity_fp64(ctx, name):
     assert rel <= 1e-9
     assert dx <= 1e-9
     for key in ("r", "sigma"):
-        assert abs(info[key] - oinfo[key]) <= 1e-6 * abs(oinfo[key]) + 1e-10, key
+        assert abs(info[key] - oinfo[key]) <= residual_tol(p, st, oinfo[key]), key
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_parity_early(ctx, name):
+    """r and sigma at iteration 40, where they are far above their rounding
+    radius on every case, so the comparison is not vacuous."""
+    p = CASES[name]()
+    x, info, st, oinfo = _trajectory(ctx, p, 40)
+    for key in ("r", "sigma"):
+        tol = residual_tol(p, st, oinfo[key])
+        say(f"[residual-early] {name} {key} gpu={info[key]:.9e} oracle={oinfo[key]:.9e} tol={tol:.1e}")
+        assert oinfo[key] > 100 * (tol - 1e-6 * abs(oinfo[key])), (key, oinfo[key])
+        assert abs(info[key] - oinfo[key]) <= tol, key
 
 
 @pytest.mark.parametrize("flags", [{"xstep": admm.XSTEP_PAPER_PROJECT}, {"sweep": admm.SWEEP_JACOBI},
@@ -250,10 +280,15 @@ LAUNCHES = {"split": admm.LAUNCH_SPLIT, "chained": admm.LAUNCH_CHAINED, "residen
 def test_launch_path_trajectory(ctx, name, launch):
     p = LAUNCH_CASES[name]()
     iters = 200 if p.n > 10000 else 500
-    if launch == "resident" and p.n > 10000:
-        pytest.skip("the resident launch only takes grids that fit on the device at once")
     say(f"[launch] {name} {launch} m={p.m} n={p.n} iters={iters}")
-    x, info, _ = ctx.solve(p, fixed(p, iters, launch=LAUNCHES[launch]))
+    try:
+        x, info, _ = ctx.solve(p, fixed(p, iters, launch=LAUNCHES[launch]))
+    except admm.AdmmError as e:
+        # the resident launch only takes grids whose blocks all fit on the
+        # device at once; past that the call is refused, never degraded
+        say(f"   refused: {e}")
+        assert launch == "resident" and e.status == admm.E_UNSUPPORTED
+        return
     st, oinfo, _ = oracle.run(p, max_iter=iters, nthreads=8)
     rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
     dx = float(np.abs(x - st["x"]).max())
@@ -266,7 +301,7 @@ def test_launch_path_trajectory(ctx, name, launch):
     dx_tol = 1e-9 if p.n <= 10000 else 1e-8
     assert rel <= 1e-9 and dx <= dx_tol
     for key in ("r", "sigma"):
-        assert abs(info[key] - oinfo[key]) <= 1e-6 * abs(oinfo[key]) + 1e-10, key
+        assert abs(info[key] - oinfo[key]) <= residual_tol(p, st, oinfo[key]), key
 
 
 @pytest.mark.parametrize("launch", list(LAUNCHES))
@@ -371,7 +406,7 @@ def test_chained_consensus_trajectory(ctx, name):
     rel_tol = 1e-9 if p.m * p.n * p.q <= 20000 else 1e-8
     assert dx <= 1e-9 and rel <= rel_tol
     for key in ("r", "sigma"):
-        assert abs(info[key] - oinfo[key]) <= 1e-6 * abs(oinfo[key]) + 1e-10, key
+        assert abs(info[key] - oinfo[key]) <= residual_tol(p, st, oinfo[key]), key
 
 
 def test_chained_consensus_convergence(ctx):
