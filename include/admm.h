@@ -201,6 +201,34 @@ admm_status admm_solve(admm_context *ctx, const admm_problem *prob,
                        const admm_settings *settings, const admm_state *warm,
                        void *x_out, admm_state *state_out, admm_info *info);
 
+/* Continue the most recent admm_solve on this context from the iterate it
+ * left in device memory: the iteration (7a)-(7i) goes on for at most
+ * more_iter further iterations (counting and checking every check_every
+ * from where it stopped, Sec. IV-B), now against the thresholds
+ * eps_primal, eps_dual, with every other setting of that solve.  A solve
+ * of a + b iterations and a solve of a followed by a resume of b give the
+ * same bits.  x_out, state_out and info are as for admm_solve, in the
+ * memspace and dtype of that solve's problem; info->iters counts from the
+ * original start.  The problem's arrays are not read again (the context
+ * holds its packed copy).  Errors: ADMM_E_INVALID_ARG when the context has
+ * no solve to continue (none yet, or the last one failed, or another entry
+ * point (solve_batch, profile) reused the workspace since), more_iter < 0
+ * or negative thresholds. */
+admm_status admm_resume(admm_context *ctx, int32_t more_iter, double eps_primal, double eps_dual,
+                        void *x_out, admm_state *state_out, admm_info *info);
+
+/* Queue at most more_iter further iterations of the most recent solve on
+ * this context (as admm_resume, with that solve's thresholds) behind the
+ * caller's stream and return without waiting for them: nothing is read
+ * back, and the device stops on its own at the thresholds or the new
+ * iteration cap.  x_out (may be NULL): device memory of the problem's dtype
+ * that receives x after those iterations, in stream order (only for a
+ * solve of a problem in device memory).  A later admm_resume (e.g. with
+ * more_iter = 0) returns x, the state and info.  A solve stopped at its
+ * iteration cap runs on; a converged one stays stopped.  The resident
+ * launch path waits for each of its launches.  Errors as admm_resume. */
+admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *x_out);
+
 /* Solve `count` independent instances of different shapes in one persistent
  * launch.  All problems share one memspace and dtype.  warm may be NULL
  * (all cold).  x_out[b] is instance b's [q][m][n] output.  infos: [count].

@@ -92,6 +92,8 @@ def lib():
             "admm_create": (C.c_int, [C.POINTER(vp), C.c_int, C.c_size_t, vp]),
             "admm_set_stream": (C.c_int, [vp, vp]),
             "admm_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "admm_resume": (C.c_int, [vp, i32, C.c_double, C.c_double, vp, vp, vp]),
+            "admm_iterate": (C.c_int, [vp, i32, vp]),
             "admm_solve_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
             "admm_submit": (C.c_int, [vp, vp, vp, u64, C.POINTER(u64)]),
             "admm_poll": (C.c_int, [vp, u64, vp, vp]),
@@ -312,6 +314,8 @@ class Context:
                               C.byref(wst) if wst is not None else None, xptr,
                               C.byref(st_c) if st_c is not None else None, C.byref(inf))
         _check(st)
+        self._last = (m, n, q, mp.device, prob.f2.dtype if mp.device else None,
+                      prob.f2.device if mp.device else None)
         out = info_dict(inf)
         if want_codes:
             codes = np.empty((q, m, n), dtype=np.uint8)
@@ -320,6 +324,54 @@ class Context:
         if st_out is not None:
             st_out["lam"] = st_out["lambda_"]
         return x_out, out, st_out
+
+
+    def resume(self, more_iter: int, eps_primal: float = 0.0, eps_dual: float = 0.0,
+               want_state: bool = False, x_out=None):
+        """admm_resume: continue the last solve of this context for at most
+        ``more_iter`` further iterations.  Returns (x, info dict, state dict
+        or None), x in the memspace and dtype of that solve's problem."""
+        last = getattr(self, "_last", None)
+        if last is None:
+            raise AdmmError(E_INVALID_ARG, "no solve to resume on this context")
+        m, n, q, device, tdt, tdev = last
+        if x_out is None:
+            if device:
+                import torch
+                x_out = torch.empty((q, m, n), dtype=tdt, device=tdev)
+            else:
+                x_out = np.empty((q, m, n))
+        xptr = x_out.data_ptr() if device else x_out.ctypes.data
+        st_out = st_c = None
+        if want_state:
+            st_out = {k: np.empty(shp) for k, shp in _state_shapes(m, n, q).items()}
+            st_c = admm_state(*[st_out[k].ctypes.data for k in STATE_KEYS])
+        inf = admm_info()
+        if device:
+            import torch
+            self.set_stream(torch.cuda.current_stream(tdev).cuda_stream)
+        st = lib().admm_resume(self.h, int(more_iter), float(eps_primal), float(eps_dual), xptr,
+                               C.byref(st_c) if st_c is not None else None, C.byref(inf))
+        _check(st)
+        if st_out is not None:
+            st_out["lam"] = st_out["lambda_"]
+        return x_out, info_dict(inf), st_out
+
+
+    def iterate(self, more_iter: int, x_out=None):
+        """admm_iterate: queue at most ``more_iter`` further iterations of the
+        last solve on the current stream and return at once; ``x_out`` (a
+        device tensor of the problem's dtype, or None) receives x after
+        them in stream order."""
+        last = getattr(self, "_last", None)
+        if last is None:
+            raise AdmmError(E_INVALID_ARG, "no solve to resume on this context")
+        if last[3]:
+            import torch
+            self.set_stream(torch.cuda.current_stream(last[5]).cuda_stream)
+        _check(lib().admm_iterate(self.h, int(more_iter), x_out.data_ptr() if x_out is not None else None),
+               allow=(OK,))
+        return x_out
 
 
 def _np_dtype(struct):

@@ -394,11 +394,17 @@ extern "C" admm_status admm_solve_batch(admm_context *ctx, int32_t count, const 
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
         DeviceGuard g(ctx->device);
+        ctx->last.valid = false;
         if ((st = solve_batch_core(ctx, probs, in_batch, S, x_out, infos)) != ADMM_OK) return st;
     }
     for (int b : alone) {
         st = admm_solve(ctx, &probs[b], &S, warm ? warm[b] : nullptr, x_out[b], nullptr, &infos[b]);
         if (st < 0) return fail(st, "batch instance " + std::to_string(b) + ": " + g_last_error);
+    }
+    {
+        // nothing of a batch is continued by admm_resume
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ctx->last.valid = false;
     }
     bool any_max = false;
     for (int b = 0; b < count; ++b) {
@@ -972,6 +978,7 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
         }
         if (!finished.empty() && !dev_ok(hipStreamSynchronize(s), "readback")) return false;
     }
+    std::vector<std::pair<uint64_t, WarmEntry>> new_warm;
     for (size_t f = 0; f < finished.size(); ++f) {
         ServeReq *r = finished[f];
         admm_info &inf = r->info;
@@ -994,21 +1001,20 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                     const size_t e = (size_t)i * r->n_pad + k;
                     r->x[(size_t)i * r->n + k] = T == 8 ? ((const double *)xb)[e] : (double)((const float *)xb)[e];
                 }
-            // warm store: x and w of this final iterate, lambda and p
+            // warm store: x and w of this final iterate, lambda and p,
+            // copied into a region of its own; the entry is published only
+            // once the copies have completed (below), since a lane takes
+            // entries from the map and reads them on its own stream
             if (r->key) {
-                std::lock_guard<std::mutex> lk(ss->mu);
-                ss->hwarm.erase(r->key);
-                auto it = ss->warm.find(r->key);
-                if (it != ss->warm.end()) {
-                    ss->fl.release(it->second.off, it->second.bytes);
-                    ss->warm.erase(it);
-                }
                 WarmEntry we;
                 we.m = r->m;
                 we.n = r->n;
                 we.n_pad = r->n_pad;
                 we.bytes = ((size_t)r->m * r->n_pad + r->n_pad) * T;
-                we.off = ss->fl.alloc(we.bytes);
+                {
+                    std::lock_guard<std::mutex> lk(ss->mu);
+                    we.off = ss->fl.alloc(we.bytes);
+                }
                 if (we.off != SIZE_MAX) {
                     (void)hipMemcpyAsync(base + we.off, base + r->x_b, (size_t)r->m * r->n_pad * T,
                                          hipMemcpyDeviceToDevice, s);
@@ -1016,8 +1022,16 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
                                          hipMemcpyDeviceToDevice, s);
                     we.lam.assign(pool, pool + r->m);
                     we.p.assign(pool + 3 * r->m, pool + 4 * r->m);
-                    we.stamp = ++ss->stamp;
-                    ss->warm[r->key] = we;
+                    new_warm.emplace_back(r->key, std::move(we));
+                } else {
+                    // no room: the key starts cold next time
+                    std::lock_guard<std::mutex> lk(ss->mu);
+                    ss->hwarm.erase(r->key);
+                    auto it = ss->warm.find(r->key);
+                    if (it != ss->warm.end()) {
+                        ss->fl.release(it->second.off, it->second.bytes);
+                        ss->warm.erase(it);
+                    }
                 }
             }
         }
@@ -1026,6 +1040,18 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
     if (!dev_ok(hipStreamSynchronize(s), "warm store")) return false;
     {
         std::lock_guard<std::mutex> lk(ss->mu);
+        // the copies are complete: publish the new warm states (a later
+        // finished request of the same key replaces an earlier one)
+        for (auto &kw : new_warm) {
+            ss->hwarm.erase(kw.first);
+            auto it = ss->warm.find(kw.first);
+            if (it != ss->warm.end()) {
+                ss->fl.release(it->second.off, it->second.bytes);
+                ss->warm.erase(it);
+            }
+            kw.second.stamp = ++ss->stamp;
+            ss->warm[kw.first] = std::move(kw.second);
+        }
         for (ServeReq *r : finished) {
             ss->fl.release(r->off, r->bytes);
             r->off = SIZE_MAX;

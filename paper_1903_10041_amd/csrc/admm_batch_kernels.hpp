@@ -53,7 +53,6 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.chain = 0;
     P.group = 1;
     P.check_every = I.check_every;
-    P.max_iter = I.max_iter;
     P.xstep_project = I.flags & 1;
     P.jacobi = (I.flags >> 1) & 1;
     P.consensus = 0;
@@ -67,8 +66,7 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.tau = P.band_hi = P.band_lo = 1.0;
     P.wdiv = 1.0;
     P.rho_cur = nullptr;
-    P.eps_p = I.eps_p;
-    P.eps_d = I.eps_d;
+    P.lim = nullptr;
     P.coef = nullptr;
     P.g0 = nullptr;
     P.f0 = nullptr;
@@ -211,7 +209,7 @@ void k_batch(BatchParams B) {
         const int win = Iu.window > 0 ? min(Iu.window, B.window) : B.window;
         for (int wi = 0; wi < win; ++wi) {
             const int t1 = s_t + 1;
-            if (t1 > P.max_iter) break;
+            if (t1 > Iu.max_iter) break;
             const bool check = (t1 % P.check_every) == 0;
             if (tid < MAXM) {
                 const int i = tid;
@@ -290,9 +288,9 @@ void k_batch(BatchParams B) {
                     s_r = r;
                     s_sg = sg;
                     if (!(r == r) || !(sg == sg)) s_stop = -4;
-                    else if (r < P.eps_p && sg < P.eps_d) s_stop = 1;
+                    else if (r < Iu.eps_p && sg < Iu.eps_d) s_stop = 1;
                 }
-                if (!s_stop && t1 >= P.max_iter) s_stop = 2;
+                if (!s_stop && t1 >= Iu.max_iter) s_stop = 2;
             }
             __syncthreads();
             if (s_stop) break;

@@ -415,7 +415,8 @@ __device__ __forceinline__ void adapt_load(SolveParams &Q, const double *rho, co
 // Residual balancing at a check iteration that does not stop (Sec. IV-A):
 // the factor applied to every rho_i (the scaled duals are divided by it).
 __device__ __forceinline__ double adapt_factor(const SolveParams &P, double r, double sigma) {
-    const double target = (P.eps_p > 0.0 && P.eps_d > 0.0) ? P.eps_p / P.eps_d : 1.0;
+    const double ep = P.lim->eps_p, ed = P.lim->eps_d;
+    const double target = (ep > 0.0 && ed > 0.0) ? ep / ed : 1.0;
     const double ratio = sigma > 0.0 ? r / sigma : INFINITY;
     if (ratio > P.band_hi * target) return P.tau;
     if (ratio < P.band_lo * target) return 1.0 / P.tau;
@@ -616,7 +617,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
         r = block_max<NT / 64>(r, lds);
         sg = block_max<NT / 64>(sg, lds);
         const bool bad = !(r == r) || !(sg == sg);
-        const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
+        const bool stop = bad || (r < P.lim->eps_p && sg < P.lim->eps_d);
         if (tid == 0) {
             ctrl->r = r;
             ctrl->sigma = sg;
@@ -643,7 +644,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
     __syncthreads();
     if (tid == 0) {
         ctrl->t = t1;
-        if (!ctrl->done && t1 >= P.max_iter) { ctrl->status = 2; ctrl->done = 1; }
+        if (!ctrl->done && t1 >= P.lim->max_iter) { ctrl->status = 2; ctrl->done = 1; }
     }
 }
 

@@ -43,6 +43,30 @@ struct BatchState;
 struct ServeState;
 extern thread_local std::string g_last_error;
 
+// A captured chunk of `chunk` iterations for one problem layout, starting
+// at chained-slot parity `phase`.  The kernels read the stop limits from
+// device memory, so the chunk is reused by any later solve of the same
+// shape and buffers whatever its thresholds or iteration cap.
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    SolveParams P;
+    int dtype = -1, chunk = 0, phase = 0;
+    uint64_t used = 0;
+};
+constexpr int kGraphCache = 4;
+
+// What admm_resume needs of the context's most recent solve.
+struct LastSolve {
+    bool valid = false;
+    SolveParams P;
+    int dtype = 0;
+    int32_t m = 0, n = 0, q = 0;
+    admm_memspace mem = ADMM_HOST;
+    admm_precision out_dtype = ADMM_F64;
+    int32_t t = 0;
+    bool t_exact = true;        // false: t is the planned count of an admm_iterate
+};
+
 }  // namespace admm
 
 struct admm_context {
@@ -52,12 +76,14 @@ struct admm_context {
     hipStream_t user = nullptr;     // caller's stream (join point)
     hipStream_t own = nullptr;      // the context's work stream
     hipEvent_t join = nullptr, ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t fev[2] = {nullptr, nullptr};   // segment ends (control-block copies)
     admm::Ctrl *hctrl = nullptr;    // pinned mirror of a Ctrl
     std::mutex mu;                  // serialises solve / solve_batch
     admm::Workspace ws;
-    hipGraphExec_t gexec = nullptr; // cached iteration-chunk graph
-    admm::SolveParams gparams;
-    int gdtype = -1, gchunk = 0;
+    admm::GraphEntry graphs[admm::kGraphCache];   // captured iteration chunks, least recently used replaced
+    uint64_t graph_clock = 0;
+    admm::Lim lim;                  // host copy of the current solve's stop limits
+    admm::LastSolve last;           // the most recent solve (admm_resume)
     bool coop = false;              // cooperative launch supported
     int num_cu = 0;
     int persist_cap[3][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
@@ -78,7 +104,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
                     int &dtype);
 admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
                           hipStream_t s);
-admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms);
+admm_status upload_limits(admm_context *ctx, const SolveParams &P, hipStream_t s);
+admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll);
 
 void batch_release(admm_context *ctx);
 void serve_shutdown(admm_context *ctx);

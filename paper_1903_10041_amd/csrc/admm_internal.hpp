@@ -2,6 +2,7 @@
 // ADMM library.  Not part of the public ABI (include/admm.h is).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cstddef>
 #include <cstdint>
 
 namespace admm {
@@ -27,6 +28,20 @@ struct Ctrl {
     double pad_;
 };
 static_assert(sizeof(Ctrl) == 64, "Ctrl is one 64-byte line");
+static_assert(offsetof(Ctrl, done) == offsetof(Ctrl, status) + 4, "status and done are adjacent");
+
+// Stop limits of one solve, in device memory beside the control block.  The
+// kernels read them there rather than from their launch parameters, so a
+// captured chunk of iterations depends only on the problem's shape and
+// buffers and is replayed unchanged when a later solve (or a resumed one)
+// asks for other thresholds or another iteration cap.
+struct Lim {
+    double eps_p, eps_d;    // r_bar, sigma_bar: stop when r < eps_p and sigma < eps_d
+    int32_t max_iter;       // stop (status 2) once t reaches it
+    int32_t pad_i;
+    double pad_[5];
+};
+static_assert(sizeof(Lim) == 64, "Lim is one 64-byte line");
 
 // Branch classes of the x-step (code = 3 * branch + clamp state).
 enum { BR_QUAD = 0, BR_CARDANO = 1, BR_TRIPLE = 2, BR_TRIG_LO = 3, BR_TRIG_HI = 4 };
@@ -44,9 +59,10 @@ struct SolveParams {
     int32_t chunks;         // chained: kChainBlock-column chunks each block sweeps in turn
     int32_t cgrid;          // chained with consensus: blocks of the launch (tiles are dealt round robin)
     int32_t group;          // finalize: lanes cooperating on one (i,j) pair
-    int32_t check_every, max_iter;
+    int32_t check_every;
     int32_t xstep_project, jacobi, consensus, want_codes;
-    double rho1, rho2, rho3, rho4, inv_q, eps_p, eps_d;
+    double rho1, rho2, rho3, rho4, inv_q;
+    const Lim *lim;         // eps_p, eps_d, max_iter (device memory)
     // adaptive rho (Sec. IV-A): the current rho_1..4 live in rho_cur ([4],
     // a second [4] for the chained path's other slot); a kernel copies them
     // into its own rho1..4 and the pending mu divisor into wdiv
@@ -90,12 +106,16 @@ hipError_t launch_pack(const SolveParams &P, int dtype, int src_dtype,
                        const void *blo, const void *bhi, void *g0_dst, void *f0_dst,
                        void *y_dst, void *blo_dst, void *bhi_dst, hipStream_t s);
 hipError_t launch_cold_init(const SolveParams &P, int dtype, hipStream_t s);
+// Stop limits of the solve into *P.lim; unstop 1 re-runs a solve stopped at
+// its iteration cap, 2 any stopped solve.
+hipError_t launch_set_run(const SolveParams &P, const Lim &v, int unstop, hipStream_t s);
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
 // Chained path: launch at graph position c reads slot c & 1 (rs).
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s);
-hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s);
+// Completes the pending iteration of slot rs into slot 0.
+hipError_t launch_chain_flush(const SolveParams &P, int rs, hipStream_t s);
 bool chain_q_fits(int m, int q, int n);   // the chained launch with consensus applies
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);

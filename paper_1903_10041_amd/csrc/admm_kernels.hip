@@ -304,12 +304,12 @@ __device__ __forceinline__ void chain_finish(const SolveParams &P, int rs, const
                 r = fmax(rres[0], wave_max(pr));
                 sg = fmax(rho[2] * rres[1], wave_max(ps));
                 const bool bad = !(r == r) || !(sg == sg);
-                const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
+                const bool stop = bad || (r < P.lim->eps_p && sg < P.lim->eps_d);
                 if (bad) { status = -4; dn = 1; }
                 else if (stop) { status = 0; dn = 1; }
                 if (P.adaptive && !stop) f = adapt_factor(P, r, sg);
             }
-            if (!dn && t >= P.max_iter) { status = 2; dn = 1; }
+            if (!dn && t >= P.lim->max_iter) { status = 2; dn = 1; }
         }
         if (f != 1.0) {
             // the scaled duals follow the change of rho (mu on its next read)
@@ -485,13 +485,13 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     }
 }
 
-// Completes a pending iteration in place in slot 0 (one block), after the
-// last chunk of a solve.
+// Completes a pending iteration of slot rs into slot 0 (one block), after
+// the last launch of a solve, so that the state rests in slot 0.
 template <int MAXM>
-__global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P) {
+__global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P, int rs) {
     __shared__ ChainShared<MAXM> sh;
-    const double wd = P.ctrl->wdiv;
-    chain_prologue<MAXM, kChainBlock>(P, 0, sh);
+    const double wd = (rs ? P.ctrl1 : P.ctrl)->wdiv;
+    chain_prologue<MAXM, kChainBlock>(P, rs, sh);
     // a divisor decided here (or left by a launch that stopped) is pending
     chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad, sh.f != 1.0 ? sh.f : wd);
 }
@@ -635,11 +635,11 @@ __device__ __forceinline__ void chainq_steps(const SolveParams &P, int rs, Chain
 #pragma unroll
             for (int w = 1; w < kChainBlock / 64; ++w) { r = fmax(r, sh.red[w][0]); sg = fmax(sg, sh.red[w][1]); }
             const bool bad = !(r == r) || !(sg == sg);
-            const bool stop = bad || (r < P.eps_p && sg < P.eps_d);
+            const bool stop = bad || (r < P.lim->eps_p && sg < P.lim->eps_d);
             if (bad) { status = -4; dn = 1; }
             else if (stop) { status = 0; dn = 1; }
         }
-        if (!dn && t >= P.max_iter) { status = 2; dn = 1; }
+        if (!dn && t >= P.lim->max_iter) { status = 2; dn = 1; }
     }
     if (act) {
         sh.toff[tid] = zoff + lam;
@@ -737,14 +737,15 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) 
     }
 }
 
-// Completes a pending iteration in place in slot 0 (one block).
+// Completes a pending iteration of slot rs into slot 0 (one block); x_1
+// moves along when it comes from slot 1.
 template <int MAXM>
-__global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P) {
+__global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P, int rs) {
     __shared__ ChainQShared<MAXM> sh;
     double lam, zoff, h, p, nu, x1, r, sg;
     int st[4];
-    chainq_steps<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, st, r, sg);
-    chainq_store<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, false, st[0], 0, st, r, sg);
+    chainq_steps<MAXM>(P, rs, sh, lam, zoff, h, p, nu, x1, st, r, sg);
+    chainq_store<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, rs != 0, st[0], 0, st, r, sg);
 }
 
 // ---------------------------------------------------- persistent resident
@@ -997,8 +998,8 @@ __global__ __launch_bounds__(kBlock) void k_init_final(SolveParams P) {
         P.ctrl->t = 0;
         P.ctrl->r = INFINITY;
         P.ctrl->sigma = INFINITY;
-        P.ctrl->status = P.max_iter > 0 ? -1 : 2;
-        P.ctrl->done = P.max_iter > 0 ? 0 : 1;
+        P.ctrl->status = P.lim->max_iter > 0 ? -1 : 2;
+        P.ctrl->done = P.lim->max_iter > 0 ? 0 : 1;
         P.ctrl->pending = 0;
         P.ctrl->wdiv = 1.0;
     }
@@ -1086,6 +1087,23 @@ __global__ __launch_bounds__(kBlock) void k_obj_final(SolveParams P, const doubl
 
 // Plain copy of known size (reads and writes `n16` 16-byte words once):
 // the reference for scaling hardware byte counters.
+// Sets the stop limits of a solve and, per `unstop`, lets a stopped solve
+// run again: 1 a stop at the iteration cap, 2 any stop (new thresholds).
+// One thread; the values travel as launch arguments, so nothing on the host
+// has to outlive the call.
+__global__ void k_set_run(Ctrl *ctrl, Lim *lim, Lim v, int unstop) {
+    *lim = v;
+    if (unstop == 2 || (unstop == 1 && ctrl->status == 2)) {
+        ctrl->status = -1;
+        ctrl->done = 0;
+    }
+}
+
+hipError_t launch_set_run(const SolveParams &P, const Lim &v, int unstop, hipStream_t s) {
+    k_set_run<<<1, 1, 0, s>>>(P.ctrl, const_cast<Lim *>(P.lim), v, unstop);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kBlock) void k_copy_calib(const float4 *src, float4 *dst, size_t n16) {
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < n16; i += (size_t)gridDim.x * kBlock)
         dst[i] = src[i];
@@ -1258,16 +1276,16 @@ hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hip
     return hipGetLastError();
 }
 
-hipError_t launch_chain_flush(const SolveParams &P, hipStream_t s) {
-    if (P.m > 4) return hipErrorInvalidValue;
+hipError_t launch_chain_flush(const SolveParams &P, int rs, hipStream_t s) {
+    if (P.m > 4 || (rs != 0 && rs != 1)) return hipErrorInvalidValue;
     if (P.consensus) {
         if ((int64_t)P.m * P.q > kChainBlock) return hipErrorInvalidValue;
-        if (P.m <= 2) k_chain_q_flush<2><<<1, kChainBlock, 0, s>>>(P);
-        else k_chain_q_flush<4><<<1, kChainBlock, 0, s>>>(P);
+        if (P.m <= 2) k_chain_q_flush<2><<<1, kChainBlock, 0, s>>>(P, rs);
+        else k_chain_q_flush<4><<<1, kChainBlock, 0, s>>>(P, rs);
         return hipGetLastError();
     }
-    if (P.m <= 2) k_chain_flush<2><<<1, kChainBlock, 0, s>>>(P);
-    else k_chain_flush<4><<<1, kChainBlock, 0, s>>>(P);
+    if (P.m <= 2) k_chain_flush<2><<<1, kChainBlock, 0, s>>>(P, rs);
+    else k_chain_flush<4><<<1, kChainBlock, 0, s>>>(P, rs);
     return hipGetLastError();
 }
 

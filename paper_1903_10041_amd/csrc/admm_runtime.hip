@@ -11,6 +11,7 @@
 #include "admm_host.hpp"
 
 #include <algorithm>
+#include <cstddef>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -177,7 +178,9 @@ extern "C" admm_status admm_create(admm_context **out, int device, size_t budget
     if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->hctrl, 4 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->fev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fev[1], hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hctrl, 6 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return fail(ADMM_E_DEVICE, "stream/event/pinned allocation failed");
     }
@@ -201,13 +204,16 @@ extern "C" void admm_destroy(admm_context *ctx) {
     serve_shutdown(ctx);
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->own);
-    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (GraphEntry &g : ctx->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (DevBuf *b : ctx->ws.all()) ctx->arena.release(*b);
     batch_release(ctx);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
     (void)hipEventDestroy(ctx->join);
     (void)hipEventDestroy(ctx->ev0);
     (void)hipEventDestroy(ctx->ev1);
+    (void)hipEventDestroy(ctx->fev[0]);
+    (void)hipEventDestroy(ctx->fev[1]);
     (void)hipStreamDestroy(ctx->own);
     delete ctx;
 }
@@ -398,7 +404,10 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     // one block of kFinalBlock threads, the resident path in one of kBlock
     P.group = finalize_group(m, q, nblk, P.persistent ? kBlock : kFinalBlock);
     P.check_every = s->check_every;
-    P.max_iter = s->max_iter;
+    std::memset(&ctx->lim, 0, sizeof ctx->lim);
+    ctx->lim.max_iter = s->max_iter;
+    ctx->lim.eps_p = s->eps_primal;
+    ctx->lim.eps_d = s->eps_dual;
     P.xstep_project = s->xstep == ADMM_XSTEP_PAPER_PROJECT;
     P.jacobi = s->sweep == ADMM_SWEEP_JACOBI;
     P.consensus = (q > 1) || s->consensus_q1;
@@ -406,8 +415,6 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.rho1 = s->rho[0]; P.rho2 = s->rho[1] / (s->rho2_per_step ? (double)n : 1.0);
     P.rho3 = s->rho[2]; P.rho4 = s->rho[3];
     P.inv_q = 1.0 / q;
-    P.eps_p = s->eps_primal;
-    P.eps_d = s->eps_dual;
     P.adaptive = s->adaptive_rho ? 1 : 0;
     P.tau = s->tau;
     P.band_hi = s->band_hi;
@@ -424,7 +431,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     // xbar1 [m]), rho_cur [2][4]
     ENS(W.scal, (14 * M + 5 * (size_t)m + 8) * sizeof(double));
     ENS(W.part, (chain ? 2 : 1) * part_doubles(m, q, nblk) * sizeof(double));
-    ENS(W.ctrl, 2 * sizeof(Ctrl) + 64);
+    // control slot 0, grid barrier words, control slot 1, stop limits
+    ENS(W.ctrl, 2 * sizeof(Ctrl) + 64 + sizeof(Lim));
     ENS(W.obj, 1024 * sizeof(double));
     if (pr->g0) ENS(W.g0, E * T);
     if (pr->f0) ENS(W.f0, E * T);
@@ -447,6 +455,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.scal1 = sc + 8 * M + 4 * m;
     P.rho_cur = sc + 14 * M + 5 * m;
     P.ctrl1 = (Ctrl *)((char *)W.ctrl.p + sizeof(Ctrl) + 64);
+    P.lim = (const Lim *)((char *)W.ctrl.p + 2 * sizeof(Ctrl) + 64);
     P.part1 = chain ? P.part + part_doubles(m, q, nblk) : nullptr;
     return ADMM_OK;
 }
@@ -489,6 +498,7 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
     const double rho0[8] = {P.rho1, P.rho2, P.rho3, P.rho4, P.rho1, P.rho2, P.rho3, P.rho4};
     HIPCHK(hipMemcpyAsync(P.rho_cur, rho0, sizeof rho0, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl) + 16, s));
+    if (admm_status st = upload_limits(ctx, P, s); st != ADMM_OK) return st;
 
     const void *f2 = pr->f2, *f1 = pr->f1, *g2 = pr->g2, *g1 = pr->g1, *g0 = pr->g0, *f0 = pr->f0;
     const void *y = pr->y, *blo = nullptr, *bhi = nullptr;
@@ -596,8 +606,8 @@ admm_status load_warm(admm_context *ctx, const admm_problem *pr, const admm_stat
     HIPCHK(hipMemcpyAsync(P.xbar1, ws->xbar1, m * sizeof(double), hipMemcpyHostToDevice, s));
     Ctrl c0;
     std::memset(&c0, 0, sizeof c0);
-    c0.status = P.max_iter > 0 ? -1 : 2;
-    c0.done = P.max_iter > 0 ? 0 : 1;
+    c0.status = ctx->lim.max_iter > 0 ? -1 : 2;
+    c0.done = ctx->lim.max_iter > 0 ? 0 : 1;
     c0.r = INFINITY;
     c0.sigma = INFINITY;
     c0.wdiv = 1.0;
@@ -620,11 +630,12 @@ static int chunk_for(int check_every) {
 constexpr int kPersistChunk = 20000;
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-admm_status iterate_persistent(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms) {
+// (It waits for each launch: the host checks the grid barrier's abort word.)
+admm_status iterate_persistent(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, long total) {
     HIPCHK(hipEventRecord(ctx->ev0, s));
-    int done = P.max_iter == 0;
+    int done = total == 0;
     long launched_iters = 0;
-    while (!done && launched_iters < (long)P.max_iter + kPersistChunk) {
+    while (!done && launched_iters < total + kPersistChunk) {
         HIPCHK(hipMemsetAsync(P.bar, 0, 4 * sizeof(uint32_t), s));
         hipError_t e = launch_persist(P, dtype, P.bar, kPersistChunk, kSpinLimit, s);
         if (e != hipSuccess) return fail(ADMM_E_DEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
@@ -636,74 +647,143 @@ admm_status iterate_persistent(admm_context *ctx, const SolveParams &P, int dtyp
         done = ctx->hctrl->done;
     }
     HIPCHK(hipEventRecord(ctx->ev1, s));
-    HIPCHK(hipStreamSynchronize(s));
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    if (dev_ms) *dev_ms = ms;
     return ADMM_OK;
 }
 
-// Run the iteration to the device stop flag with a captured graph per chunk.
-admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, double *dev_ms) {
-    if (P.persistent) return iterate_persistent(ctx, P, dtype, s, dev_ms);
-    const int chunk = chunk_for(P.check_every);
-    const bool reuse = ctx->gexec && ctx->gdtype == dtype && ctx->gchunk == chunk &&
-                       std::memcmp(&ctx->gparams, &P, sizeof P) == 0;
-    if (!reuse) {
-        if (ctx->gexec) { (void)hipGraphExecDestroy(ctx->gexec); ctx->gexec = nullptr; }
-        hipGraph_t g;
-        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        for (int c = 0; c < chunk; ++c) {
-            const bool check = (c + 1) % P.check_every == 0;
-            hipError_t e = P.chain ? launch_chain(P, dtype, check, c & 1, s) : launch_iteration(P, dtype, check, s);
-            if (e != hipSuccess) {
-                hipGraph_t junk;
-                (void)hipStreamEndCapture(s, &junk);
-                if (junk) (void)hipGraphDestroy(junk);
-                return fail(ADMM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+// Stop limits of ctx->lim to the device (as launch arguments of a one-thread
+// kernel, so that no host buffer has to outlive the call).
+admm_status upload_limits(admm_context *ctx, const SolveParams &P, hipStream_t s) {
+    HIPCHK(launch_set_run(P, ctx->lim, 0, s));
+    return ADMM_OK;
+}
+
+// Chunks of direct launches a solve issues for a layout with no captured
+// graph before it captures one (ADMM_DIRECT_CHUNKS): one-off solves of a
+// new shape (serving lanes, closed-loop instants) then pay no capture and
+// instantiation; a solve that keeps going is moved onto a graph.
+static int direct_chunks() {
+    static const int v = [] {
+        const char *e = std::getenv("ADMM_DIRECT_CHUNKS");
+        return e ? std::max(0, std::atoi(e)) : 2;
+    }();
+    return v;
+}
+
+static GraphEntry *graph_find(admm_context *ctx, const SolveParams &P, int dtype, int chunk, int phase) {
+    for (GraphEntry &g : ctx->graphs)
+        if (g.exec && g.dtype == dtype && g.chunk == chunk && g.phase == phase &&
+            std::memcmp(&g.P, &P, sizeof P) == 0) {
+            g.used = ++ctx->graph_clock;
+            return &g;
+        }
+    return nullptr;
+}
+
+// One launch of iteration t (1-based) at chained-slot parity rs.
+static hipError_t launch_one(const SolveParams &P, int dtype, long t, int rs, hipStream_t s) {
+    const bool check = t % P.check_every == 0;
+    return P.chain ? launch_chain(P, dtype, check, rs, s) : launch_iteration(P, dtype, check, s);
+}
+
+// Capture `chunk` launches starting at a multiple of check_every at slot
+// parity `phase`, instantiate, and keep the result in the cache.
+static admm_status graph_build(admm_context *ctx, const SolveParams &P, int dtype, int chunk, int phase,
+                               hipStream_t s, GraphEntry **out) {
+    GraphEntry *g = &ctx->graphs[0];
+    for (GraphEntry &e : ctx->graphs)
+        if (!e.exec || e.used < g->used) { g = &e; if (!e.exec) break; }
+    if (g->exec) { (void)hipGraphExecDestroy(g->exec); g->exec = nullptr; }
+    hipGraph_t gr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < chunk; ++c) {
+        hipError_t e = launch_one(P, dtype, c + 1, (c + phase) & 1, s);
+        if (e != hipSuccess) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(s, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            return fail(ADMM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamEndCapture(s, &gr));
+    hipError_t e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) { g->exec = nullptr; return fail(ADMM_E_DEVICE, "graph instantiate failed"); }
+    g->P = P;
+    g->dtype = dtype;
+    g->chunk = chunk;
+    g->phase = phase;
+    g->used = ++ctx->graph_clock;
+    *out = g;
+    return ADMM_OK;
+}
+
+// Run the iteration from iteration t0 until the device stop flag is set or
+// the limit ctx->lim.max_iter is reached.  Launches go out in segments:
+// direct launches up to the next multiple of check_every, then chunks of
+// `chunk` iterations (a captured graph once the layout has one, or after a
+// few chunks of direct launches), and direct launches for a remainder
+// shorter than a chunk.  With `poll`, each segment is followed by a copy of
+// the control block and the host waits for the one before last (two
+// segments in flight), so it stops issuing soon after the device stops;
+// without, everything is issued at once (launches after a stop do
+// nothing).  On the chained path the state ends in slot 0 (the flush).
+// Returns with the work queued behind ctx->ev0 .. ctx->ev1 on `s`.
+admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll) {
+    const long total = std::max(0L, (long)ctx->lim.max_iter - t0);
+    if (P.persistent) return iterate_persistent(ctx, P, dtype, s, total);
+    const int ce = P.check_every;
+    const int chunk = chunk_for(ce);
+    HIPCHK(hipEventRecord(ctx->ev0, s));
+    Ctrl *hc = ctx->hctrl;
+    long issued = 0, segs = 0;
+    int phase = 0, direct_used = 0;
+    bool done = total == 0;
+    while (!done && issued < total) {
+        const long t = t0 + issued;     // iterations completed before this segment
+        const long rem = total - issued;
+        long seg;
+        GraphEntry *g = nullptr;
+        if (t % ce != 0) {
+            seg = std::min<long>(rem, ce - t % ce);
+        } else if (rem >= chunk) {
+            seg = chunk;
+            g = graph_find(ctx, P, dtype, chunk, phase);
+            if (!g && direct_used >= direct_chunks()) {
+                admm_status st = graph_build(ctx, P, dtype, chunk, phase, s, &g);
+                if (st != ADMM_OK) return st;
+            }
+            if (!g) ++direct_used;
+        } else {
+            seg = rem;
+        }
+        if (g) {
+            if (hipGraphLaunch(g->exec, s) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
+        } else {
+            for (long c = 0; c < seg; ++c) {
+                const hipError_t e = launch_one(P, dtype, t + c + 1, (int)((phase + c) & 1), s);
+                if (e != hipSuccess) return fail(ADMM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
         }
-        HIPCHK(hipStreamEndCapture(s, &g));
-        hipError_t e = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) { ctx->gexec = nullptr; return fail(ADMM_E_DEVICE, "graph instantiate failed"); }
-        ctx->gparams = P;
-        ctx->gdtype = dtype;
-        ctx->gchunk = chunk;
-    }
-    const long max_chunks = (P.max_iter + chunk - 1) / chunk;
-    HIPCHK(hipEventRecord(ctx->ev0, s));
-    // Two chunks in flight: after queuing chunk c (and a copy of the control
-    // block behind it), wait for the copy queued behind chunk c-1.
-    Ctrl *hc = ctx->hctrl;
-    hipEvent_t flag_ev[2] = {nullptr, nullptr};
-    HIPCHK(hipEventCreateWithFlags(&flag_ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&flag_ev[1], hipEventDisableTiming));
-    auto cleanup = [&]() { (void)hipEventDestroy(flag_ev[0]); (void)hipEventDestroy(flag_ev[1]); };
-    long launched = 0;
-    bool done = P.max_iter == 0;
-    while (!done && launched < max_chunks) {
-        const int slot = (int)(launched & 1);
-        if (hipGraphLaunch(ctx->gexec, s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "graph launch failed"); }
-        (void)hipMemcpyAsync(&hc[slot], P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
-        (void)hipEventRecord(flag_ev[slot], s);
-        ++launched;
+        if (P.chain) phase = (int)((phase + seg) & 1);
+        issued += seg;
+        if (!poll) continue;
+        const int slot = (int)(segs & 1);
+        // the control block the segment's last launch wrote
+        const Ctrl *cdev = phase ? P.ctrl1 : P.ctrl;
+        HIPCHK(hipMemcpyAsync(&hc[slot], cdev, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(ctx->fev[slot], s));
+        ++segs;
         int wait_slot = -1;
-        if (launched == max_chunks) wait_slot = slot;            // last one: wait for it
-        else if (launched >= 2) wait_slot = slot ^ 1;            // the previous chunk
+        if (issued >= total) wait_slot = slot;            // last one: wait for it
+        else if (segs >= 2) wait_slot = slot ^ 1;         // the previous segment
         if (wait_slot >= 0) {
-            if (hipEventSynchronize(flag_ev[wait_slot]) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "event sync failed"); }
+            if (hipEventSynchronize(ctx->fev[wait_slot]) != hipSuccess) return fail(ADMM_E_DEVICE, "event sync failed");
             done = hc[wait_slot].done != 0;
         }
     }
-    // chained: the scalar steps of the last iteration run here
-    if (P.chain && launch_chain_flush(P, s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "flush launch failed"); }
-    (void)hipEventRecord(ctx->ev1, s);
-    if (hipStreamSynchronize(s) != hipSuccess) { cleanup(); return fail(ADMM_E_DEVICE, "stream sync failed"); }
-    cleanup();
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-    if (dev_ms) *dev_ms = ms;
+    // chained: the scalar steps of the last iteration, into slot 0
+    if (P.chain && launch_chain_flush(P, phase, s) != hipSuccess) return fail(ADMM_E_DEVICE, "flush launch failed");
+    HIPCHK(hipEventRecord(ctx->ev1, s));
     return ADMM_OK;
 }
 
@@ -756,6 +836,72 @@ admm_status export_state(admm_context *ctx, const admm_problem *pr, const SolveP
 
 }  // namespace admm
 
+namespace admm {
+
+// The end of a solve or a resumed solve: objective, x out in the caller's
+// memspace and dtype (shape->mem, shape->dtype), the state export, info.
+static admm_status finish_solve(admm_context *ctx, const admm_problem *shape, const SolveParams &P, int dtype,
+                                hipStream_t s, void *x_out, admm_state *state_out, admm_info &inf) {
+    HIPCHK(launch_objective(P, dtype, (double *)ctx->ws.obj.p, s));
+    HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ctx->hctrl + 3, P.rho_cur, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    const size_t E = (size_t)shape->q * shape->m * shape->n;
+    admm_status st;
+    if (shape->mem == ADMM_DEVICE) {
+        HIPCHK(launch_unpack_x(P, dtype, x_out, shape->dtype == ADMM_F64 ? 0 : 1, s));
+    } else {
+        if ((st = ctx->arena.ensure(ctx->ws.staging, E * sizeof(double))) != ADMM_OK) return st;
+        HIPCHK(launch_unpack_x(P, dtype, ctx->ws.staging.p, 0, s));
+        HIPCHK(hipMemcpyAsync(x_out, ctx->ws.staging.p, E * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    const double dev_ms = ms;
+    const Ctrl c = *ctx->hctrl;
+    double rho_fin[4];
+    std::memcpy(rho_fin, (const void *)(ctx->hctrl + 3), sizeof rho_fin);
+    if (c.bad_input & 2) return fail(ADMM_E_DEVICE, "check-iteration schedule out of step");
+    if (state_out && (st = export_state(ctx, shape, P, dtype, c.wdiv, state_out, s)) != ADMM_OK) return st;
+    std::memset(&inf, 0, sizeof inf);
+    for (int k = 0; k < 4; ++k) inf.rho[k] = rho_fin[k];
+    inf.status = c.status == 0 ? ADMM_OK : (c.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
+    inf.iters = c.t;
+    inf.r = c.r;
+    inf.sigma = c.sigma;
+    inf.objective = c.objective;
+    inf.device_ms = dev_ms;
+    if (P.want_codes) {
+        const size_t Ep = (size_t)shape->q * shape->m * P.n_pad;
+        std::vector<uint8_t> codes(Ep);
+        HIPCHK(hipMemcpy(codes.data(), P.codes, Ep, hipMemcpyDeviceToHost));
+        for (size_t r = 0; r < (size_t)shape->q * shape->m; ++r)
+            for (int k = 0; k < shape->n; ++k) {
+                const uint8_t cd = codes[r * P.n_pad + k];
+                if (cd < 15) inf.branch_count[cd]++;
+            }
+    }
+    HIPCHK(hipEventRecord(ctx->join, s));
+    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    // the iterate stays on the device: admm_resume may continue it
+    if (inf.status != ADMM_E_NUMERICAL) {
+        LastSolve &L = ctx->last;
+        L.valid = true;
+        L.P = P;
+        L.dtype = dtype;
+        L.m = shape->m;
+        L.n = shape->n;
+        L.q = shape->q;
+        L.mem = shape->mem;
+        L.out_dtype = shape->dtype;
+        L.t = c.t;
+        L.t_exact = true;
+    }
+    return ADMM_OK;
+}
+
+}  // namespace admm
+
 extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, const admm_settings *settings,
                                   const admm_state *warm, void *x_out, admm_state *state_out, admm_info *info) {
     using clk = std::chrono::steady_clock;
@@ -768,6 +914,7 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     if ((st = validate_problem_shape(pr)) != ADMM_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
+    ctx->last.valid = false;
     hipStream_t s = ctx->own;
     // order after the caller's stream (device inputs may be produced there)
     HIPCHK(hipEventRecord(ctx->join, ctx->user));
@@ -781,51 +928,109 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     } else {
         HIPCHK(launch_cold_init(P, dtype, s));
     }
-    double dev_ms = 0.0;
-    if ((st = iterate(ctx, P, dtype, s, &dev_ms)) != ADMM_OK) return st;
-    HIPCHK(launch_objective(P, dtype, (double *)ctx->ws.obj.p, s));
-    HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(ctx->hctrl + 3, P.rho_cur, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    // x out
-    const size_t E = (size_t)pr->q * pr->m * pr->n;
-    if (pr->mem == ADMM_DEVICE) {
-        HIPCHK(launch_unpack_x(P, dtype, x_out, pr->dtype == ADMM_F64 ? 0 : 1, s));
-    } else {
-        if ((st = ctx->arena.ensure(ctx->ws.staging, E * sizeof(double))) != ADMM_OK) return st;
-        HIPCHK(launch_unpack_x(P, dtype, ctx->ws.staging.p, 0, s));
-        HIPCHK(hipMemcpyAsync(x_out, ctx->ws.staging.p, E * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    const Ctrl c = *ctx->hctrl;
-    double rho_fin[4];
-    std::memcpy(rho_fin, (const void *)(ctx->hctrl + 3), sizeof rho_fin);
-    if (c.bad_input & 2) return fail(ADMM_E_DEVICE, "check-iteration schedule out of step");
-    if (state_out && (st = export_state(ctx, pr, P, dtype, c.wdiv, state_out, s)) != ADMM_OK) return st;
+    if ((st = iterate(ctx, P, dtype, s, 0, true)) != ADMM_OK) return st;
     admm_info inf;
-    std::memset(&inf, 0, sizeof inf);
-    for (int k = 0; k < 4; ++k) inf.rho[k] = rho_fin[k];
-    inf.status = c.status == 0 ? ADMM_OK : (c.status == 2 ? ADMM_MAX_ITER : ADMM_E_NUMERICAL);
-    inf.iters = c.t;
-    inf.r = c.r;
-    inf.sigma = c.sigma;
-    inf.objective = c.objective;
-    inf.device_ms = dev_ms;
-    if (P.want_codes) {
-        const size_t Ep = (size_t)pr->q * pr->m * P.n_pad;
-        std::vector<uint8_t> codes(Ep);
-        HIPCHK(hipMemcpy(codes.data(), P.codes, Ep, hipMemcpyDeviceToHost));
-        for (size_t r = 0; r < (size_t)pr->q * pr->m; ++r)
-            for (int k = 0; k < pr->n; ++k) {
-                const uint8_t cd = codes[r * P.n_pad + k];
-                if (cd < 15) inf.branch_count[cd]++;
-            }
-    }
-    HIPCHK(hipEventRecord(ctx->join, s));
-    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    if ((st = finish_solve(ctx, pr, P, dtype, s, x_out, state_out, inf)) != ADMM_OK) return st;
     inf.total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     if (info) *info = inf;
     if (inf.status == ADMM_E_NUMERICAL) return fail(ADMM_E_NUMERICAL, "residual became NaN");
     return (admm_status)inf.status;
+}
+
+namespace admm {
+
+// Common start of admm_resume / admm_iterate: the record of the solve to
+// continue, with its exact iteration count (read back when an asynchronous
+// continuation left only the planned one).
+static admm_status continue_start(admm_context *ctx, int32_t more_iter, hipStream_t s, LastSolve &L) {
+    if (!ctx->last.valid) return fail(ADMM_E_INVALID_ARG, "no solve to resume on this context");
+    L = ctx->last;
+    if (!L.t_exact) {
+        HIPCHK(hipMemcpyAsync(ctx->hctrl, L.P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        L.t = ctx->hctrl->t;
+        L.t_exact = true;
+        ctx->last = L;
+    }
+    if ((int64_t)L.t + more_iter > INT32_MAX) return fail(ADMM_E_INVALID_ARG, "iteration count overflows");
+    return ADMM_OK;
+}
+
+static admm_problem shape_of(const LastSolve &L) {
+    admm_problem shape;
+    std::memset(&shape, 0, sizeof shape);
+    shape.m = L.m;
+    shape.n = L.n;
+    shape.q = L.q;
+    shape.mem = L.mem;
+    shape.dtype = L.out_dtype;
+    return shape;
+}
+
+}  // namespace admm
+
+extern "C" admm_status admm_resume(admm_context *ctx, int32_t more_iter, double eps_primal, double eps_dual,
+                                   void *x_out, admm_state *state_out, admm_info *info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    if (!x_out) return fail(ADMM_E_INVALID_ARG, "x_out is NULL");
+    if (more_iter < 0) return fail(ADMM_E_INVALID_ARG, "more_iter must be >= 0");
+    if (!(eps_primal >= 0.0) || !(eps_dual >= 0.0))
+        return fail(ADMM_E_INVALID_ARG, "eps_primal and eps_dual must be >= 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->own;
+    HIPCHK(hipEventRecord(ctx->join, ctx->user));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    LastSolve L;
+    admm_status st;
+    if ((st = continue_start(ctx, more_iter, s, L)) != ADMM_OK) return st;
+    ctx->last.valid = false;
+    const SolveParams &P = L.P;
+    std::memset(&ctx->lim, 0, sizeof ctx->lim);
+    ctx->lim.max_iter = L.t + more_iter;
+    ctx->lim.eps_p = eps_primal;
+    ctx->lim.eps_d = eps_dual;
+    // the state rests in slot 0 with nothing pending: running again
+    // (status -1, done 0; the iteration count and residuals stay)
+    HIPCHK(launch_set_run(P, ctx->lim, more_iter > 0 ? 2 : 0, s));
+    if ((st = iterate(ctx, P, L.dtype, s, L.t, true)) != ADMM_OK) return st;
+    const admm_problem shape = shape_of(L);
+    admm_info inf;
+    if ((st = finish_solve(ctx, &shape, P, L.dtype, s, x_out, state_out, inf)) != ADMM_OK) return st;
+    inf.total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (info) *info = inf;
+    if (inf.status == ADMM_E_NUMERICAL) return fail(ADMM_E_NUMERICAL, "residual became NaN");
+    return (admm_status)inf.status;
+}
+
+extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *x_out) {
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    if (more_iter < 0) return fail(ADMM_E_INVALID_ARG, "more_iter must be >= 0");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->own;
+    HIPCHK(hipEventRecord(ctx->join, ctx->user));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    LastSolve L;
+    admm_status st;
+    if ((st = continue_start(ctx, more_iter, s, L)) != ADMM_OK) return st;
+    if (x_out && L.mem != ADMM_DEVICE)
+        return fail(ADMM_E_INVALID_ARG, "x_out of admm_iterate is device memory: the solve's problem was on the host");
+    const SolveParams &P = L.P;
+    ctx->last.valid = false;
+    ctx->lim.max_iter = L.t + more_iter;     // thresholds stay those of the solve
+    // a stop at the old iteration cap runs again; a converged solve stays
+    HIPCHK(launch_set_run(P, ctx->lim, 1, s));
+    if ((st = iterate(ctx, P, L.dtype, s, L.t, false)) != ADMM_OK) return st;
+    if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, L.out_dtype == ADMM_F64 ? 0 : 1, s));
+    HIPCHK(hipEventRecord(ctx->join, s));
+    HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+    L.t += more_iter;          // planned; the device may have stopped earlier
+    L.t_exact = false;
+    ctx->last = L;
+    return ADMM_OK;
 }
 
 // Branch codes of the last x-step, [q][m][n] (debug_branch_codes solves).
@@ -882,6 +1087,7 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
     if (st != ADMM_OK) return st;
     if ((st = validate_problem_shape(pr)) != ADMM_OK) return st;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->last.valid = false;   // the timed launches reuse the workspace
     DeviceGuard g(ctx->device);
     hipStream_t s = ctx->own;
     HIPCHK(hipEventRecord(ctx->join, ctx->user));

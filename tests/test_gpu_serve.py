@@ -221,3 +221,26 @@ def test_warm_keys_across_lanes_and_batched_path():
         assert abs(ia["objective"] - ic["objective"]) <= 1e-5 * (1 + abs(ic["objective"])), key
     cold.close()
     ctx_b.close()
+
+
+def test_overlapping_same_key_requests_stay_valid():
+    """Requests of one key submitted together (so several are in flight at
+    once, some on the batched path and some on the lanes) race for the key's
+    warm state; whichever state a request starts from is a complete earlier
+    iterate, so every result is finite and reaches the cold optimum."""
+    ns = [600, 9000, 700, 8500, 650, 10000, 800, 9500]
+    probs = [W.uniform_problem(2, n, 4500 + r) for r, n in enumerate(ns)]
+    s = settings(precision=admm.F64, eps_primal=1e-6, eps_dual=1e-6)
+    print("[serve] 3 bursts of 8 same-key requests across the lane threshold", flush=True)
+    ctx = admm.Context(0, hbm_budget_bytes=2 << 30)
+    cold = admm.Context(0, hbm_budget_bytes=1 << 30)
+    ref = [cold.solve(p, s)[1]["objective"] for p in probs]
+    cold.close()
+    for burst in range(3):
+        tickets = [ctx.submit(p, s, warm_key=77) for p in probs]
+        for p, t, oref in zip(probs, tickets, ref):
+            x, inf = wait(ctx, t, p)
+            assert inf["status"] == admm.OK, (burst, p.n, inf)
+            assert np.all(np.isfinite(x))
+            assert abs(inf["objective"] - oref) <= 1e-5 * (1 + abs(oref)), (burst, p.n)
+    ctx.close()
