@@ -112,13 +112,18 @@ def run_gpu(args, precision_name):
                              precision=prec, launch=launch)
 
     # warm-up: the problem is staged, started from the cold start and the
-    # first W iterations run, untimed.  The timed region continues that
-    # iterate for exactly K iterations (admm_iterate: queued on the stream
-    # without host round trips, x written to a device tensor at the end),
-    # bracketed by device synchronisations.
+    # first W iterations run, untimed; a first queued run of K iterations
+    # captures the launch graph that such a run replays, and the solve of
+    # W is repeated so that the timed run starts from the same point.  The
+    # timed region continues that iterate for exactly K iterations
+    # (admm_iterate: queued on the stream without host round trips, x
+    # written to a device tensor at the end), bracketed by device
+    # synchronisations.
     w = max(1, args.warmup)
-    ctx.solve(pd, fixed(w))
     xbuf = torch.empty((p.q, p.m, p.n), dtype=tdt, device=pd.f2.device)
+    ctx.solve(pd, fixed(w))
+    ctx.iterate(args.steps, x_out=xbuf)
+    ctx.solve(pd, fixed(w))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.iterate(args.steps, x_out=xbuf)

@@ -249,6 +249,8 @@ admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_proble
  * one request at a time through admm_solve, so their result equals
  * admm_solve's.  Environment, read when serving starts on a context:
  * ADMM_SERVE_BIG_N (8192, 0 = no lanes), ADMM_SERVE_LANES (2),
+ * ADMM_SERVE_MAX_QUEUE (2^20 requests waiting for admission, over the
+ * batched queue and the lanes' queues, before ADMM_E_QUEUE_FULL),
  * ADMM_SERVE_WINDOW (50 iterations per window), ADMM_SERVE_WINDOW_REF (16:
  * requests with m * ceil(n / 256) above it yield after proportionally
  * fewer iterations; 0 = off).  Two requests with the same key in flight at

@@ -616,6 +616,9 @@ struct ServeState {
     uint64_t next_ticket = 1, stamp = 0;
     int dtype = -1;
     int window = 50;
+    // requests queued and not yet admitted (batched queue and lane queues)
+    // beyond which submit answers ADMM_E_QUEUE_FULL
+    size_t max_queue = kServeMaxQueue;
     // per-instance window: window * win_ref / (m * columns per thread) when
     // that is smaller, at least check_every, so one window costs about the
     // same for every resident and a long horizon does not hold the others
@@ -1285,6 +1288,7 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
     ss->dtype = dtype;
     if (const char *e = std::getenv("ADMM_SERVE_WINDOW")) ss->window = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("ADMM_SERVE_WINDOW_REF")) ss->win_ref = std::max(0, std::atoi(e));
+    if (const char *e = std::getenv("ADMM_SERVE_MAX_QUEUE")) ss->max_queue = (size_t)std::max(1L, std::atol(e));
     DeviceGuard g(ctx->device);
     if (hipStreamCreateWithFlags(&ss->s, hipStreamNonBlocking) != hipSuccess) {
         delete ss;
@@ -1401,7 +1405,9 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
         delete r;
         return fail(ADMM_E_DEVICE, "serving worker stopped: " + ss->fail_msg);
     }
-    if (ss->pending.size() >= kServeMaxQueue) {
+    size_t queued = ss->pending.size();
+    for (ServeLane *ln : ss->lanes) queued += ln->q.size();
+    if (queued >= ss->max_queue) {
         delete r;
         return fail(ADMM_E_QUEUE_FULL, "serving queue full");
     }

@@ -43,7 +43,7 @@ struct BatchState;
 struct ServeState;
 extern thread_local std::string g_last_error;
 
-// A captured chunk of `chunk` iterations for one problem layout, starting
+// A captured run of `chunk` iterations for one problem layout, starting
 // at chained-slot parity `phase`.  The kernels read the stop limits from
 // device memory, so the chunk is reused by any later solve of the same
 // shape and buffers whatever its thresholds or iteration cap.
@@ -51,9 +51,13 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     SolveParams P;
     int dtype = -1, chunk = 0, phase = 0;
+    int offset = 0;         // (t - 1) mod check_every of the first launch's iteration t
+    bool flush = false;     // a queued run: cap set first, chained flush and x out after
+    void *xout = nullptr;   // where that run unpacks x (null: nowhere)
+    int xdt = 0;
     uint64_t used = 0;
 };
-constexpr int kGraphCache = 4;
+constexpr int kGraphCache = 8;
 
 // What admm_resume needs of the context's most recent solve.
 struct LastSolve {

@@ -109,6 +109,9 @@ hipError_t launch_cold_init(const SolveParams &P, int dtype, hipStream_t s);
 // Stop limits of the solve into *P.lim; unstop 1 re-runs a solve stopped at
 // its iteration cap, 2 any stopped solve.
 hipError_t launch_set_run(const SolveParams &P, const Lim &v, int unstop, hipStream_t s);
+// The cap to the iterations completed plus `more` (> 0), re-running a solve
+// stopped at its old cap.
+hipError_t launch_set_run_more(const SolveParams &P, int more, hipStream_t s);
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_finalize(const SolveParams &P, hipStream_t s);

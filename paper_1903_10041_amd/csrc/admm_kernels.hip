@@ -1089,10 +1089,12 @@ __global__ __launch_bounds__(kBlock) void k_obj_final(SolveParams P, const doubl
 // the reference for scaling hardware byte counters.
 // Sets the stop limits of a solve and, per `unstop`, lets a stopped solve
 // run again: 1 a stop at the iteration cap, 2 any stop (new thresholds).
-// One thread; the values travel as launch arguments, so nothing on the host
-// has to outlive the call.
-__global__ void k_set_run(Ctrl *ctrl, Lim *lim, Lim v, int unstop) {
-    *lim = v;
+// With more > 0 the cap is relative: the iterations completed so far plus
+// `more` (the thresholds stay).  One thread; the values travel as launch
+// arguments, so nothing on the host has to outlive the call.
+__global__ void k_set_run(Ctrl *ctrl, Lim *lim, Lim v, int unstop, int more) {
+    if (more > 0) lim->max_iter = ctrl->t + more;
+    else *lim = v;
     if (unstop == 2 || (unstop == 1 && ctrl->status == 2)) {
         ctrl->status = -1;
         ctrl->done = 0;
@@ -1100,7 +1102,13 @@ __global__ void k_set_run(Ctrl *ctrl, Lim *lim, Lim v, int unstop) {
 }
 
 hipError_t launch_set_run(const SolveParams &P, const Lim &v, int unstop, hipStream_t s) {
-    k_set_run<<<1, 1, 0, s>>>(P.ctrl, const_cast<Lim *>(P.lim), v, unstop);
+    k_set_run<<<1, 1, 0, s>>>(P.ctrl, const_cast<Lim *>(P.lim), v, unstop, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_run_more(const SolveParams &P, int more, hipStream_t s) {
+    const Lim v{};
+    k_set_run<<<1, 1, 0, s>>>(P.ctrl, const_cast<Lim *>(P.lim), v, 1, more);
     return hipGetLastError();
 }
 

@@ -669,10 +669,11 @@ static int direct_chunks() {
     return v;
 }
 
-static GraphEntry *graph_find(admm_context *ctx, const SolveParams &P, int dtype, int chunk, int phase) {
+static GraphEntry *graph_find(admm_context *ctx, const SolveParams &P, int dtype, int chunk, int phase,
+                              int offset, bool flush, void *xout = nullptr, int xdt = 0) {
     for (GraphEntry &g : ctx->graphs)
-        if (g.exec && g.dtype == dtype && g.chunk == chunk && g.phase == phase &&
-            std::memcmp(&g.P, &P, sizeof P) == 0) {
+        if (g.exec && g.dtype == dtype && g.chunk == chunk && g.phase == phase && g.offset == offset &&
+            g.flush == flush && g.xout == xout && g.xdt == xdt && std::memcmp(&g.P, &P, sizeof P) == 0) {
             g.used = ++ctx->graph_clock;
             return &g;
         }
@@ -685,37 +686,51 @@ static hipError_t launch_one(const SolveParams &P, int dtype, long t, int rs, hi
     return P.chain ? launch_chain(P, dtype, check, rs, s) : launch_iteration(P, dtype, check, s);
 }
 
-// Capture `chunk` launches starting at a multiple of check_every at slot
-// parity `phase`, instantiate, and keep the result in the cache.
+// Capture `chunk` launches whose first one runs an iteration t with
+// (t - 1) mod check_every == offset, at slot parity `phase`, instantiate,
+// and keep the result in the cache in place of the least recently used
+// entry.  With `flush` (a queued run, admm_iterate) the graph also sets the
+// iteration cap to `chunk` more than the count so far first, and ends with
+// the chained flush and, if xout is given, the unpack of x into it (dtype
+// xdt: 0 double, 1 float).
 static admm_status graph_build(admm_context *ctx, const SolveParams &P, int dtype, int chunk, int phase,
-                               hipStream_t s, GraphEntry **out) {
+                               int offset, bool flush, hipStream_t s, GraphEntry **out,
+                               void *xout = nullptr, int xdt = 0) {
     GraphEntry *g = &ctx->graphs[0];
     for (GraphEntry &e : ctx->graphs)
         if (!e.exec || e.used < g->used) { g = &e; if (!e.exec) break; }
     if (g->exec) { (void)hipGraphExecDestroy(g->exec); g->exec = nullptr; }
     hipGraph_t gr;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < chunk; ++c) {
-        hipError_t e = launch_one(P, dtype, c + 1, (c + phase) & 1, s);
-        if (e != hipSuccess) {
-            hipGraph_t junk = nullptr;
-            (void)hipStreamEndCapture(s, &junk);
-            if (junk) (void)hipGraphDestroy(junk);
-            return fail(ADMM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
-        }
+    hipError_t e = flush ? launch_set_run_more(P, chunk, s) : hipSuccess;
+    for (int c = 0; c < chunk && e == hipSuccess; ++c) e = launch_one(P, dtype, offset + c + 1, (c + phase) & 1, s);
+    if (e == hipSuccess && flush && P.chain) e = launch_chain_flush(P, (chunk + phase) & 1, s);
+    if (e == hipSuccess && flush && xout) e = launch_unpack_x(P, dtype, xout, xdt, s);
+    if (e != hipSuccess) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(s, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        return fail(ADMM_E_DEVICE, std::string("capture: ") + hipGetErrorString(e));
     }
     HIPCHK(hipStreamEndCapture(s, &gr));
-    hipError_t e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0);
     (void)hipGraphDestroy(gr);
     if (e != hipSuccess) { g->exec = nullptr; return fail(ADMM_E_DEVICE, "graph instantiate failed"); }
     g->P = P;
     g->dtype = dtype;
     g->chunk = chunk;
     g->phase = phase;
+    g->offset = offset;
+    g->flush = flush;
+    g->xout = xout;
+    g->xdt = xdt;
     g->used = ++ctx->graph_clock;
     *out = g;
     return ADMM_OK;
 }
+
+// Longest run of queued iterations (admm_iterate) captured as one graph.
+constexpr long kSpanMax = 200;
 
 // Run the iteration from iteration t0 until the device stop flag is set or
 // the limit ctx->lim.max_iter is reached.  Launches go out in segments:
@@ -747,9 +762,9 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
             seg = std::min<long>(rem, ce - t % ce);
         } else if (rem >= chunk) {
             seg = chunk;
-            g = graph_find(ctx, P, dtype, chunk, phase);
+            g = graph_find(ctx, P, dtype, chunk, phase, 0, false);
             if (!g && direct_used >= direct_chunks()) {
-                admm_status st = graph_build(ctx, P, dtype, chunk, phase, s, &g);
+                admm_status st = graph_build(ctx, P, dtype, chunk, phase, 0, false, s, &g);
                 if (st != ADMM_OK) return st;
             }
             if (!g) ++direct_used;
@@ -1021,10 +1036,22 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
     const SolveParams &P = L.P;
     ctx->last.valid = false;
     ctx->lim.max_iter = L.t + more_iter;     // thresholds stay those of the solve
-    // a stop at the old iteration cap runs again; a converged solve stays
-    HIPCHK(launch_set_run(P, ctx->lim, 1, s));
-    if ((st = iterate(ctx, P, L.dtype, s, L.t, false)) != ADMM_OK) return st;
-    if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, L.out_dtype == ADMM_F64 ? 0 : 1, s));
+    const int xdt = L.out_dtype == ADMM_F64 ? 0 : 1;
+    if (!P.persistent && more_iter > 0 && more_iter <= kSpanMax) {
+        // the whole run as one graph (cap, launches, flush, x out), kept
+        // for the next run of the same length from the same point of the
+        // check cadence into the same output
+        const int off = L.t % P.check_every;
+        GraphEntry *gr = graph_find(ctx, P, L.dtype, more_iter, 0, off, true, x_out, xdt);
+        if (!gr && (st = graph_build(ctx, P, L.dtype, more_iter, 0, off, true, s, &gr, x_out, xdt)) != ADMM_OK)
+            return st;
+        if (hipGraphLaunch(gr->exec, s) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
+    } else {
+        // a stop at the old iteration cap runs again; a converged solve stays
+        HIPCHK(launch_set_run(P, ctx->lim, 1, s));
+        if ((st = iterate(ctx, P, L.dtype, s, L.t, false)) != ADMM_OK) return st;
+        if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, xdt, s));
+    }
     HIPCHK(hipEventRecord(ctx->join, s));
     HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
     L.t += more_iter;          // planned; the device may have stopped earlier

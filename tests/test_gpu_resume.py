@@ -184,3 +184,29 @@ def test_iterate_leaves_a_converged_solve_stopped():
     assert i0["status"] == admm.OK and i1["status"] == admm.OK
     assert i1["iters"] == i0["iters"]
     assert np.array_equal(x0, x1)
+
+
+@pytest.mark.parametrize("name", ["c1-chained", "robust_q5-chained", "c1-split"])
+def test_iterate_long_run_and_repeat(name):
+    """A queued run longer than one captured span (issued as aligned chunks
+    without waiting), and the same queued run twice from the same point
+    (the second replays the cached graph): the bits of one solve."""
+    mk, launch = CASES[name]
+    p = mk()
+    ctx = admm.Context(0)
+    try:
+        x_ref, i_ref, _ = ctx.solve(p, fixed(p, 5 + 450, launch=launch))
+        x20, _, _ = ctx.solve(p, fixed(p, 25, launch=launch))
+        for _ in range(2):
+            ctx.solve(p, fixed(p, 5, launch=launch))
+            ctx.iterate(20)
+            x, i, _ = ctx.resume(0)
+            assert i["iters"] == 25 and np.array_equal(x, x20)
+        ctx.solve(p, fixed(p, 5, launch=launch))
+        ctx.iterate(450)
+        x, i, _ = ctx.resume(0)
+    finally:
+        ctx.close()
+    say(f"[iterate-long] {name}: iters {i['iters']} vs {i_ref['iters']}")
+    assert i["iters"] == i_ref["iters"] == 455
+    assert np.array_equal(x, x_ref)
