@@ -229,6 +229,25 @@ admm_status admm_resume(admm_context *ctx, int32_t more_iter, double eps_primal,
  * launch path waits for each of its launches.  Errors as admm_resume. */
 admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *x_out);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): admm_solve of a cold start for a
+ * problem in device memory (mem == ADMM_DEVICE; x_out device memory of the
+ * problem's dtype), with every buffer of the solve cut from a static
+ * device array of 64 MiB that the library holds on each device it runs on
+ * until the process ends.  The call allocates nothing: no hipMalloc,
+ * hipFree or graph instantiation (its iterations are issued as direct
+ * launches).  Results equal admm_solve's for the same problem and
+ * settings.  The array is shared by all contexts on a device and keeps the
+ * last call's contents; the library runs one such call at a time per
+ * device (host lock), and device work queued by other means that overlaps
+ * a call races with it.  Errors: ADMM_E_OUT_OF_BUDGET when the solve
+ * needs more than the 64 MiB (about m n q = 2.8e6 elements in FP32
+ * storage, half that in FP64), ADMM_E_INVALID_ARG for host arrays,
+ * ADMM_E_UNSUPPORTED for debug_branch_codes; otherwise as admm_solve.
+ * No warm start, no state export, and admm_resume does not continue it. */
+admm_status admm_solve_noalloc(admm_context *ctx, const admm_problem *prob,
+                               const admm_settings *settings, void *x_out, admm_info *info);
+
 /* Solve `count` independent instances of different shapes in one persistent
  * launch.  All problems share one memspace and dtype.  warm may be NULL
  * (all cold).  x_out[b] is instance b's [q][m][n] output.  infos: [count].

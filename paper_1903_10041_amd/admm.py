@@ -94,6 +94,7 @@ def lib():
             "admm_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "admm_resume": (C.c_int, [vp, i32, C.c_double, C.c_double, vp, vp, vp]),
             "admm_iterate": (C.c_int, [vp, i32, vp]),
+            "admm_solve_noalloc": (C.c_int, [vp, vp, vp, vp, vp]),
             "admm_solve_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
             "admm_submit": (C.c_int, [vp, vp, vp, u64, C.POINTER(u64)]),
             "admm_poll": (C.c_int, [vp, u64, vp, vp]),
@@ -357,6 +358,25 @@ class Context:
             st_out["lam"] = st_out["lambda_"]
         return x_out, info_dict(inf), st_out
 
+
+    def solve_noalloc(self, prob, settings: Optional[Settings] = None, x_out=None):
+        """admm_solve_noalloc: a cold-start solve of a problem in device
+        memory whose buffers come from the library's static scratch array.
+        Returns (x, info dict)."""
+        mp = _Marshal(prob)
+        if not mp.device:
+            raise TypeError("admm_solve_noalloc takes device arrays")
+        import torch
+        if x_out is None:
+            x_out = torch.empty((prob.q, prob.m, prob.n), dtype=prob.f2.dtype, device=prob.f2.device)
+        s = settings.to_c() if settings else None
+        inf = admm_info()
+        self.set_stream(torch.cuda.current_stream(prob.f2.device).cuda_stream)
+        st = lib().admm_solve_noalloc(self.h, C.byref(mp.st), C.byref(s) if s is not None else None,
+                                      x_out.data_ptr(), C.byref(inf))
+        _check(st)
+        self._last = None
+        return x_out, info_dict(inf)
 
     def iterate(self, more_iter: int, x_out=None):
         """admm_iterate: queue at most ``more_iter`` further iterations of the

@@ -32,6 +32,14 @@ struct Arena {
     void release(DevBuf &b);
 };
 
+// Buffers cut in turn from one fixed device region (the no-allocation
+// entry point's static scratch array).
+struct Carve {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+    admm_status take(DevBuf &b, size_t bytes);
+};
+
 struct Workspace {
     DevBuf coef, g0, f0, y, blo, bhi, x, w, codes, scal, part, ctrl, obj, staging;
     std::vector<DevBuf *> all() {
@@ -104,12 +112,15 @@ admm_status validate_problem_shape(const admm_problem *p);
 int finalize_group(int m, int q, int nblk, int threads);
 int sweep_cpt(int n, int q);
 int persist_columns(admm_context *ctx, int dtype, int m, int n, int q);
+// Layout and buffers of one solve; fills P.  Buffers come from the
+// context's workspace, or (Wc, cv given) into Wc from the carve.
 admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settings *s, SolveParams &P,
-                    int &dtype);
+                    int &dtype, Workspace *Wc = nullptr, Carve *cv = nullptr);
 admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
                           hipStream_t s);
 admm_status upload_limits(admm_context *ctx, const SolveParams &P, hipStream_t s);
-admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll);
+admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll,
+                    bool graphs = true);
 
 void batch_release(admm_context *ctx);
 void serve_shutdown(admm_context *ctx);

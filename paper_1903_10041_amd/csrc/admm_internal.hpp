@@ -13,6 +13,9 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPad = 64;             // n is padded to a multiple of this
 constexpr int kChainBlock = 1024;    // threads per block of the chained iteration
 constexpr int kChainMaxBlocks = 512; // largest grid the chained iteration takes
+constexpr int kMaxSources = 8;       // largest m any kernel takes
+// Bytes of the static scratch array of the no-allocation entry point.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
 
 // Device-resident control block of one solve (one instance).
 struct Ctrl {

@@ -1125,7 +1125,7 @@ hipError_t launch_copy_calib(const void *src, void *dst, size_t bytes, hipStream
 
 // ------------------------------------------------------------ launchers
 
-int max_m_supported() { return 8; }
+int max_m_supported() { return kMaxSources; }
 
 template <typename T, int MODE, int CPT, bool CHECK, int FEAT>
 static void launch_sweep_c(const SolveParams &P, hipStream_t s) {

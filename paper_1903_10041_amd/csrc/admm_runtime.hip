@@ -64,6 +64,50 @@ void Arena::release(DevBuf &b) {
     b.bytes = 0;
 }
 
+admm_status Carve::take(DevBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    if (used + bytes > cap)
+        return fail(ADMM_E_OUT_OF_BUDGET, "the problem needs more than the " + std::to_string(cap >> 20) +
+                                              " MiB of static scratch of admm_solve_noalloc");
+    b.p = base + used;
+    b.bytes = bytes;
+    used += bytes;
+    return ADMM_OK;
+}
+
+}  // namespace admm
+
+// Static scratch of admm_solve_noalloc: every buffer of its solve is cut
+// from this array, so the call allocates nothing.  Each device holds its
+// own copy, at its own address, for the life of the process.  In host code
+// `scratch` only names the symbol; its device address on a device comes from
+// hipGetSymbolAddress, taken once per device when a context is created
+// there (scratch_setup) and kept in g_scratch.
+static __device__ __align__(256) unsigned char scratch[admm::kScratchBytes];
+
+namespace admm {
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_use[kMaxDevices];   // one no-allocation solve at a time per device
+}  // namespace
+
+// With `device` current: its address of the scratch array, looked up once.
+static admm_status scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(ADMM_E_INVALID_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return ADMM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(ADMM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[device] = ptr;
+    return ADMM_OK;
+}
+
 }  // namespace admm
 
 // ------------------------------------------------------------- validation
@@ -183,6 +227,10 @@ extern "C" admm_status admm_create(admm_context **out, int device, size_t budget
         hipHostMalloc((void **)&ctx->hctrl, 6 * sizeof(Ctrl), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
         return fail(ADMM_E_DEVICE, "stream/event/pinned allocation failed");
+    }
+    if ((st = scratch_setup(device)) != ADMM_OK) {
+        admm_destroy(ctx);
+        return st;
     }
     int coop = 0, ncu = 0;
     (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
@@ -337,8 +385,8 @@ int finalize_group(int m, int q, int nblk, int threads) {
 
 // Layout and buffers of one solve; fills P.
 admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settings *s, SolveParams &P,
-                    int &dtype) {
-    Workspace &W = ctx->ws;
+                    int &dtype, Workspace *Wc, Carve *cv) {
+    Workspace &W = Wc ? *Wc : ctx->ws;
     Arena &A = ctx->arena;
     dtype = (int)s->precision;   // 0 F64, 1 F32_MIXED, 2 F32 (float storage for 1 and 2)
     const size_t T = dtype == 0 ? 8 : 4;
@@ -421,7 +469,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.band_lo = s->band_lo;
     P.wdiv = 1.0;
     admm_status st;
-#define ENS(buf, bytes) if ((st = A.ensure(buf, bytes)) != ADMM_OK) return st
+#define ENS(buf, bytes) if ((st = cv ? cv->take(buf, bytes) : A.ensure(buf, bytes)) != ADMM_OK) return st
     ENS(W.coef, E * 4 * T);
     ENS(W.x, E * T);
     ENS(W.y, K * T);
@@ -465,20 +513,23 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
                           hipStream_t s) {
     const int m = pr->m, n = pr->n, q = pr->q;
     const size_t E = (size_t)q * m * n;
-    std::vector<double> slo(m), shi(m);
+    // fixed-size host arrays (m <= kMaxSources): staging allocates nothing
+    // for problems in device memory
+    double slo[kMaxSources] = {}, shi[kMaxSources] = {};
     const int src_dtype = pr->mem == ADMM_HOST ? 0 : (pr->dtype == ADMM_F64 ? 0 : 1);
     const size_t ST = src_dtype == 0 ? 8 : 4;
+    if (m > kMaxSources) return fail(ADMM_E_UNSUPPORTED, "too many sources");
     if (pr->bounds == ADMM_BOUNDS_PER_SOURCE) {
         if (pr->mem == ADMM_HOST) {
-            std::memcpy(slo.data(), pr->x_lo, m * sizeof(double));
-            std::memcpy(shi.data(), pr->x_hi, m * sizeof(double));
+            std::memcpy(slo, pr->x_lo, m * sizeof(double));
+            std::memcpy(shi, pr->x_hi, m * sizeof(double));
         } else {
-            std::vector<char> a(m * ST), b(m * ST);
-            HIPCHK(hipMemcpy(a.data(), pr->x_lo, m * ST, hipMemcpyDeviceToHost));
-            HIPCHK(hipMemcpy(b.data(), pr->x_hi, m * ST, hipMemcpyDeviceToHost));
+            double a[kMaxSources], b[kMaxSources];
+            HIPCHK(hipMemcpy(a, pr->x_lo, m * ST, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(b, pr->x_hi, m * ST, hipMemcpyDeviceToHost));
             for (int i = 0; i < m; ++i) {
-                slo[i] = ST == 8 ? ((double *)a.data())[i] : ((float *)a.data())[i];
-                shi[i] = ST == 8 ? ((double *)b.data())[i] : ((float *)b.data())[i];
+                slo[i] = ST == 8 ? a[i] : ((const float *)a)[i];
+                shi[i] = ST == 8 ? b[i] : ((const float *)b)[i];
             }
             for (int i = 0; i < m; ++i)
                 if (!std::isfinite(slo[i]) || !std::isfinite(shi[i]) || slo[i] > shi[i])
@@ -486,15 +537,12 @@ admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const Solve
         }
         if (dtype != 0)
             for (int i = 0; i < m; ++i) { slo[i] = (double)(float)slo[i]; shi[i] = (double)(float)shi[i]; }
-    } else {
-        std::fill(slo.begin(), slo.end(), 0.0);
-        std::fill(shi.begin(), shi.end(), 0.0);
     }
-    std::vector<double> hb(3 * (size_t)m);
-    std::memcpy(hb.data(), slo.data(), m * sizeof(double));
-    std::memcpy(hb.data() + m, shi.data(), m * sizeof(double));
-    std::memcpy(hb.data() + 2 * m, pr->c, m * sizeof(double));
-    HIPCHK(hipMemcpyAsync((void *)P.slo, hb.data(), 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
+    double hb[3 * kMaxSources];
+    std::memcpy(hb, slo, m * sizeof(double));
+    std::memcpy(hb + m, shi, m * sizeof(double));
+    std::memcpy(hb + 2 * m, pr->c, m * sizeof(double));
+    HIPCHK(hipMemcpyAsync((void *)P.slo, hb, 3 * m * sizeof(double), hipMemcpyHostToDevice, s));
     const double rho0[8] = {P.rho1, P.rho2, P.rho3, P.rho4, P.rho1, P.rho2, P.rho3, P.rho4};
     HIPCHK(hipMemcpyAsync(P.rho_cur, rho0, sizeof rho0, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(P.ctrl, 0, sizeof(Ctrl) + 16, s));
@@ -741,9 +789,11 @@ constexpr long kSpanMax = 200;
 // the control block and the host waits for the one before last (two
 // segments in flight), so it stops issuing soon after the device stops;
 // without, everything is issued at once (launches after a stop do
-// nothing).  On the chained path the state ends in slot 0 (the flush).
+// nothing).  Without `graphs` every launch is a direct one (no capture, no
+// instantiation).  On the chained path the state ends in slot 0 (the flush).
 // Returns with the work queued behind ctx->ev0 .. ctx->ev1 on `s`.
-admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll) {
+admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll,
+                    bool graphs) {
     const long total = std::max(0L, (long)ctx->lim.max_iter - t0);
     if (P.persistent) return iterate_persistent(ctx, P, dtype, s, total);
     const int ce = P.check_every;
@@ -762,8 +812,8 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
             seg = std::min<long>(rem, ce - t % ce);
         } else if (rem >= chunk) {
             seg = chunk;
-            g = graph_find(ctx, P, dtype, chunk, phase, 0, false);
-            if (!g && direct_used >= direct_chunks()) {
+            g = graphs ? graph_find(ctx, P, dtype, chunk, phase, 0, false) : nullptr;
+            if (!g && graphs && direct_used >= direct_chunks()) {
                 admm_status st = graph_build(ctx, P, dtype, chunk, phase, 0, false, s, &g);
                 if (st != ADMM_OK) return st;
             }
@@ -856,8 +906,9 @@ namespace admm {
 // The end of a solve or a resumed solve: objective, x out in the caller's
 // memspace and dtype (shape->mem, shape->dtype), the state export, info.
 static admm_status finish_solve(admm_context *ctx, const admm_problem *shape, const SolveParams &P, int dtype,
-                                hipStream_t s, void *x_out, admm_state *state_out, admm_info &inf) {
-    HIPCHK(launch_objective(P, dtype, (double *)ctx->ws.obj.p, s));
+                                hipStream_t s, void *x_out, admm_state *state_out, admm_info &inf,
+                                double *obj_scratch = nullptr, bool keep = true) {
+    HIPCHK(launch_objective(P, dtype, obj_scratch ? obj_scratch : (double *)ctx->ws.obj.p, s));
     HIPCHK(hipMemcpyAsync(ctx->hctrl, P.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(ctx->hctrl + 3, P.rho_cur, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     const size_t E = (size_t)shape->q * shape->m * shape->n;
@@ -899,7 +950,7 @@ static admm_status finish_solve(admm_context *ctx, const admm_problem *shape, co
     HIPCHK(hipEventRecord(ctx->join, s));
     HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
     // the iterate stays on the device: admm_resume may continue it
-    if (inf.status != ADMM_E_NUMERICAL) {
+    if (keep && inf.status != ADMM_E_NUMERICAL) {
         LastSolve &L = ctx->last;
         L.valid = true;
         L.P = P;
@@ -946,6 +997,51 @@ extern "C" admm_status admm_solve(admm_context *ctx, const admm_problem *pr, con
     if ((st = iterate(ctx, P, dtype, s, 0, true)) != ADMM_OK) return st;
     admm_info inf;
     if ((st = finish_solve(ctx, pr, P, dtype, s, x_out, state_out, inf)) != ADMM_OK) return st;
+    inf.total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    if (info) *info = inf;
+    if (inf.status == ADMM_E_NUMERICAL) return fail(ADMM_E_NUMERICAL, "residual became NaN");
+    return (admm_status)inf.status;
+}
+
+extern "C" admm_status admm_solve_noalloc(admm_context *ctx, const admm_problem *pr,
+                                          const admm_settings *settings, void *x_out, admm_info *info) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    if (!x_out) return fail(ADMM_E_INVALID_ARG, "x_out is NULL");
+    admm_settings S = settings ? *settings : ctx->defaults;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    if ((st = validate_problem_shape(pr)) != ADMM_OK) return st;
+    if (pr->mem != ADMM_DEVICE)
+        return fail(ADMM_E_INVALID_ARG, "admm_solve_noalloc takes a problem in device memory");
+    if (S.debug_branch_codes) return fail(ADMM_E_UNSUPPORTED, "admm_solve_noalloc records no branch codes");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    char *base = (char *)g_scratch[ctx->device];
+    if (!base) return fail(ADMM_E_DEVICE, "the scratch array of this device was not set up");
+    // the array is shared by every context on the device: one solve at a time
+    std::lock_guard<std::mutex> su(g_scratch_use[ctx->device]);
+    ctx->last.valid = false;
+    hipStream_t s = ctx->own;
+    HIPCHK(hipEventRecord(ctx->join, ctx->user));
+    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    Carve cv;
+    cv.base = base;
+    cv.cap = kScratchBytes;
+    Workspace W;
+    DevBuf obj;
+    SolveParams P;
+    int dtype = 0;
+    if ((st = prepare(ctx, pr, &S, P, dtype, &W, &cv)) != ADMM_OK) return st;
+    if ((st = cv.take(obj, 1024 * sizeof(double))) != ADMM_OK) return st;
+    if ((st = stage_problem(ctx, pr, P, dtype, s)) != ADMM_OK) return st;
+    HIPCHK(launch_cold_init(P, dtype, s));
+    // direct launches only: capturing and instantiating a graph allocates
+    if ((st = iterate(ctx, P, dtype, s, 0, true, false)) != ADMM_OK) return st;
+    admm_info inf;
+    if ((st = finish_solve(ctx, pr, P, dtype, s, x_out, nullptr, inf, (double *)obj.p, false)) != ADMM_OK)
+        return st;
     inf.total_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     if (info) *info = inf;
     if (inf.status == ADMM_E_NUMERICAL) return fail(ADMM_E_NUMERICAL, "residual became NaN");
