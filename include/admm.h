@@ -249,13 +249,51 @@ admm_status admm_solve_noalloc(admm_context *ctx, const admm_problem *prob,
                                const admm_settings *settings, void *x_out, admm_info *info);
 
 /* Solve `count` independent instances of different shapes in one persistent
- * launch.  All problems share one memspace and dtype.  warm may be NULL
+ * launch: the instances' cold starts and persistent queue kernels (one per
+ * kernel variant of the batch plan, each on a stream of its own) and the
+ * unpack of x are one captured graph, replayed by later calls on the same
+ * buffers with the same variant counts.  All problems share one memspace and dtype.  warm may be NULL
  * (all cold).  x_out[b] is instance b's [q][m][n] output.  infos: [count].
  * Returns ADMM_OK if every instance converged, ADMM_MAX_ITER if some hit
  * max_iter, or the first error. */
 admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
                              const admm_settings *settings, const admm_state *const *warm,
                              void *const *x_out, admm_info *infos);
+
+/* Kernel plan of the batched path (admm_solve_batch and the serving
+ * windows): each instance of program (1) runs as one block of 256 threads,
+ * or as a single wave of 64 threads, chosen per source class (m <= 2, <= 4,
+ * <= 8) and horizon bucket (n <= 64, 128, 256, 512, 1024, 2048, beyond).
+ * wave[c * 7 + b] = 1 selects the single wave for class c, bucket b.  The
+ * default is the 256-thread block everywhere; a context created with the
+ * environment variable ADMM_BATCH_PLAN naming a plan file starts from it.
+ * The plan changes the order of the block reductions, so results are
+ * deterministic for a given plan and may differ at rounding level between
+ * plans.
+ *
+ * admm_tune_batch: the autotuner, in two timed stages.  First, for every
+ * (class, bucket) the given instances occupy, it times the batched kernels
+ * on up to 64 of them, repeated to fill the device, for `iters` iterations
+ * with no early stop, once with each block size (best of three runs).
+ * Second, starting from the context's plan, it switches the buckets whose
+ * single wave measured at least 3% faster one at a time (largest expected
+ * saving first) and keeps a switch only if the device time of the whole
+ * batch, solved with `settings`, falls by more than 1% (best of two runs).
+ * It installs the result on the context and, if json_path is not NULL,
+ * writes it there as JSON ("wave" rows, the per-bucket nanoseconds per
+ * instance-iteration and the batch times).  ns_out (may be NULL): 44
+ * doubles, [2][3][7] block then wave timings (0 for empty buckets), then
+ * the batch's device milliseconds under the starting and the tuned plan.
+ * Instances outside the batched kernels (q > 1, f0/g0, per-step bounds)
+ * are ignored.
+ * admm_set_batch_plan: install wave[21] (entries 0 or 1), or, if json_path
+ * is not NULL, the plan read from that file.  admm_get_batch_plan: the
+ * context's plan into wave[21]. */
+admm_status admm_tune_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
+                            const admm_settings *settings, int32_t iters, const char *json_path,
+                            double *ns_out);
+admm_status admm_set_batch_plan(admm_context *ctx, const uint8_t *wave, const char *json_path);
+admm_status admm_get_batch_plan(admm_context *ctx, uint8_t *wave);
 
 /* Serving.  submit copies the problem (host memory only) and returns a
  * ticket at once; the instance is admitted to the device when a slot and

@@ -95,6 +95,9 @@ def lib():
             "admm_resume": (C.c_int, [vp, i32, C.c_double, C.c_double, vp, vp, vp]),
             "admm_iterate": (C.c_int, [vp, i32, vp]),
             "admm_solve_noalloc": (C.c_int, [vp, vp, vp, vp, vp]),
+            "admm_tune_batch": (C.c_int, [vp, i32, vp, vp, i32, C.c_char_p, vp]),
+            "admm_set_batch_plan": (C.c_int, [vp, vp, C.c_char_p]),
+            "admm_get_batch_plan": (C.c_int, [vp, vp]),
             "admm_solve_batch": (C.c_int, [vp, i32, vp, vp, vp, vp, vp]),
             "admm_submit": (C.c_int, [vp, vp, vp, u64, C.POINTER(u64)]),
             "admm_poll": (C.c_int, [vp, u64, vp, vp]),
@@ -530,6 +533,53 @@ def _solve_batch(ctx, probs, settings=None, x_outs=None):
     st = lib().admm_solve_batch(ctx.h, n, arr, C.byref(s) if s is not None else None, None, ptrs, infos)
     _check(st)
     return x_outs, [info_dict(infos[i]) for i in range(n)]
+
+
+PLAN_CLASSES, PLAN_BUCKETS = 3, 7
+
+
+def tune_batch(ctx: "Context", probs, settings: Optional[Settings] = None, iters: int = 40,
+               json_path: Optional[str] = None):
+    """admm_tune_batch on a BatchPack or a list of problems: times both block
+    sizes per (source class, horizon bucket), installs the plan on the
+    context and writes it to ``json_path`` (if given).  Returns (plan as a
+    3 x 7 uint8 array, timings as a 2 x 3 x 7 array of nanoseconds per
+    instance-iteration (block, then wave), and the batch's device ms under
+    the starting and the tuned plan)."""
+    s = settings.to_c() if settings else None
+    ns = np.zeros(2 * PLAN_CLASSES * PLAN_BUCKETS + 2)
+    if isinstance(probs, BatchPack):
+        recs, count, dev = probs.recs_c, probs.count, probs.device
+        tdev = probs.torch_device
+    else:
+        ms = [_Marshal(p) for p in probs]
+        recs = (admm_problem * max(1, len(ms)))(*[m.st for m in ms])
+        count, dev = len(ms), bool(ms) and ms[0].device
+        tdev = probs[0].f2.device if dev else None
+    if dev:
+        import torch
+        ctx.set_stream(torch.cuda.current_stream(tdev).cuda_stream)
+    _check(lib().admm_tune_batch(ctx.h, count, recs, C.byref(s) if s is not None else None, int(iters),
+                                 json_path.encode() if json_path else None, ns.ctypes.data), allow=(OK,))
+    k = 2 * PLAN_CLASSES * PLAN_BUCKETS
+    return get_batch_plan(ctx), ns[:k].reshape(2, PLAN_CLASSES, PLAN_BUCKETS), (float(ns[k]), float(ns[k + 1]))
+
+
+def get_batch_plan(ctx: "Context") -> np.ndarray:
+    w = np.zeros(PLAN_CLASSES * PLAN_BUCKETS, dtype=np.uint8)
+    _check(lib().admm_get_batch_plan(ctx.h, w.ctypes.data), allow=(OK,))
+    return w.reshape(PLAN_CLASSES, PLAN_BUCKETS)
+
+
+def set_batch_plan(ctx: "Context", wave=None, json_path: Optional[str] = None):
+    """Install a batch plan (3 x 7 of 0/1) or the plan of a JSON file."""
+    if json_path is not None:
+        _check(lib().admm_set_batch_plan(ctx.h, None, json_path.encode()), allow=(OK,))
+        return
+    w = np.ascontiguousarray(np.asarray(wave, dtype=np.uint8).reshape(-1))
+    if w.size != PLAN_CLASSES * PLAN_BUCKETS:
+        raise ValueError("a batch plan has 3 x 7 entries")
+    _check(lib().admm_set_batch_plan(ctx.h, w.ctypes.data, None), allow=(OK,))
 
 
 def admm_solve_batch(ctx: "Context", probs, settings: Optional[Settings] = None, x_outs=None):

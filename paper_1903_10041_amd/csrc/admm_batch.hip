@@ -4,6 +4,8 @@
 #include "admm_host.hpp"
 
 #include <algorithm>
+#include <cctype>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -61,6 +63,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_pack(BatchParams B, const Pack
     }
 }
 
+// Clears n counters (a kernel rather than a memset, so that a captured
+// graph holds no memset node).
+__global__ void k_zero_i32(int32_t *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 template <typename T, typename D>
 __global__ __launch_bounds__(kBlock) void k_batch_unpack(BatchParams B, D *const *dst) {
     for (int b = blockIdx.x; b < B.count; b += gridDim.x) {
@@ -76,49 +84,76 @@ __global__ __launch_bounds__(kBlock) void k_batch_unpack(BatchParams B, D *const
 
 // Grid of a batch kernel: all resident blocks, no more than the queue.
 template <typename K>
-static int batch_grid(admm_context *ctx, K kernel, int count) {
+static int batch_grid(admm_context *ctx, K kernel, int threads, int count) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
     return std::max(1, std::min(count, nb * std::max(1, ctx->num_cu)));
 }
 
+template <typename T, int MAXM, int MIXED>
+static void launch_batch_m(admm_context *ctx, bool wave, const BatchParams &B, bool init, hipStream_t s) {
+    if (init) k_batch_init<T, MAXM><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
+    if (wave) k_batch<T, MAXM, MIXED, 64><<<batch_grid(ctx, k_batch<T, MAXM, MIXED, 64>, 64, B.count), 64, 0, s>>>(B);
+    else k_batch<T, MAXM, MIXED, kBlock><<<batch_grid(ctx, k_batch<T, MAXM, MIXED, kBlock>, kBlock, B.count), kBlock,
+                                           0, s>>>(B);
+}
+
 template <typename T, int MIXED>
-static hipError_t launch_batch_class(admm_context *ctx, int cls, const BatchParams &B, bool init, hipStream_t s) {
+static hipError_t launch_batch_variant(admm_context *ctx, int v, const BatchParams &B, bool init, hipStream_t s) {
     if (B.count == 0) return hipSuccess;
-    if (cls == 0) {
-        if (init) k_batch_init<T, 2><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
-        k_batch<T, 2, MIXED><<<batch_grid(ctx, k_batch<T, 2, MIXED>, B.count), kBlock, 0, s>>>(B);
-    } else if (cls == 1) {
-        if (init) k_batch_init<T, 4><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
-        k_batch<T, 4, MIXED><<<batch_grid(ctx, k_batch<T, 4, MIXED>, B.count), kBlock, 0, s>>>(B);
-    } else {
-        if (init) k_batch_init<T, 8><<<std::min(B.count, 4096), kBlock, 0, s>>>(B);
-        k_batch<T, 8, MIXED><<<batch_grid(ctx, k_batch<T, 8, MIXED>, B.count), kBlock, 0, s>>>(B);
-    }
+    const int cls = variant_class(v);
+    const bool wave = variant_wave(v);
+    if (cls == 0) launch_batch_m<T, 2, MIXED>(ctx, wave, B, init, s);
+    else if (cls == 1) launch_batch_m<T, 4, MIXED>(ctx, wave, B, init, s);
+    else launch_batch_m<T, 8, MIXED>(ctx, wave, B, init, s);
     return hipGetLastError();
 }
 
-hipError_t launch_batch(admm_context *ctx, int dtype, int cls, const BatchParams &B, bool init, hipStream_t s) {
-    if (dtype == 0) return launch_batch_class<double, MODE_F64>(ctx, cls, B, init, s);
-    if (dtype == 1) return launch_batch_class<float, MODE_MIXED>(ctx, cls, B, init, s);
-    return launch_batch_class<float, MODE_F32>(ctx, cls, B, init, s);
+hipError_t launch_batch(admm_context *ctx, int dtype, int v, const BatchParams &B, bool init, hipStream_t s) {
+    if (dtype == 0) return launch_batch_variant<double, MODE_F64>(ctx, v, B, init, s);
+    if (dtype == 1) return launch_batch_variant<float, MODE_MIXED>(ctx, v, B, init, s);
+    return launch_batch_variant<float, MODE_F32>(ctx, v, B, init, s);
 }
 
 int batch_class(int m) { return m <= 2 ? 0 : (m <= 4 ? 1 : 2); }
 
+int batch_bucket(int n) {
+    int b = 0;
+    while (b < kPlanBuckets - 1 && n > kPlanBucketTop[b]) ++b;
+    return b;
+}
+
+// Kernel variant of an instance: its source class, and one wave per
+// instance where the plan says so for its horizon.
+int batch_variant(const admm_context *ctx, int m, int n) {
+    const int c = batch_class(m);
+    return c + (ctx->plan.wave[c][batch_bucket(n)] ? kClasses : 0);
+}
+
+// Key of the captured pipeline of a batched call: what its launches read.
+struct BatchGraphKey {
+    int dtype, out_dtype, cnt, window;
+    int count[kVariants];
+    const void *bufs[10];
+    bool operator==(const BatchGraphKey &o) const { return std::memcmp(this, &o, sizeof *this) == 0; }
+};
+
 struct BatchState {
     DevBuf coef, x, y, w, pool, inst, order, next, bad, src, stage, outp;
-    hipStream_t cs[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t cs[kVariants] = {};
+    hipEvent_t ev[kVariants + 1] = {};
+    hipGraphExec_t gexec = nullptr;   // the last call's pipeline, replayed while the key holds
+    BatchGraphKey gkey;
 };
 
 static admm_status batch_state(admm_context *ctx, BatchState *&bs) {
     if (!ctx->batch) {
         bs = new BatchState();
-        for (int c = 0; c < 3; ++c)
+        std::memset(&bs->gkey, 0, sizeof bs->gkey);
+        for (int c = 0; c < kVariants; ++c)
             if (hipStreamCreateWithFlags(&bs->cs[c], hipStreamNonBlocking) != hipSuccess)
                 return fail(ADMM_E_DEVICE, "stream creation failed");
-        for (int e = 0; e < 4; ++e)
+        for (int e = 0; e < kVariants + 1; ++e)
             if (hipEventCreateWithFlags(&bs->ev[e], hipEventDisableTiming) != hipSuccess)
                 return fail(ADMM_E_DEVICE, "event creation failed");
         ctx->batch = bs;
@@ -133,6 +168,7 @@ void batch_release(admm_context *ctx) {
     for (DevBuf *b : {&bs->coef, &bs->x, &bs->y, &bs->w, &bs->pool, &bs->inst, &bs->order, &bs->next, &bs->bad,
                       &bs->src, &bs->stage, &bs->outp})
         ctx->arena.release(*b);
+    if (bs->gexec) (void)hipGraphExecDestroy(bs->gexec);
     for (auto s : bs->cs)
         if (s) (void)hipStreamDestroy(s);
     for (auto e : bs->ev)
@@ -205,8 +241,8 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
     ENS(bs->w, K * T);
     ENS(bs->pool, PO * sizeof(double));
     ENS(bs->inst, cnt * sizeof(BInst));
-    ENS(bs->order, 3 * (size_t)cnt * sizeof(int32_t));
-    ENS(bs->next, 4 * sizeof(int32_t));
+    ENS(bs->order, kVariants * (size_t)cnt * sizeof(int32_t));
+    ENS(bs->next, 8 * sizeof(int32_t));
     ENS(bs->bad, cnt * sizeof(int32_t));
     ENS(bs->src, cnt * sizeof(PackSrc) + cnt * sizeof(void *));
     if (host) ENS(bs->stage, SRC * sizeof(double));
@@ -282,31 +318,18 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
             return fail(ADMM_E_INVALID_ARG, "batch instance " + std::to_string(idx[b]) +
                                                 ": arrays must be finite, with f2, g2 >= 0 and x_lo <= x_hi");
 
-    // per-class queues, longest first (work ~ m n^2: iterations grow with n)
-    std::vector<int32_t> order[3];
-    for (int b = 0; b < cnt; ++b) order[batch_class(inst[b].m)].push_back(b);
+    // per-variant queues, longest first (work ~ m n^2: iterations grow with n)
+    std::vector<int32_t> order[kVariants];
+    for (int b = 0; b < cnt; ++b) order[batch_variant(ctx, inst[b].m, inst[b].n)].push_back(b);
     for (auto &o : order)
         std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
             return (double)inst[a].m * inst[a].n * inst[a].n > (double)inst[b].m * inst[b].n * inst[b].n;
         });
-    std::vector<int32_t> ord_all(3 * (size_t)cnt, 0);
-    for (int c = 0; c < 3; ++c) std::copy(order[c].begin(), order[c].end(), ord_all.begin() + (size_t)c * cnt);
-    BCHK(hipMemcpyAsync(bs->order.p, ord_all.data(), 3 * (size_t)cnt * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    BCHK(hipMemsetAsync(bs->next.p, 0, 4 * sizeof(int32_t), s));
-    BCHK(hipEventRecord(bs->ev[0], s));
-    BCHK(hipEventRecord(ctx->ev0, s));
-    for (int c = 0; c < 3; ++c) {
-        if (order[c].empty()) continue;
-        BCHK(hipStreamWaitEvent(bs->cs[c], bs->ev[0], 0));
-        BatchParams Bc = B;
-        Bc.order = (const int32_t *)bs->order.p + (size_t)c * cnt;
-        Bc.count = (int)order[c].size();
-        Bc.next = (int32_t *)bs->next.p + c;
-        BCHK(launch_batch(ctx, dtype, c, Bc, true, bs->cs[c]));
-        BCHK(hipEventRecord(bs->ev[1 + c], bs->cs[c]));
-        BCHK(hipStreamWaitEvent(s, bs->ev[1 + c], 0));
-    }
-    BCHK(hipEventRecord(ctx->ev1, s));
+    std::vector<int32_t> ord_all(kVariants * (size_t)cnt, 0);
+    for (int v = 0; v < kVariants; ++v)
+        std::copy(order[v].begin(), order[v].end(), ord_all.begin() + (size_t)v * cnt);
+    BCHK(hipMemcpyAsync(bs->order.p, ord_all.data(), kVariants * (size_t)cnt * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s));
     // outputs
     std::vector<void *> dst(cnt);
     if (host) {
@@ -321,11 +344,59 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
     void **dst_dev = (void **)((char *)bs->src.p + cnt * sizeof(PackSrc));
     BCHK(hipMemcpyAsync(dst_dev, dst.data(), cnt * sizeof(void *), hipMemcpyHostToDevice, s));
     const int out_dtype = host ? 0 : src_dtype;
-    if (dtype == 0 && out_dtype == 0) k_batch_unpack<double, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
-    else if (dtype == 0) k_batch_unpack<double, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
-    else if (out_dtype == 0) k_batch_unpack<float, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
-    else k_batch_unpack<float, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
-    BCHK(hipGetLastError());
+    // The pipeline (queue heads zeroed, each variant's cold start and
+    // persistent kernel on a stream of its own, the unpack after all of
+    // them) is captured once as a graph and replayed by later calls whose
+    // launches read the same buffers with the same counts.
+    BatchGraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.dtype = dtype;
+    key.out_dtype = out_dtype;
+    key.cnt = cnt;
+    key.window = B.window;
+    for (int v = 0; v < kVariants; ++v) key.count[v] = (int)order[v].size();
+    const void *kb[10] = {bs->coef.p, bs->x.p, bs->y.p, bs->w.p, bs->pool.p, bs->inst.p,
+                          bs->order.p, bs->next.p, bs->src.p, (const void *)dst_dev};
+    std::memcpy(key.bufs, kb, sizeof kb);
+    if (!bs->gexec || !(bs->gkey == key)) {
+        if (bs->gexec) { (void)hipGraphExecDestroy(bs->gexec); bs->gexec = nullptr; }
+        hipGraph_t gr = nullptr;
+        BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        k_zero_i32<<<1, 64, 0, s>>>((int32_t *)bs->next.p, 8);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(bs->ev[0], s);
+        for (int v = 0; v < kVariants && e == hipSuccess; ++v) {
+            if (order[v].empty()) continue;
+            BatchParams Bv = B;
+            Bv.order = (const int32_t *)bs->order.p + (size_t)v * cnt;
+            Bv.count = (int)order[v].size();
+            Bv.next = (int32_t *)bs->next.p + v;
+            e = hipStreamWaitEvent(bs->cs[v], bs->ev[0], 0);
+            if (e == hipSuccess) e = launch_batch(ctx, dtype, v, Bv, true, bs->cs[v]);
+            if (e == hipSuccess) e = hipEventRecord(bs->ev[1 + v], bs->cs[v]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, bs->ev[1 + v], 0);
+        }
+        if (e == hipSuccess) {
+            if (dtype == 0 && out_dtype == 0) k_batch_unpack<double, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
+            else if (dtype == 0) k_batch_unpack<double, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
+            else if (out_dtype == 0) k_batch_unpack<float, double><<<pg, kBlock, 0, s>>>(B, (double *const *)dst_dev);
+            else k_batch_unpack<float, float><<<pg, kBlock, 0, s>>>(B, (float *const *)dst_dev);
+            e = hipGetLastError();
+        }
+        const hipError_t ec = hipStreamEndCapture(s, &gr);
+        if (e == hipSuccess) e = ec;
+        if (e == hipSuccess) e = hipGraphInstantiate(&bs->gexec, gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+            bs->gexec = nullptr;
+            return fail(ADMM_E_DEVICE, std::string("batched pipeline capture: ") + hipGetErrorString(e));
+        }
+        bs->gkey = key;
+    }
+    BCHK(hipEventRecord(ctx->ev0, s));
+    BCHK(hipGraphLaunch(bs->gexec, s));
+    BCHK(hipEventRecord(ctx->ev1, s));
     std::vector<BInst> fin(cnt);
     BCHK(hipMemcpyAsync(fin.data(), bs->inst.p, cnt * sizeof(BInst), hipMemcpyDeviceToHost, s));
     std::vector<double> hout;
@@ -363,9 +434,247 @@ static admm_status solve_batch_core(admm_context *ctx, const admm_problem *probs
     return ADMM_OK;
 }
 
+// ------------------------------------------------------------ the tuner
+//
+// The plan file: {"format": "admm-batch-plan-1", ..., "wave": [[7 ints] x 3]}
+// (class rows m <= 2, <= 4, <= 8; bucket columns n <= 64 .. beyond 2048;
+// 1 = one wave per instance).  Only the "wave" rows are read back.
+
+admm_status plan_load_file(admm_context *ctx, const char *path) {
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ADMM_E_INVALID_ARG, std::string("cannot open batch plan ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    const size_t at = txt.find("\"wave\"");
+    if (at == std::string::npos) return fail(ADMM_E_INVALID_ARG, std::string("no \"wave\" table in ") + path);
+    BatchPlan p;
+    int got_n = 0;
+    for (size_t i = at + 6; i < txt.size() && got_n < kClasses * kPlanBuckets; ++i) {
+        const char ch = txt[i];
+        if (ch == '0' || ch == '1') {
+            if (i + 1 < txt.size() && std::isdigit((unsigned char)txt[i + 1]))
+                return fail(ADMM_E_INVALID_ARG, std::string("batch plan entries are 0 or 1: ") + path);
+            p.wave[got_n / kPlanBuckets][got_n % kPlanBuckets] = (uint8_t)(ch - '0');
+            ++got_n;
+        } else if (std::isdigit((unsigned char)ch)) {
+            return fail(ADMM_E_INVALID_ARG, std::string("batch plan entries are 0 or 1: ") + path);
+        }
+    }
+    if (got_n != kClasses * kPlanBuckets)
+        return fail(ADMM_E_INVALID_ARG, std::string("batch plan needs 3 rows of 7 entries: ") + path);
+    ctx->plan = p;
+    return ADMM_OK;
+}
+
+static bool plan_write_file(const char *path, const BatchPlan &p, const admm_settings &S, int iters,
+                            const double (*ns)[kClasses][kPlanBuckets], const double *batch_ms) {
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return false;
+    std::fprintf(f, "{\n  \"format\": \"admm-batch-plan-1\",\n  \"arch\": \"gfx950\",\n  \"precision\": %d,\n"
+                    "  \"iters\": %d,\n  \"bucket_top\": [",
+                 (int)S.precision, iters);
+    for (int b = 0; b < kPlanBuckets - 1; ++b) std::fprintf(f, "%s%d", b ? ", " : "", kPlanBucketTop[b]);
+    std::fprintf(f, "],\n  \"wave\": [");
+    for (int c = 0; c < kClasses; ++c) {
+        std::fprintf(f, "%s[", c ? ", " : "");
+        for (int b = 0; b < kPlanBuckets; ++b) std::fprintf(f, "%s%d", b ? ", " : "", (int)p.wave[c][b]);
+        std::fprintf(f, "]");
+    }
+    std::fprintf(f, "],\n  \"ns_per_instance_iteration\": {");
+    for (int w = 0; w < 2; ++w) {
+        std::fprintf(f, "%s\"%s\": [", w ? ", " : "", w ? "wave" : "block");
+        for (int c = 0; c < kClasses; ++c) {
+            std::fprintf(f, "%s[", c ? ", " : "");
+            for (int b = 0; b < kPlanBuckets; ++b) std::fprintf(f, "%s%.1f", b ? ", " : "", ns[w][c][b]);
+            std::fprintf(f, "]");
+        }
+        std::fprintf(f, "]");
+    }
+    std::fprintf(f, "},\n  \"batch_device_ms\": {\"start\": %.4f, \"tuned\": %.4f}\n}\n", batch_ms[0],
+                 batch_ms[1]);
+    return std::fclose(f) == 0;
+}
+
 }  // namespace admm
 
 using namespace admm;
+
+extern "C" admm_status admm_tune_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
+                                       const admm_settings *settings, int32_t iters, const char *json_path,
+                                       double *ns_out) {
+    if (!ctx || (count > 0 && !probs)) return fail(ADMM_E_INVALID_ARG, "NULL argument");
+    if (count < 0 || iters < 1 || iters > 10000) return fail(ADMM_E_INVALID_ARG, "count >= 0 and iters in [1, 10000]");
+    admm_settings S = settings ? *settings : ctx->defaults;
+    admm_status st = validate_settings(&S);
+    if (st != ADMM_OK) return st;
+    for (int b = 0; b < count; ++b) {
+        if ((st = validate_problem_shape(&probs[b])) != ADMM_OK)
+            return fail(st, "batch instance " + std::to_string(b) + ": " + g_last_error);
+        if (probs[b].mem != probs[0].mem || (probs[b].mem == ADMM_DEVICE && probs[b].dtype != probs[0].dtype))
+            return fail(ADMM_E_INVALID_ARG, "all batch instances must share one memspace and dtype");
+    }
+    // fixed work: iters iterations, no early stop
+    S.max_iter = iters;
+    S.eps_primal = 0.0;
+    S.eps_dual = 0.0;
+    S.adaptive_rho = 0;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    ctx->last.valid = false;
+    std::vector<int> groups[kClasses][kPlanBuckets];
+    for (int b = 0; b < count; ++b)
+        if (batchable(probs[b])) groups[batch_class(probs[b].m)][batch_bucket(probs[b].n)].push_back(b);
+    const BatchPlan saved = ctx->plan;
+    BatchPlan result = saved;
+    double ns[2][kClasses][kPlanBuckets] = {};
+    const bool dev = count > 0 && probs[0].mem == ADMM_DEVICE;
+    const size_t T = dev ? (probs[0].dtype == ADMM_F64 ? 8 : 4) : 8;
+    // enough instances to fill the device several times over, so that each
+    // variant is measured at its throughput, not at one instance's latency
+    const int target = std::max(256, 8 * std::max(1, ctx->num_cu));
+    DevBuf dout;
+    std::vector<double> hout;
+    for (int c = 0; c < kClasses; ++c)
+        for (int bk = 0; bk < kPlanBuckets; ++bk) {
+            const std::vector<int> &ids = groups[c][bk];
+            if (ids.empty()) continue;
+            // at most 64 distinct instances, spread over the group, repeated
+            std::vector<int> pick;
+            const int np = std::min<int>(64, (int)ids.size());
+            for (int i = 0; i < np; ++i) pick.push_back(ids[(size_t)i * ids.size() / np]);
+            std::vector<admm_problem> tp;
+            while ((int)tp.size() < target)
+                for (int i : pick) tp.push_back(probs[i]);
+            const int cnt = (int)tp.size();
+            size_t out_elems = 0;
+            for (const admm_problem &p : tp) out_elems += (size_t)p.m * p.n;
+            std::vector<void *> xo(cnt);
+            if (dev) {
+                if ((st = ctx->arena.ensure(dout, out_elems * T)) != ADMM_OK) { ctx->arena.release(dout); ctx->plan = saved; return st; }
+                size_t o = 0;
+                for (int b = 0; b < cnt; ++b) { xo[b] = (char *)dout.p + o * T; o += (size_t)tp[b].m * tp[b].n; }
+            } else {
+                hout.resize(out_elems);
+                size_t o = 0;
+                for (int b = 0; b < cnt; ++b) { xo[b] = hout.data() + o; o += (size_t)tp[b].m * tp[b].n; }
+            }
+            std::vector<admm_info> inf(cnt);
+            std::vector<int> all(cnt);
+            std::iota(all.begin(), all.end(), 0);
+            for (int w = 0; w < 2; ++w) {
+                ctx->plan.wave[c][bk] = (uint8_t)w;
+                double best = INFINITY;
+                for (int rep = 0; rep < 3; ++rep) {
+                    if ((st = solve_batch_core(ctx, tp.data(), all, S, xo.data(), inf.data())) != ADMM_OK) {
+                        ctx->arena.release(dout);
+                        ctx->plan = saved;
+                        return st;
+                    }
+                    best = std::min(best, inf[0].device_ms);
+                }
+                ns[w][c][bk] = best * 1e6 / ((double)cnt * iters);
+            }
+            ctx->plan = saved;
+        }
+    ctx->arena.release(dout);
+    // Second stage, on the batch itself with the caller's settings: the
+    // buckets whose single wave measured faster are switched one at a time,
+    // largest expected saving first, and a switch is kept only if the whole
+    // batch's device time falls by more than 1% (the kernels of different
+    // variants share the device, so a bucket's own throughput does not
+    // settle the makespan).
+    std::vector<int> all_b;
+    for (int b = 0; b < count; ++b)
+        if (batchable(probs[b])) all_b.push_back(b);
+    double batch_ms[2] = {0.0, 0.0};
+    if (!all_b.empty()) {
+        S = settings ? *settings : ctx->defaults;
+        S.adaptive_rho = 0;
+        std::vector<void *> xo(count, nullptr);
+        size_t out_elems = 0;
+        for (int b : all_b) out_elems += (size_t)probs[b].m * probs[b].n;
+        if (dev && (st = ctx->arena.ensure(dout, out_elems * T)) != ADMM_OK) { ctx->plan = saved; return st; }
+        if (!dev) hout.resize(out_elems);
+        size_t o = 0;
+        for (int b : all_b) {
+            xo[b] = dev ? (void *)((char *)dout.p + o * T) : (void *)(hout.data() + o);
+            o += (size_t)probs[b].m * probs[b].n;
+        }
+        std::vector<admm_info> inf(count);
+        auto timed = [&](const BatchPlan &pl, double &ms) -> admm_status {
+            ctx->plan = pl;
+            ms = INFINITY;
+            for (int rep = 0; rep < 2; ++rep) {
+                admm_status e = solve_batch_core(ctx, probs, all_b, S, xo.data(), inf.data());
+                if (e != ADMM_OK) return e;
+                ms = std::min(ms, inf[all_b[0]].device_ms);
+            }
+            return ADMM_OK;
+        };
+        BatchPlan cur = saved;
+        double cur_ms;
+        if ((st = timed(cur, cur_ms)) != ADMM_OK) { ctx->arena.release(dout); ctx->plan = saved; return st; }
+        batch_ms[0] = cur_ms;
+        std::vector<std::pair<double, int>> cand;   // (expected saving, c * buckets + b)
+        for (int c = 0; c < kClasses; ++c)
+            for (int bk = 0; bk < kPlanBuckets; ++bk) {
+                const double gain = (ns[0][c][bk] - ns[1][c][bk]) * (double)groups[c][bk].size();
+                const bool want = ns[1][c][bk] < 0.97 * ns[0][c][bk];
+                if (!groups[c][bk].empty() && want != (cur.wave[c][bk] != 0))
+                    cand.push_back({want ? gain : -gain, c * kPlanBuckets + bk});
+            }
+        std::sort(cand.begin(), cand.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+        for (const auto &cd : cand) {
+            BatchPlan trial = cur;
+            const int c = cd.second / kPlanBuckets, bk = cd.second % kPlanBuckets;
+            trial.wave[c][bk] ^= 1;
+            double ms;
+            if ((st = timed(trial, ms)) != ADMM_OK) { ctx->arena.release(dout); ctx->plan = saved; return st; }
+            if (ms < 0.99 * cur_ms) { cur = trial; cur_ms = ms; }
+        }
+        batch_ms[1] = cur_ms;
+        result = cur;
+        ctx->arena.release(dout);
+    }
+    ctx->plan = result;
+    if (ns_out) {
+        for (int w = 0; w < 2; ++w)
+            for (int c = 0; c < kClasses; ++c)
+                for (int bk = 0; bk < kPlanBuckets; ++bk) ns_out[(w * kClasses + c) * kPlanBuckets + bk] = ns[w][c][bk];
+        ns_out[2 * kClasses * kPlanBuckets] = batch_ms[0];
+        ns_out[2 * kClasses * kPlanBuckets + 1] = batch_ms[1];
+    }
+    if (json_path && !plan_write_file(json_path, result, S, iters, ns, batch_ms))
+        return fail(ADMM_E_INVALID_ARG, std::string("cannot write the batch plan to ") + json_path);
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_set_batch_plan(admm_context *ctx, const uint8_t *wave, const char *json_path) {
+    if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (json_path) return plan_load_file(ctx, json_path);
+    if (!wave) return fail(ADMM_E_INVALID_ARG, "give a plan table or a plan file");
+    BatchPlan p;
+    for (int c = 0; c < kClasses; ++c)
+        for (int b = 0; b < kPlanBuckets; ++b) {
+            const uint8_t v = wave[c * kPlanBuckets + b];
+            if (v > 1) return fail(ADMM_E_INVALID_ARG, "batch plan entries are 0 or 1");
+            p.wave[c][b] = v;
+        }
+    ctx->plan = p;
+    return ADMM_OK;
+}
+
+extern "C" admm_status admm_get_batch_plan(admm_context *ctx, uint8_t *wave) {
+    if (!ctx || !wave) return fail(ADMM_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int c = 0; c < kClasses; ++c)
+        for (int b = 0; b < kPlanBuckets; ++b) wave[c * kPlanBuckets + b] = ctx->plan.wave[c][b];
+    return ADMM_OK;
+}
 
 extern "C" admm_status admm_solve_batch(admm_context *ctx, int32_t count, const admm_problem *probs,
                                         const admm_settings *settings, const admm_state *const *warm,
@@ -761,8 +1070,8 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
     };
     Arena &A = ctx->arena;
     if (A.ensure(ss->inst, std::max<size_t>(1, na) * sizeof(BInst)) != ADMM_OK ||
-        A.ensure(ss->order, 3 * std::max<size_t>(1, na) * sizeof(int32_t)) != ADMM_OK ||
-        A.ensure(ss->next, 4 * sizeof(int32_t)) != ADMM_OK) {
+        A.ensure(ss->order, kVariants * std::max<size_t>(1, na) * sizeof(int32_t)) != ADMM_OK ||
+        A.ensure(ss->next, 8 * sizeof(int32_t)) != ADMM_OK) {
         serve_fail(ss, "serving descriptors do not fit the budget");
         return false;
     }
@@ -916,25 +1225,25 @@ static bool serve_cycle(admm_context *ctx, ServeState *ss) {
     // window's readback, fresh ones start running); the kernel skips any
     // whose start left another status (max_iter = 0), so the order needs
     // no readback of the descriptors.
-    std::vector<int32_t> order[3];
+    std::vector<int32_t> order[kVariants];
     for (int a = 0; a < na; ++a)
-        if (insts[a].status != -1000) order[batch_class(insts[a].m)].push_back(a);
+        if (insts[a].status != -1000) order[batch_variant(ctx, insts[a].m, insts[a].n)].push_back(a);
     for (auto &o : order)
         std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
             return (double)insts[a].m * insts[a].n > (double)insts[b].m * insts[b].n;
         });
-    std::vector<int32_t> ord_all(3 * (size_t)std::max(1, na), 0);
-    for (int c = 0; c < 3; ++c) std::copy(order[c].begin(), order[c].end(), ord_all.begin() + (size_t)c * na);
+    std::vector<int32_t> ord_all(kVariants * (size_t)std::max(1, na), 0);
+    for (int v = 0; v < kVariants; ++v) std::copy(order[v].begin(), order[v].end(), ord_all.begin() + (size_t)v * na);
     if (!dev_ok(hipMemcpyAsync(ss->order.p, ord_all.data(), ord_all.size() * sizeof(int32_t), hipMemcpyHostToDevice, s), "upload") ||
-        !dev_ok(hipMemsetAsync(ss->next.p, 0, 4 * sizeof(int32_t), s), "memset"))
+        !dev_ok(hipMemsetAsync(ss->next.p, 0, 8 * sizeof(int32_t), s), "memset"))
         return false;
-    for (int c = 0; c < 3; ++c) {
-        if (order[c].empty()) continue;
+    for (int v = 0; v < kVariants; ++v) {
+        if (order[v].empty()) continue;
         BatchParams Bc = B;
-        Bc.order = (const int32_t *)ss->order.p + (size_t)c * na;
-        Bc.count = (int)order[c].size();
-        Bc.next = (int32_t *)ss->next.p + c;
-        if (!dev_ok(launch_batch(ctx, dtype, c, Bc, false, s), "window")) return false;
+        Bc.order = (const int32_t *)ss->order.p + (size_t)v * na;
+        Bc.count = (int)order[v].size();
+        Bc.next = (int32_t *)ss->next.p + v;
+        if (!dev_ok(launch_batch(ctx, dtype, v, Bc, false, s), "window")) return false;
     }
     std::vector<BInst> after(na);
     if (!dev_ok(hipMemcpyAsync(after.data(), ss->inst.p, na * sizeof(BInst), hipMemcpyDeviceToHost, s), "readback") ||

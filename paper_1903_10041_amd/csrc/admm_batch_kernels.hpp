@@ -105,14 +105,27 @@ __device__ __forceinline__ void inst_pointers(const BatchParams &B, const BInst 
 }
 
 // Sum over the block of m values per thread, result in out[i] (LDS).
-template <int MAXM>
-__device__ __forceinline__ void block_sum_rows(int m, const double *v, double (*lds)[kBlock], double *out) {
+// NT = 256 (four waves): through LDS, each wave reducing whole rows; NT = 64
+// (one wave): the wave's DPP reduction of each row, no LDS round trip.
+template <int MAXM, int NT = kBlock>
+__device__ __forceinline__ void block_sum_rows(int m, const double *v, double (*lds)[NT], double *out) {
+    static_assert(NT == 64 || NT == 256, "one or four waves per block");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (NT == 64) {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+            if (i < m) {
+                const double a = wave_sum(v[i]);
+                if (lane == 0) out[i] = a;
+            }
+        __syncthreads();
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MAXM; ++i)
         if (i < m) lds[i][tid] = v[i];
     __syncthreads();
-    for (int i = wv; i < m; i += kWaves) {
+    for (int i = wv; i < m; i += NT / 64) {
         double a = (lds[i][lane] + lds[i][lane + 64]) + (lds[i][lane + 128] + lds[i][lane + 192]);
         a = wave_sum(a);
         if (lane == 0) out[i] = a;
@@ -121,15 +134,26 @@ __device__ __forceinline__ void block_sum_rows(int m, const double *v, double (*
 }
 
 // Max over the block of `rows` values per thread (rows <= MAXM + 2).
-template <int MAXM>
-__device__ __forceinline__ void block_max_rows(int rows, const double *v, double (*lds)[kBlock], double *out,
+template <int MAXM, int NT = kBlock>
+__device__ __forceinline__ void block_max_rows(int rows, const double *v, double (*lds)[NT], double *out,
                                                bool negate) {
+    static_assert(NT == 64 || NT == 256, "one or four waves per block");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (NT == 64) {
+#pragma unroll
+        for (int i = 0; i < MAXM + 2; ++i)
+            if (i < rows) {
+                const double a = wave_max(negate ? -v[i] : v[i]);
+                if (lane == 0) out[i] = negate ? -a : a;
+            }
+        __syncthreads();
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < MAXM + 2; ++i)
         if (i < rows) lds[i][tid] = negate ? -v[i] : v[i];
     __syncthreads();
-    for (int i = wv; i < rows; i += kWaves) {
+    for (int i = wv; i < rows; i += NT / 64) {
         double a = fmax(fmax(lds[i][lane], lds[i][lane + 64]), fmax(lds[i][lane + 128], lds[i][lane + 192]));
         a = wave_max(a);
         if (lane == 0) out[i] = negate ? -a : a;
@@ -162,11 +186,15 @@ __device__ __forceinline__ BInst uniform_inst(const BInst &I) {
 
 // Occupancy: with the descriptor uniform and the per-source scalars read
 // from LDS, the classes m <= 2 and m <= 4 fit 3 and 2 waves per SIMD
-// without spills; m <= 8 is held to 2 waves (256 registers).
-template <typename T, int MAXM, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 2 ? 3 : 2)))
+// without spills; m <= 8 is held to 2 waves (256 registers).  NT is the
+// block (instance) size: 256 threads, or one wave for short horizons, where
+// four waves would leave most lanes idle and pay block barriers for little
+// work.  The reduction trees differ with NT, so the bits of a result depend
+// on the NT chosen for its (m, n) (the plan is a function of m and n only).
+template <typename T, int MAXM, int MODE, int NT = kBlock>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(MAXM <= 2 ? 3 : 2)))
 void k_batch(BatchParams B) {
-    __shared__ double lds[MAXM + 2][kBlock];
+    __shared__ double lds[MAXM + 2][NT];
     __shared__ double s_lam[MAXM], s_zoff[MAXM], s_h[MAXM], s_p[MAXM], s_cap[MAXM], s_lo[MAXM], s_hi[MAXM];
     __shared__ double s_sum[MAXM], s_max[MAXM + 2], s_min[MAXM];
     __shared__ double s_r, s_sg;
@@ -223,7 +251,7 @@ void k_batch(BatchParams B) {
             Acc<MAXM> acc;
             acc.reset();
             if (check) {
-                for (int k = tid; k < n; k += kBlock) {
+                for (int k = tid; k < n; k += NT) {
                     asm volatile("" ::: "memory");
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
@@ -231,7 +259,7 @@ void k_batch(BatchParams B) {
                     col_store(P, 0, k, d);
                 }
             } else {
-                for (int k = tid; k < n; k += kBlock) {
+                for (int k = tid; k < n; k += NT) {
                     asm volatile("" ::: "memory");
                     Col<T, MAXM> d;
                     col_load(P, 0, k, d);
@@ -239,7 +267,7 @@ void k_batch(BatchParams B) {
                     col_store(P, 0, k, d);
                 }
             }
-            block_sum_rows<MAXM>(m, acc.gsum, lds, s_sum);
+            block_sum_rows<MAXM, NT>(m, acc.gsum, lds, s_sum);
             if (check) {
                 // rows: dg-max of each source, then the demand and s-x
                 // residual maxima
@@ -249,11 +277,11 @@ void k_batch(BatchParams B) {
                     const double dm = i < MAXM ? acc.dgmax[i < MAXM ? i : 0] : 0.0;
                     vv[i] = i < m ? dm : (i == m ? acc.rdem : (i == m + 1 ? acc.sig3 : 0.0));
                 }
-                block_max_rows<MAXM>(m + 2, vv, lds, s_max, false);
+                block_max_rows<MAXM, NT>(m + 2, vv, lds, s_max, false);
                 double vm[MAXM + 2];
 #pragma unroll
                 for (int i = 0; i < MAXM + 2; ++i) vm[i] = i < MAXM ? acc.dgmin[i < MAXM ? i : 0] : 0.0;
-                block_max_rows<MAXM>(m, vm, lds, s_min, true);
+                block_max_rows<MAXM, NT>(m, vm, lds, s_min, true);
             }
             // scalar steps (7b)+(7g), (7d)+(7i) for each source, residuals
             if (tid < m) {
@@ -307,7 +335,7 @@ void k_batch(BatchParams B) {
             double o = 0.0;
             const V4<T> *cf = (const V4<T> *)P.coef;
             const T *X = (const T *)P.x;
-            for (int e = tid; e < m * P.n_pad; e += kBlock) {
+            for (int e = tid; e < m * P.n_pad; e += NT) {
                 const int k = e % P.n_pad;
                 if (k < n) {
                     const double xv = (double)X[e];
@@ -317,7 +345,7 @@ void k_batch(BatchParams B) {
             double ov[MAXM];
 #pragma unroll
             for (int i = 0; i < MAXM; ++i) ov[i] = i == 0 ? o : 0.0;
-            block_sum_rows<MAXM>(1, ov, lds, s_sum);
+            block_sum_rows<MAXM, NT>(1, ov, lds, s_sum);
         }
         if (tid == 0) {
             I.t = s_t;

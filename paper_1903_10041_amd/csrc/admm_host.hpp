@@ -67,6 +67,21 @@ struct GraphEntry {
 };
 constexpr int kGraphCache = 8;
 
+// Kernel plan of the batched path: per source class (m <= 2, <= 4, <= 8)
+// and horizon bucket (n <= 64, 128, 256, 512, 1024, 2048, beyond), whether
+// an instance runs on one wave (64 threads) rather than a block of four.
+// Default: four waves everywhere; admm_tune_batch measures and sets it, or
+// it is read from the JSON file named by ADMM_BATCH_PLAN at context creation.
+constexpr int kClasses = 3;
+constexpr int kVariants = 2 * kClasses;       // variant v: class v % 3, one wave if v >= 3
+constexpr int kPlanBuckets = 7;
+constexpr int kPlanBucketTop[kPlanBuckets - 1] = {64, 128, 256, 512, 1024, 2048};
+struct BatchPlan {
+    uint8_t wave[kClasses][kPlanBuckets] = {};
+};
+inline int variant_class(int v) { return v % kClasses; }
+inline bool variant_wave(int v) { return v >= kClasses; }
+
 // What admm_resume needs of the context's most recent solve.
 struct LastSolve {
     bool valid = false;
@@ -96,6 +111,7 @@ struct admm_context {
     uint64_t graph_clock = 0;
     admm::Lim lim;                  // host copy of the current solve's stop limits
     admm::LastSolve last;           // the most recent solve (admm_resume)
+    admm::BatchPlan plan;           // kernel variant per (m, n) of the batched path
     bool coop = false;              // cooperative launch supported
     int num_cu = 0;
     int persist_cap[3][3][3] = {{{-1, -1, -1}, {-1, -1, -1}, {-1, -1, -1}},
@@ -123,6 +139,10 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
                     bool graphs = true);
 
 void batch_release(admm_context *ctx);
+int batch_class(int m);
+int batch_bucket(int n);
+int batch_variant(const admm_context *ctx, int m, int n);
+admm_status plan_load_file(admm_context *ctx, const char *path);
 void serve_shutdown(admm_context *ctx);
 
 }  // namespace admm

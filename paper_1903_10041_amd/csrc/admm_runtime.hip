@@ -232,6 +232,12 @@ extern "C" admm_status admm_create(admm_context **out, int device, size_t budget
         admm_destroy(ctx);
         return st;
     }
+    if (const char *plan = std::getenv("ADMM_BATCH_PLAN")) {
+        if (*plan && (st = plan_load_file(ctx, plan)) != ADMM_OK) {
+            admm_destroy(ctx);
+            return st;
+        }
+    }
     int coop = 0, ncu = 0;
     (void)hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
     (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
@@ -375,6 +381,16 @@ static void chain_grid(admm_context *ctx, int n, int &nblk, int &chunks) {
     nblk = (n + kChainBlock * chunks - 1) / (kChainBlock * chunks);
 }
 
+// Blocks of the chained launch with the consensus block: at most one per
+// compute unit (ADMM_CHAINQ_GRID overrides the cap, for tuning sweeps).
+static int chainq_grid_cap(admm_context *ctx) {
+    static const int forced = [] {
+        const char *e = std::getenv("ADMM_CHAINQ_GRID");
+        return e ? std::atoi(e) : 0;
+    }();
+    return forced > 0 ? forced : std::max(1, ctx->num_cu);
+}
+
 int finalize_group(int m, int q, int nblk, int threads) {
     // lanes per (i, j) pair: as many as the block has per pair (several
     // waves for a few pairs over many tiles), no more than the tiles
@@ -445,7 +461,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     // chained with consensus: at most one block per compute unit, each
     // sweeping its share of the q * nblk column tiles in turn
     if (chain && (q > 1 || s->consensus_q1))
-        P.cgrid = std::min(q * ((n + kChainBlock - 1) / kChainBlock), std::max(1, ctx->num_cu));
+        P.cgrid = std::min(q * ((n + kChainBlock - 1) / kChainBlock), chainq_grid_cap(ctx));
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     // lanes per (i,j) pair in the scalar steps: the split path runs them in

@@ -153,3 +153,106 @@ def test_batch_pack_equals_list_call(ctx, where):
         assert int(rec["iters"][b]) == infos[b]["iters"]
         assert int(rec["status"][b]) == infos[b]["status"]
         assert float(rec["objective"][b]) == infos[b]["objective"]
+
+
+WAVE_ALL = np.ones((3, 7), dtype=np.uint8)
+BLOCK_ALL = np.zeros((3, 7), dtype=np.uint8)
+
+
+@pytest.mark.parametrize("plan", ["wave", "block"])
+def test_batch_plan_variants_follow_oracle(plan):
+    """Every instance on one wave (64 threads) or on a 256-thread block, for
+    every source class and horizon: each instance against the oracle."""
+    c = admm.Context(0)
+    try:
+        admm.set_batch_plan(c, WAVE_ALL if plan == "wave" else BLOCK_ALL)
+        assert np.array_equal(admm.get_batch_plan(c), WAVE_ALL if plan == "wave" else BLOCK_ALL)
+        probs = mixed_batch(count=48, seed=310, n_hi=2600)
+        print(f"[batch plan {plan}] 48 instances, n < 2600, 200 iterations", flush=True)
+        xs, infos = c.solve_batch(probs, fixed(200))
+        for p, x, inf in zip(probs, xs, infos):
+            st, oi, _ = oracle.run(p, max_iter=200)
+            assert inf["iters"] == 200
+            assert np.abs(x - st["x"]).max() <= 1e-9, (plan, p.m, p.n)
+            assert abs(inf["objective"] - oi["objective"]) <= 1e-9 * (1 + abs(oi["objective"]))
+        # served requests run the same kernel variant as the batched call
+        s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+                          rho2_per_step=True)
+        p = probs[5]
+        xb, ib = c.solve_batch([p], s)
+        t = c.submit(p, s)
+        while (out := c.poll(t, p.m, p.n)) is None:
+            pass
+        assert np.array_equal(out[0], xb[0]) and out[1]["iters"] == ib[0]["iters"]
+    finally:
+        c.close()
+
+
+def test_batch_graph_replay_is_stable():
+    """Repeated calls on one pack replay the captured pipeline: the same
+    bits every time, equal to a fresh context's first call."""
+    import torch
+    dev = torch.device("cuda:0")
+    probs = mixed_batch(60, 311, n_hi=1500)
+    tp = [W.Problem(**{k: (torch.from_numpy(v).to(device=dev, dtype=torch.float32).contiguous()
+                           if isinstance(v, np.ndarray) and k != "c" else v)
+                       for k, v in vars(p).items()}) for p in probs]
+    s = admm.Settings(max_iter=5000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED, rho2_per_step=True)
+    c = admm.Context(0)
+    fresh = admm.Context(0)
+    try:
+        pack = admm.BatchPack(tp)
+        outs = []
+        for _ in range(3):
+            x, rec = c.solve_batch(pack, s)
+            torch.cuda.synchronize()
+            outs.append((x.clone(), rec["iters"].copy(), rec["objective"].copy()))
+        pack2 = admm.BatchPack(tp)
+        x2, rec2 = fresh.solve_batch(pack2, s)
+        torch.cuda.synchronize()
+        for x, it, ob in outs:
+            assert torch.equal(x, x2)
+            assert np.array_equal(it, rec2["iters"]) and np.array_equal(ob, rec2["objective"])
+    finally:
+        c.close()
+        fresh.close()
+
+
+def test_tune_batch_writes_and_loads_plan(tmp_path):
+    """The autotuner times both block sizes on the classes and horizons a
+    batch occupies, installs the faster plan and writes it as JSON; a new
+    context loads the file, and results under the tuned plan follow the
+    oracle."""
+    import json
+    probs = W.batch_c3(count=256)
+    path = str(tmp_path / "plan.json")
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED,
+                      rho2_per_step=True)
+    c = admm.Context(0)
+    c2 = admm.Context(0)
+    try:
+        plan, ns, (ms0, ms1) = admm.tune_batch(c, probs, s, iters=30, json_path=path)
+        print(f"[tune] plan rows {plan.tolist()}", flush=True)
+        print(f"[tune] block ns/instance-iteration {np.round(ns[0], 1).tolist()}", flush=True)
+        print(f"[tune] wave  ns/instance-iteration {np.round(ns[1], 1).tolist()}", flush=True)
+        doc = json.load(open(path))
+        assert doc["format"] == "admm-batch-plan-1"
+        assert np.array_equal(np.array(doc["wave"], dtype=np.uint8), plan)
+        occupied = ns[0] > 0
+        assert occupied.any() and np.array_equal(ns[1] > 0, occupied)
+        # a bucket is on one wave only where that measured clearly faster,
+        # and the tuned plan is no slower on the batch than the start
+        print(f"[tune] batch device ms: start {ms0:.3f}, tuned {ms1:.3f}", flush=True)
+        assert not (plan.astype(bool) & ~(occupied & (ns[1] < 0.97 * ns[0]))).any()
+        assert 0 < ms1 <= ms0
+        assert doc["batch_device_ms"]["tuned"] <= doc["batch_device_ms"]["start"]
+        admm.set_batch_plan(c2, json_path=path)
+        assert np.array_equal(admm.get_batch_plan(c2), plan)
+        sample = probs[::16]
+        xs, infos = c2.solve_batch(sample, fixed(100))
+        for p, x, inf in zip(sample, xs, infos):
+            st, oi, _ = oracle.run(p, max_iter=100)
+            assert np.abs(x - st["x"]).max() <= 1e-9
+    finally:
+        c.close()
+        c2.close()
