@@ -476,111 +476,167 @@ def run_batch(args):
             "speedup_vs_plain": (conv / dt) * dt_plain}
 
 
-def run_serve(args):
-    """Open-loop Poisson client at --serve-rate requests/s for
-    --serve-seconds: requests with m in {2, 4}, n log-uniform [100, 50000],
-    256 warm-start keys, residual 1e-4, f32 storage.  Instances come from a
-    pool of --serve-pool seeded problems reused round-robin (generating
-    every request's arrays would cost more host time than the solves).
-    Then the first --serve-plain-sample requests of the same stream one
-    after another through admm_solve, cold."""
-    import math
+def _serve_stream_run(ctx, streams, s, rate, seconds, seed, threads=4):
+    """One open-loop Poisson run at `rate` requests/s for `seconds`: each
+    arrival picks a stream uniformly and submits its next window, warm key =
+    the stream.  Client threads own disjoint streams (a thinned Poisson
+    process each); one poller collects results."""
     import threading
     import numpy as np
     from paper_1903_10041_amd import admm
-    from paper_1903_10041_amd import workloads as W
-    rng = np.random.default_rng(5)
-    pool = []
-    for r in range(args.serve_pool):
-        m = int(rng.choice([2, 4]))
-        n = int(round(math.exp(rng.uniform(math.log(100), math.log(50000)))))
-        pool.append(W.uniform_problem(m, n, 5 * 7_000_003 + r))
-    nreq = int(args.serve_rate * args.serve_seconds)
-    gaps = rng.exponential(1.0 / args.serve_rate, size=nreq)
-    keys = rng.integers(1, 257, size=nreq)
-    ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
-    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=_prec(args),
-                      rho2_per_step=True)
-    # warm-up
-    for p in pool[:8]:
-        t = ctx.submit(p, s)
-        while ctx.poll(t, p.m, p.n) is None:
-            time.sleep(0.001)
-    lat, iters, status, horizon = [], [], [], []
+    rng = np.random.default_rng(seed)
+    nreq = int(rate * seconds)
+    times = np.cumsum(rng.exponential(1.0 / rate, size=nreq))
+    sid = rng.integers(0, len(streams), size=nreq)
+    nxt = [0] * len(streams)
+    lat, iters, warm, status, horizon = [], [], [], [], []
     submitted = {}
-    done_flag = [False]
     lock = threading.Lock()
+    stop = [False]
+    refused = [0]
+    depth = [0]
 
     def poller():
         while True:
             with lock:
                 items = list(submitted.items())
-            if not items and done_flag[0]:
+            if not items and stop[0]:
                 return
-            for t, (p, ts) in items:
-                out = ctx.poll(t, p.m, p.n)
+            for t, (p, ts, w) in items:
+                out = ctx.poll(t, p.m, p.n, p.q)
                 if out is not None:
                     lat.append(time.perf_counter() - ts)
-                    horizon.append(p.n)
                     iters.append(out[1]["iters"])
                     status.append(out[1]["status"])
+                    warm.append(w)
+                    horizon.append(p.n)
                     with lock:
                         del submitted[t]
             time.sleep(0.0002)
 
-    depth = 0
-    th = threading.Thread(target=poller)
-    th.start()
+    def client(tid, t0):
+        for r in range(nreq):
+            k = int(sid[r])
+            if k % threads != tid:
+                continue
+            due = t0 + times[r]
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            st_ = streams[k]
+            w = nxt[k]
+            if w >= st_.windows:
+                continue
+            nxt[k] += 1
+            p = st_.window(w)
+            ts = time.perf_counter()
+            try:
+                t = ctx.submit(p, s, warm_key=k + 1)
+            except admm.AdmmError as e:
+                if e.status != admm.E_QUEUE_FULL:
+                    raise
+                refused[0] += 1
+                continue
+            with lock:
+                submitted[t] = (p, ts, w > 0)
+                depth[0] = max(depth[0], len(submitted))
+
+    pt = threading.Thread(target=poller)
+    pt.start()
     t0 = time.perf_counter()
-    due = t0
-    for r in range(nreq):
-        due += gaps[r]
-        now = time.perf_counter()
-        if due > now:
-            time.sleep(due - now)
-        p = pool[r % len(pool)]
-        ts = time.perf_counter()
-        t = ctx.submit(p, s, warm_key=int(keys[r]))
-        with lock:
-            submitted[t] = (p, ts)
-            depth = max(depth, len(submitted))
+    cl = [threading.Thread(target=client, args=(i, t0)) for i in range(threads)]
+    for c in cl:
+        c.start()
+    for c in cl:
+        c.join()
     t_sub = time.perf_counter() - t0
-    done_flag[0] = True
-    th.join()
+    stop[0] = True
+    pt.join()
     t_all = time.perf_counter() - t0
-    # the same request stream, one request after another through the plain
-    # per-instance admm_solve (cold starts), on a sample
-    plain_ms = []
-    for r in range(min(args.serve_plain_sample, nreq)):
-        p = pool[r % len(pool)]
-        tp = time.perf_counter()
-        ctx.solve(p, s)
-        plain_ms.append((time.perf_counter() - tp) * 1000.0)
-    ctx.close()
     lat_ms = np.array(lat) * 1000.0
-    hz = np.array(horizon)
     it = np.array(iters)
-    # requests with n >= 8192 run on the serving lanes (admm_solve), the
-    # rest in the batched windows
-    lanes = hz >= 8192
+    wm = np.array(warm, dtype=bool)
+    hz = np.array(horizon)
 
     def pct(sel):
         if not sel.any():
             return None
         return {"count": int(sel.sum()), "p50_ms": float(np.percentile(lat_ms[sel], 50)),
                 "p99_ms": float(np.percentile(lat_ms[sel], 99)),
-                "iters_p50": float(np.percentile(it[sel], 50)), "iters_p99": float(np.percentile(it[sel], 99))}
-    return {"workload": f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, m in {{2,4}}, "
-                        f"n log-uniform [100, 50000] (pool of {len(pool)}), 256 warm keys, residual 1e-4, "
-                        "f32 storage, rho_2 / n",
-            "requests": nreq, "completed": len(lat), "converged": int(sum(st == admm.OK for st in status)),
-            "solves_per_s": len(lat) / t_all, "offered_per_s": nreq / t_sub,
-            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
-            "max_ms": float(lat_ms.max()), "mean_iters": float(np.mean(iters)), "drain_s": t_all - t_sub,
-            "long_n_ge_8192": pct(lanes), "short": pct(~lanes), "max_outstanding": depth,
-            "plain_path": {"requests": len(plain_ms), "solves_per_s": len(plain_ms) / (sum(plain_ms) / 1000.0),
-                           "p50_ms": float(np.percentile(plain_ms, 50)),
-                           "p99_ms": float(np.percentile(plain_ms, 99))} if plain_ms else None}
+                "iters_mean": float(it[sel].mean()), "iters_p50": float(np.percentile(it[sel], 50))}
+    done = len(lat)
+    return {"offered_per_s": nreq / max(t_sub, 1e-9), "requests": nreq, "completed": done,
+            "refused_queue_full": refused[0], "converged": int(sum(st == admm.OK for st in status)),
+            "solves_per_s": done / t_all, "drain_s": t_all - t_sub, "max_outstanding": depth[0],
+            "p50_ms": float(np.percentile(lat_ms, 50)) if done else None,
+            "p99_ms": float(np.percentile(lat_ms, 99)) if done else None,
+            "warm": pct(wm), "cold": pct(~wm), "long_n_ge_8192": pct(hz >= 8192), "short": pct(hz < 8192)}
+
+
+def run_serve(args):
+    """The serving case: 256 receding-horizon client streams (m in {2, 4},
+    n log-uniform [100, 50000], a fixed coefficient trajectory each; request
+    r of a stream is the window one step after request r - 1 and is warm-
+    started from its final state), open-loop Poisson arrivals.  First
+    --serve-rate requests/s for --serve-seconds; then a sweep of offered
+    rates (--serve-sweep, --serve-sweep-seconds each) that stops once p99
+    passes 1 s or fewer than 90% of the offered requests complete per
+    second; the sustainable rate is the highest rate that held.  Then the
+    first --serve-plain-sample windows of the streams one after another
+    through the plain admm_solve (cold), for the per-instance rate."""
+    import numpy as np
+    from paper_1903_10041_amd import admm
+    from paper_1903_10041_amd import workloads as W
+    rates = [float(v) for v in args.serve_sweep.split(",") if v]
+    total_s = args.serve_seconds + args.serve_sweep_seconds * len(rates)
+    per_stream = int(max(args.serve_rate, max(rates, default=0.0)) * total_s / 256 * 1.5) + 16
+    t0 = time.perf_counter()
+    streams = W.serving_streams_c5(seed=5, streams=256, requests_per_stream=per_stream)
+    gen_s = time.perf_counter() - t0
+    ctx = admm.Context(0, hbm_budget_bytes=32 << 30)
+    s = admm.Settings(max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, precision=_prec(args),
+                      rho2_per_step=True)
+    # warm-up on a separate context: code objects and buffers
+    wctx = admm.Context(0, hbm_budget_bytes=4 << 30)
+    for k in range(8):
+        p = streams[k].window(streams[k].windows - 1)
+        t = wctx.submit(p, s)
+        while wctx.poll(t, p.m, p.n) is None:
+            time.sleep(0.001)
+    wctx.close()
+    main = _serve_stream_run(ctx, streams, s, args.serve_rate, args.serve_seconds, seed=51)
+    sweep = []
+    sustainable = None
+    for i, rate in enumerate(rates):
+        rr = _serve_stream_run(ctx, streams, s, rate, args.serve_sweep_seconds, seed=52 + i)
+        # the Python client itself cannot offer more than some thousands of
+        # requests per second (each request's window is copied twice on the
+        # host); past that the sweep measures the client, not the engine
+        client_limited = rr["offered_per_s"] < 0.9 * rate
+        held = (not client_limited and rr["p99_ms"] is not None and rr["p99_ms"] <= 1000.0
+                and rr["solves_per_s"] >= 0.9 * rr["offered_per_s"] and rr["refused_queue_full"] == 0)
+        sweep.append({k: rr[k] for k in ("offered_per_s", "solves_per_s", "completed", "refused_queue_full",
+                                         "p50_ms", "p99_ms", "max_outstanding")}
+                     | {"nominal_per_s": rate, "held": held, "client_limited": client_limited})
+        if not held:
+            break
+        sustainable = rate
+    # the plain per-instance path on the first windows of the streams, cold
+    plain_ms = []
+    for k in range(min(args.serve_plain_sample, len(streams))):
+        p = streams[k].window(0)
+        tp = time.perf_counter()
+        ctx.solve(p, s)
+        plain_ms.append((time.perf_counter() - tp) * 1000.0)
+    ctx.close()
+    plain = {"requests": len(plain_ms), "solves_per_s": len(plain_ms) / (sum(plain_ms) / 1000.0),
+             "p50_ms": float(np.percentile(plain_ms, 50)), "p99_ms": float(np.percentile(plain_ms, 99))}
+    main.update({"workload": f"256 receding-horizon streams (m in {{2,4}}, n log-uniform [100, 50000]), "
+                             f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, warm keys per "
+                             "stream, residual 1e-4, f32 storage, rho_2 / n",
+                 "stream_generation_s": gen_s, "rate_sweep": sweep, "sustainable_per_s": sustainable,
+                 "plain_path": plain})
+    return main
 
 
 def run_robust(args):
@@ -724,7 +780,9 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=5.0)
-    ap.add_argument("--serve-pool", type=int, default=384)
+    ap.add_argument("--serve-sweep", default="3000,5000,7000,10000",
+                    help="offered rates (requests/s) of the serving capacity sweep")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=2.0)
     ap.add_argument("--serve-plain-sample", type=int, default=200,
                     help="requests of the served stream also run one by one through admm_solve")
     ap.add_argument("--robust-max-iter", type=int, default=100000)

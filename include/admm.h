@@ -140,8 +140,9 @@ typedef struct {
      * band_hi * eps_primal / eps_dual and divided by tau when r / sigma <
      * band_lo * eps_primal / eps_dual (ratio target 1 if a threshold is 0);
      * the scaled duals mu, lambda, nu, p are divided by the same factor, so
-     * the unscaled multipliers do not change.  admm_solve only (batched
-     * instances with it run through admm_solve; admm_submit refuses it).
+     * the unscaled multipliers do not change.  Run by admm_solve (batched
+     * instances with it run through admm_solve; served requests with it run
+     * on a serving lane).
      * Defaults 0, 1.1, 1.2, 0.8; tau > 1, 0 < band_lo <= band_hi. */
     int32_t adaptive_rho;
     double tau, band_hi, band_lo;
@@ -295,27 +296,32 @@ admm_status admm_tune_batch(admm_context *ctx, int32_t count, const admm_problem
 admm_status admm_set_batch_plan(admm_context *ctx, const uint8_t *wave, const char *json_path);
 admm_status admm_get_batch_plan(admm_context *ctx, uint8_t *wave);
 
-/* Serving.  submit copies the problem (host memory only) and returns a
- * ticket at once; the instance is admitted to the device when a slot and
- * the HBM budget allow, and runs alongside the others already resident.
- * warm_key != 0 warm-starts from the final state of the previous request
- * with the same key (shifted to the new horizon as a receding-horizon
- * re-solve, Alg. 2) and stores this request's final state under it.
- * Requests with n >= 8192 run on lanes instead: sub-contexts (each with
- * 1/16 of this context's budget and its own stream and thread) that solve
- * one request at a time through admm_solve, so their result equals
- * admm_solve's.  Environment, read when serving starts on a context:
- * ADMM_SERVE_BIG_N (8192, 0 = no lanes), ADMM_SERVE_LANES (2),
+/* Serving.  submit copies the problem (host arrays, or device arrays read
+ * back during the call) and returns a ticket at once; the instance is
+ * admitted to the device when a slot and the HBM budget allow, and runs
+ * alongside the others already resident.  warm_key != 0 warm-starts from
+ * the final state of the previous request with the same key (shifted to
+ * the new horizon as a receding-horizon re-solve, Alg. 2: x and s - mu move
+ * one step, the last step takes the cold start, lambda and p carry over,
+ * nu restarts at 0) and stores this request's final state under it; a
+ * state is only reused by a request of the same m and q.  Requests with
+ * n >= 8192, and every request the batched kernels do not take (q > 1,
+ * f0/g0, per-step bounds, adaptive rho), run on lanes instead:
+ * sub-contexts (each with 1/(8 * lanes) of this context's budget and its
+ * own stream and thread) that solve one request at a time through
+ * admm_solve, so their result equals admm_solve's with that warm start.
+ * Environment, read when serving starts on a context:
+ * ADMM_SERVE_BIG_N (8192, 0 = no lanes), ADMM_SERVE_LANES (8),
  * ADMM_SERVE_MAX_QUEUE (2^20 requests waiting for admission, over the
  * batched queue and the lanes' queues, before ADMM_E_QUEUE_FULL),
  * ADMM_SERVE_WINDOW (50 iterations per window), ADMM_SERVE_WINDOW_REF (16:
  * requests with m * ceil(n / 256) above it yield after proportionally
  * fewer iterations; 0 = off).  Two requests with the same key in flight at
- * once race for its warm state.  Errors: ADMM_E_UNSUPPORTED (device
- * arrays, q > 1, f0/g0, per-step bounds, adaptive rho),
- * ADMM_E_OUT_OF_BUDGET (an instance larger than the serving arena),
- * ADMM_E_QUEUE_FULL, ADMM_E_INVALID_ARG (mixed precisions on one
- * context, invalid inputs). */
+ * once race for its warm state (each starts from some complete earlier
+ * state of the key, or cold).  Errors: ADMM_E_UNSUPPORTED (a request for
+ * a lane on a context without lanes), ADMM_E_OUT_OF_BUDGET (an instance
+ * larger than the serving arena or a lane's budget), ADMM_E_QUEUE_FULL,
+ * ADMM_E_INVALID_ARG (mixed precisions on one context, invalid inputs). */
 admm_status admm_submit(admm_context *ctx, const admm_problem *prob,
                         const admm_settings *settings, uint64_t warm_key,
                         uint64_t *ticket);

@@ -262,10 +262,12 @@ class Context:
         return _solve_batch(self, probs, settings, x_outs)
 
     def submit(self, prob, settings: Optional[Settings] = None, warm_key: int = 0) -> int:
-        """admm_submit (host arrays).  Returns the ticket."""
+        """admm_submit (host arrays, or device tensors read back during the
+        call).  Returns the ticket."""
         mp = _Marshal(prob)
         if mp.device:
-            raise TypeError("admm_submit takes host arrays")
+            import torch
+            torch.cuda.current_stream(prob.f2.device).synchronize()
         s = settings.to_c() if settings else None
         t = C.c_uint64()
         _check(lib().admm_submit(self.h, C.byref(mp.st), C.byref(s) if s is not None else None,

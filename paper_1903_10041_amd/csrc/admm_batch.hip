@@ -798,7 +798,11 @@ struct ServeReq {
     uint64_t ticket = 0, key = 0;
     admm_settings S;
     int m = 0, n = 0, n_pad = 0;
+    int q = 1;                  // scenarios (q > 1 runs on a lane)
+    bool per_step = false;      // bounds [m][n] rather than [m]
+    bool general = false;       // outside the batched kernels: runs on a lane
     std::vector<double> f2, f1, g2, g1, y, lo, hi, c;
+    std::vector<double> f0, g0;   // empty: zero
     size_t off = SIZE_MAX, bytes = 0;
     // byte offsets (from the arena base) of the parts of the chunk
     size_t coef_b = 0, x_b = 0, y_b = 0, w_b = 0, pool_b = 0;
@@ -893,8 +897,8 @@ constexpr size_t kServeMaxQueue = 1u << 20;
 // Warm state of a request served on a lane: x [m][n] and w = s - mu [n]
 // of its final iterate, lambda and p per source.
 struct HostWarm {
-    int m = 0, n = 0;
-    std::vector<double> x, w, lam, p;
+    int m = 0, n = 0, q = 1;
+    std::vector<double> x, w, lam, p;   // [q][m][n], [q][n], [q][m], [q][m]
 };
 
 struct ServeLane {
@@ -969,7 +973,7 @@ static void serve_fail(ServeState *ss, const std::string &msg) {
 // Called with ss->mu held; false when nothing was moved.
 static bool adopt_host_warm(ServeState *ss, uint64_t key, size_t T, hipStream_t s) {
     auto hit = ss->hwarm.find(key);
-    if (hit == ss->hwarm.end()) return false;
+    if (hit == ss->hwarm.end() || hit->second.q != 1) return false;
     const HostWarm &hw = hit->second;
     const size_t n_pad = (size_t)(hw.n + kPad - 1) / kPad * kPad, rows = (size_t)hw.m * n_pad;
     WarmEntry we;
@@ -1382,44 +1386,59 @@ static void serve_main(admm_context *ctx, ServeState *ss) {
     }
 }
 
-// A lane request's warm start, as the batched path builds it: x and w
-// shifted one step (steps past the old horizon take the cold defaults), x
-// clamped into the new box, lambda and p from the previous solve,
-// z = g(x), h = min(c, sum_k g(x)).
+// A lane request's warm start, as the batched path builds it, for every
+// scenario: x and w shifted one step (steps past the old horizon take the
+// cold defaults), x clamped into the new box, lambda and p from the
+// previous solve, z = g(x), h = min(c, sum_k g(x)); nu = 0 (the first step
+// moved, so the old consensus multipliers no longer apply) and x_bar_1 the
+// mean of the new first steps.
+static double req_lo(const ServeReq *r, int i, int k) {
+    return r->per_step ? r->lo[(size_t)i * r->n + k] : r->lo[i];
+}
+static double req_hi(const ServeReq *r, int i, int k) {
+    return r->per_step ? r->hi[(size_t)i * r->n + k] : r->hi[i];
+}
+
 static void lane_warm_state(const ServeReq *r, const HostWarm &hw, std::vector<double> &x,
                             std::vector<double> &sv, std::vector<double> &mu, std::vector<double> &h,
                             std::vector<double> &p, std::vector<double> &nu, std::vector<double> &xbar1,
                             std::vector<double> &lam, std::vector<double> &zoff) {
-    const int m = r->m, n = r->n;
-    x.assign((size_t)m * n, 0.0);
-    sv.assign(n, 0.0);
-    mu.assign(n, 0.0);
-    h.assign(m, 0.0);
+    const int m = r->m, n = r->n, q = r->q;
+    const size_t M = (size_t)q * m;
+    x.assign(M * n, 0.0);
+    sv.assign((size_t)q * n, 0.0);
+    mu.assign((size_t)q * n, 0.0);
+    h.assign(M, 0.0);
     p = hw.p;
-    nu.assign(m, 0.0);
+    nu.assign(M, 0.0);
     xbar1.assign(m, 0.0);
     lam = hw.lam;
-    zoff.assign(m, 0.0);
-    std::vector<double> gs(m, 0.0);
-    for (int k = 0; k < n; ++k) {
-        const bool have = k + 1 < hw.n;
-        double sx = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double lo = r->lo[i], hi = r->hi[i];
-            const double x0 = have ? hw.x[(size_t)i * hw.n + k + 1] : std::min(std::max(0.0, lo), hi);
-            const double xv = std::min(std::max(x0, lo), hi);
-            const size_t e = (size_t)i * n + k;
-            x[e] = xv;
-            gs[i] += (r->g2[e] * xv + r->g1[e]) * xv;
-            sx += xv;
+    zoff.assign(M, 0.0);
+    std::vector<double> gs(M, 0.0);
+    for (int j = 0; j < q; ++j)
+        for (int k = 0; k < n; ++k) {
+            const bool have = k + 1 < hw.n;
+            double sx = 0.0;
+            for (int i = 0; i < m; ++i) {
+                const double lo = req_lo(r, i, k), hi = req_hi(r, i, k);
+                const size_t e = ((size_t)j * m + i) * n + k;
+                const double x0 = have ? hw.x[((size_t)j * m + i) * hw.n + k + 1] : std::min(std::max(0.0, lo), hi);
+                const double xv = std::min(std::max(x0, lo), hi);
+                x[e] = xv;
+                const double g0 = r->g0.empty() ? 0.0 : r->g0[e];
+                gs[(size_t)j * m + i] += (r->g2[e] * xv + r->g1[e]) * xv + g0;
+                sx += xv;
+            }
+            const double wv = have ? hw.w[(size_t)j * hw.n + k + 1] : std::max(0.0, sx - r->y[(size_t)j * n + k]);
+            sv[(size_t)j * n + k] = std::max(wv, 0.0);
+            mu[(size_t)j * n + k] = std::max(-wv, 0.0);
         }
-        const double wv = have ? hw.w[k + 1] : std::max(0.0, sx - r->y[k]);
-        sv[k] = std::max(wv, 0.0);
-        mu[k] = std::max(-wv, 0.0);
-    }
+    for (int j = 0; j < q; ++j)
+        for (int i = 0; i < m; ++i) h[(size_t)j * m + i] = std::min(r->c[i], gs[(size_t)j * m + i]);
     for (int i = 0; i < m; ++i) {
-        h[i] = std::min(r->c[i], gs[i]);
-        xbar1[i] = x[(size_t)i * n];
+        double s1 = 0.0;
+        for (int j = 0; j < q; ++j) s1 += x[((size_t)j * m + i) * n];
+        xbar1[i] = s1 / q;
     }
 }
 
@@ -1438,10 +1457,10 @@ static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
             ln->q.pop_front();
             if (r->key) {
                 auto it = ss->hwarm.find(r->key);
-                if (it != ss->hwarm.end() && it->second.m == r->m) {
+                if (it != ss->hwarm.end() && it->second.m == r->m && it->second.q == r->q) {
                     hw = it->second;
                     have_warm = true;
-                } else if (it == ss->hwarm.end()) {
+                } else if (it == ss->hwarm.end() && r->q == 1) {
                     // last solved on the batched path: take its entry out of
                     // the map (the region stays reserved until read back)
                     auto wit = ss->warm.find(r->key);
@@ -1470,6 +1489,7 @@ static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
                 };
                 hw.m = dev_we.m;
                 hw.n = dev_we.n;
+                hw.q = 1;
                 hw.x.resize((size_t)hw.m * hw.n);
                 hw.w.resize(hw.n);
                 for (int i = 0; i < hw.m; ++i)
@@ -1484,14 +1504,16 @@ static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
         std::memset(&pr, 0, sizeof pr);
         pr.m = r->m;
         pr.n = r->n;
-        pr.q = 1;
+        pr.q = r->q;
         pr.mem = ADMM_HOST;
         pr.dtype = ADMM_F64;
         pr.f2 = r->f2.data();
         pr.f1 = r->f1.data();
         pr.g2 = r->g2.data();
         pr.g1 = r->g1.data();
-        pr.bounds = ADMM_BOUNDS_PER_SOURCE;
+        pr.f0 = r->f0.empty() ? nullptr : r->f0.data();
+        pr.g0 = r->g0.empty() ? nullptr : r->g0.data();
+        pr.bounds = r->per_step ? ADMM_BOUNDS_PER_STEP : ADMM_BOUNDS_PER_SOURCE;
         pr.x_lo = r->lo.data();
         pr.x_hi = r->hi.data();
         pr.y = r->y.data();
@@ -1505,20 +1527,23 @@ static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
             warm.p = wp.data(); warm.nu = wnu.data(); warm.xbar1 = wxb.data();
             warm.lambda_s = wlam.data(); warm.zoff_s = wzoff.data();
         }
-        r->x.assign((size_t)r->m * r->n, 0.0);
-        std::vector<double> ox, os, omu, oh, op, olam, ozoff;
+        const size_t M = (size_t)r->q * r->m;
+        r->x.assign(M * r->n, 0.0);
+        std::vector<double> ox, os, omu, oh, op, olam, ozoff, onu, oxb;
         admm_state out;
         std::memset(&out, 0, sizeof out);
         if (r->key) {
-            ox.resize((size_t)r->m * r->n);
-            os.resize(r->n);
-            omu.resize(r->n);
-            oh.resize(r->m);
-            op.resize(r->m);
-            olam.resize(r->m);
-            ozoff.resize(r->m);
+            ox.resize(M * r->n);
+            os.resize((size_t)r->q * r->n);
+            omu.resize((size_t)r->q * r->n);
+            oh.resize(M);
+            op.resize(M);
+            olam.resize(M);
+            ozoff.resize(M);
+            onu.resize(M);
+            oxb.resize(r->m);
             out.x = ox.data(); out.s = os.data(); out.mu = omu.data(); out.h = oh.data(); out.p = op.data();
-            out.lambda_s = olam.data(); out.zoff_s = ozoff.data();
+            out.lambda_s = olam.data(); out.zoff_s = ozoff.data(); out.nu = onu.data(); out.xbar1 = oxb.data();
         }
         admm_info inf;
         std::memset(&inf, 0, sizeof inf);
@@ -1540,14 +1565,16 @@ static void lane_main(admm_context *ctx, ServeState *ss, ServeLane *ln) {
             HostWarm nw;
             nw.m = r->m;
             nw.n = r->n;
+            nw.q = r->q;
             nw.x = std::move(ox);
-            nw.w.resize(r->n);
-            for (int k = 0; k < r->n; ++k) nw.w[k] = os[k] - omu[k];
+            nw.w.resize((size_t)r->q * r->n);
+            for (size_t k = 0; k < nw.w.size(); ++k) nw.w[k] = os[k] - omu[k];
             nw.lam = std::move(olam);
             nw.p = std::move(op);
             ss->hwarm[r->key] = std::move(nw);
         }
         r->f2.clear(); r->f1.clear(); r->g2.clear(); r->g1.clear(); r->y.clear();
+        r->f0.clear(); r->g0.clear();
         ss->done[r->ticket] = r;
         ss->cv.notify_all();
     }
@@ -1610,7 +1637,7 @@ static admm_status serve_start(admm_context *ctx, int dtype) {
     size_t bytes = std::min(left, ctx->arena.budget / 8 * 5);
     bytes = std::min(bytes, (size_t)16 << 30) & ~size_t(255);
     if (const char *e = std::getenv("ADMM_SERVE_BIG_N")) ss->big_n = std::max(0, std::atoi(e));
-    int nlanes = 2;
+    int nlanes = 8;
     if (const char *e = std::getenv("ADMM_SERVE_LANES")) nlanes = std::max(0, std::min(16, std::atoi(e)));
     if (ss->big_n == 0) nlanes = 0;
     ss->lane_budget = nlanes ? ctx->arena.budget / 8 / nlanes : 0;
@@ -1649,10 +1676,9 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     admm_status st = validate_settings(&S);
     if (st != ADMM_OK) return st;
     if ((st = validate_problem_shape(prob)) != ADMM_OK) return st;
-    if (prob->mem != ADMM_HOST) return fail(ADMM_E_UNSUPPORTED, "admm_submit takes host arrays");
-    if (!batchable(*prob))
-        return fail(ADMM_E_UNSUPPORTED, "admm_submit serves q = 1 instances with per-source bounds and no g0/f0");
-    if (S.adaptive_rho) return fail(ADMM_E_UNSUPPORTED, "admm_submit runs with fixed rho");
+    // what the batched kernels do not take (q > 1, f0/g0, per-step bounds,
+    // adaptive rho) runs on a lane, through admm_solve
+    const bool general = !batchable(*prob) || S.adaptive_rho;
     const int dtype = (int)S.precision;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1667,28 +1693,81 @@ extern "C" admm_status admm_submit(admm_context *ctx, const admm_problem *prob, 
     r->key = warm_key;
     r->m = prob->m;
     r->n = prob->n;
+    r->q = prob->q;
+    r->per_step = prob->bounds == ADMM_BOUNDS_PER_STEP;
+    r->general = general;
     r->n_pad = (prob->n + kPad - 1) / kPad * kPad;
     r->bytes = serve_chunk_bytes(r->m, r->n_pad, T, nullptr);
     // a long horizon goes to a lane when its solve fits a lane's budget,
-    // else it stays on the batched path
-    const bool big = ss->big_n > 0 && r->n >= ss->big_n && lane_request_bytes(r->m, r->n, T) <= ss->lane_budget;
+    // else it stays on the batched path; a general request needs a lane
+    const bool lane_fits = !ss->lanes.empty() && lane_request_bytes(r->q * r->m, r->n, T) <= ss->lane_budget;
+    if (general && !lane_fits) {
+        delete r;
+        return ss->lanes.empty()
+                   ? fail(ADMM_E_UNSUPPORTED, "q > 1, f0/g0, per-step bounds and adaptive rho are served on lanes, "
+                                              "and this context has none (ADMM_SERVE_BIG_N = 0)")
+                   : fail(ADMM_E_OUT_OF_BUDGET, "instance larger than a serving lane's budget");
+    }
+    const bool big = general || (ss->big_n > 0 && r->n >= ss->big_n && lane_fits);
     if (!big && r->bytes > ss->fl.total()) {
         delete r;
         return fail(ADMM_E_OUT_OF_BUDGET, "instance larger than the serving arena");
     }
-    const size_t E = (size_t)r->m * r->n;
-    auto cp = [](const void *p, size_t n) {
-        const double *d = (const double *)p;
-        return std::vector<double>(d, d + n);
+    // deep copies of the arrays (device arrays are read back now, so that
+    // no caller pointer is kept past the call)
+    const size_t E = (size_t)r->q * r->m * r->n;
+    const size_t NB = r->per_step ? (size_t)r->m * r->n : (size_t)r->m;
+    const bool dev = prob->mem == ADMM_DEVICE;
+    const size_t ST = dev && prob->dtype != ADMM_F64 ? 4 : 8;
+    bool copy_ok = true;
+    auto cp = [&](const void *p, size_t n) {
+        std::vector<double> v;
+        if (!p) return v;
+        v.resize(n);
+        if (!dev) {
+            std::memcpy(v.data(), p, n * sizeof(double));
+        } else if (ST == 8) {
+            copy_ok &= hipMemcpy(v.data(), p, n * 8, hipMemcpyDeviceToHost) == hipSuccess;
+        } else {
+            std::vector<float> f(n);
+            copy_ok &= hipMemcpy(f.data(), p, n * 4, hipMemcpyDeviceToHost) == hipSuccess;
+            for (size_t i = 0; i < n; ++i) v[i] = f[i];
+        }
+        return v;
     };
-    r->f2 = cp(prob->f2, E);
-    r->f1 = cp(prob->f1, E);
-    r->g2 = cp(prob->g2, E);
-    r->g1 = cp(prob->g1, E);
-    r->y = cp(prob->y, r->n);
-    r->lo = cp(prob->x_lo, r->m);
-    r->hi = cp(prob->x_hi, r->m);
-    r->c = cp(prob->c, r->m);
+    {
+        DeviceGuard g(ctx->device);
+        r->f2 = cp(prob->f2, E);
+        r->f1 = cp(prob->f1, E);
+        r->g2 = cp(prob->g2, E);
+        r->g1 = cp(prob->g1, E);
+        r->f0 = cp(prob->f0, E);
+        r->g0 = cp(prob->g0, E);
+        r->y = cp(prob->y, (size_t)r->q * r->n);
+        r->lo = cp(prob->x_lo, NB);
+        r->hi = cp(prob->x_hi, NB);
+    }
+    r->c.assign(prob->c, prob->c + r->m);
+    if (!copy_ok) {
+        delete r;
+        return fail(ADMM_E_DEVICE, "reading the problem's device arrays failed");
+    }
+    if (dev) {
+        // what validate_problem_shape checks for host arrays
+        auto finite = [](const std::vector<double> &v) {
+            for (double a : v)
+                if (!std::isfinite(a)) return false;
+            return true;
+        };
+        bool ok = finite(r->f2) && finite(r->f1) && finite(r->g2) && finite(r->g1) && finite(r->f0) &&
+                  finite(r->g0) && finite(r->y);
+        for (size_t e = 0; ok && e < E; ++e) ok = r->f2[e] >= 0.0 && r->g2[e] >= 0.0;
+        for (size_t e = 0; ok && e < NB; ++e) ok = std::isfinite(r->lo[e]) && std::isfinite(r->hi[e]) && r->lo[e] <= r->hi[e];
+        if (!ok) {
+            delete r;
+            return fail(ADMM_E_INVALID_ARG, "problem arrays must be finite, with f2, g2 >= 0 (Assumption 1) and x_lo <= x_hi");
+        }
+    }
     BInst &I = r->inst;
     std::memset(&I, 0, sizeof I);
     I.m = r->m;
@@ -1764,6 +1843,7 @@ extern "C" admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key) {
     ServeState *ss = ctx->serve;
     if (!ss) return ADMM_OK;
     std::lock_guard<std::mutex> lk(ss->mu);
+    ss->hwarm.erase(warm_key);
     auto it = ss->warm.find(warm_key);
     if (it != ss->warm.end()) {
         ss->fl.release(it->second.off, it->second.bytes);

@@ -205,6 +205,84 @@ def serving_c5(seed: int = 5, rate_hz: float = 2000.0, duration_s: float = 60.0,
     return out
 
 
+class RecedingStream:
+    """One client stream of the serving case: a fixed coefficient trajectory
+    longer than the stream's horizon, so that request r of the stream is the
+    window of steps [r, r + n) -- each request is the previous one moved one
+    step on, as in the receding-horizon re-solve of Alg. 2.
+
+    Plain streams (q = 1): m sources with C1's distributions drawn as [m][L]
+    in the order f2, f1, g2, g1, then the demand [L]; a window's capacity is
+    0.7 sum_k g(2) over the window.  Robust streams (``robust=True``): the
+    PHEV-shaped two-source scenario program of ``phev_c4`` over a trajectory
+    of L steps with q demand scenarios, windows of n steps.
+
+    ``window(r)`` returns the request as a Problem whose arrays are the
+    stream's own buffers (overwritten by the next call; the serving call
+    copies what it is given).
+    """
+
+    def __init__(self, seed: int, m: int, n: int, length: int, robust: bool = False, q: int = 1):
+        if length < n:
+            raise ValueError("the trajectory must be at least one horizon long")
+        self.m, self.n, self.L, self.robust = m, n, length, robust
+        if robust:
+            t = phev_c4(seed=seed, q=q, n=length)
+            self.q = q
+            self._f2, self._f1, self._g2, self._g1, self._y = t.f2, t.f1, t.g2, t.g1, t.y
+            self.xlo, self.xhi = t.xlo, t.xhi
+            self._cap_per_step = float(t.c[1]) / length
+            self.m = 2
+        else:
+            rng = np.random.default_rng(seed)
+            self.q = 1
+            shp = (1, m, length)
+            self._f2 = rng.uniform(0.1, 1.0, size=shp)
+            self._f1 = rng.uniform(-1.0, 1.0, size=shp)
+            self._g2 = rng.uniform(0.01, 0.1, size=shp)
+            self._g1 = rng.uniform(0.8, 1.2, size=shp)
+            self._y = rng.uniform(0.5, 1.5, size=(1, length))
+            self.xlo, self.xhi = np.zeros(m), np.full(m, 2.0)
+        shp_w = (self.q, self.m, n)
+        self._buf = {k: np.empty(shp_w) for k in ("f2", "f1", "g2", "g1")}
+        self._buf["y"] = np.empty((self.q, n))
+
+    @property
+    def windows(self) -> int:
+        return self.L - self.n + 1
+
+    def window(self, r: int) -> Problem:
+        if not 0 <= r < self.windows:
+            raise IndexError("window past the end of the trajectory")
+        sl = slice(r, r + self.n)
+        for k, a in (("f2", self._f2), ("f1", self._f1), ("g2", self._g2), ("g1", self._g1)):
+            np.copyto(self._buf[k], a[:, :, sl])
+        np.copyto(self._buf["y"], self._y[:, sl])
+        if self.robust:
+            c = np.array([math.inf, self._cap_per_step * self.n])
+        else:
+            g2, g1 = self._buf["g2"][0], self._buf["g1"][0]
+            c = 0.7 * (g2 * 4.0 + g1 * 2.0).sum(axis=1)
+        return Problem(m=self.m, n=self.n, q=self.q, f2=self._buf["f2"], f1=self._buf["f1"],
+                       g2=self._buf["g2"], g1=self._buf["g1"], xlo=self.xlo, xhi=self.xhi,
+                       y=self._buf["y"], c=c, name=f"window_{r}")
+
+
+def serving_streams_c5(seed: int = 5, streams: int = 256, requests_per_stream: int = 64,
+                       n_lo: int = 100, n_hi: int = 50000) -> List[RecedingStream]:
+    """The serving case's client streams: stream s has m in {2, 4} and a
+    horizon n log-uniform in [n_lo, n_hi] (drawn from one generator seeded
+    ``seed``), and a trajectory of n + requests_per_stream - 1 steps seeded
+    ``seed * 7_000_003 + s``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(streams):
+        m = int(rng.choice([2, 4]))
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        out.append(RecedingStream(seed * 7_000_003 + s, m, n, n + requests_per_stream - 1))
+    return out
+
+
 @dataclasses.dataclass
 class QuarticBatch:
     """N independent box-constrained quartics A x^4 + B x^3 + C x^2 + D x."""

@@ -244,3 +244,111 @@ def test_overlapping_same_key_requests_stay_valid():
             assert np.all(np.isfinite(x))
             assert abs(inf["objective"] - oref) <= 1e-5 * (1 + abs(oref)), (burst, p.n)
     ctx.close()
+
+
+def _stream_run(ctx, streams, s, interleave):
+    """Receding-horizon streams: request r of stream k is window r of its
+    trajectory, warm-started (key k) from request r - 1's final state.
+    Returns {(k, r): (x, info)}."""
+    plan = {k: st_[1] for k, st_ in streams.items()}
+    probs = {(k, r): streams[k][0].window(r).copy() for k in streams for r in range(plan[k])}
+    results = {}
+    if not interleave:
+        for k in streams:
+            for r in range(plan[k]):
+                p = probs[(k, r)]
+                results[(k, r)] = wait(ctx, ctx.submit(p, s, warm_key=k), p)
+        return results, probs
+    pos = {k: 0 for k in streams}
+    live = {k: ctx.submit(probs[(k, 0)], s, warm_key=k) for k in streams}
+    while live:
+        for k in list(live):
+            p = probs[(k, pos[k])]
+            out = ctx.poll(live[k], p.m, p.n, p.q)
+            if out is None:
+                continue
+            results[(k, pos[k])] = out
+            pos[k] += 1
+            if pos[k] < plan[k]:
+                live[k] = ctx.submit(probs[(k, pos[k])], s, warm_key=k)
+            else:
+                del live[k]
+        time.sleep(0.0002)
+    return results, probs
+
+
+def test_robust_receding_stream_alone_vs_mix():
+    """The robust scenario program (q = 5, n = 600) served as a receding-
+    horizon stream (Alg. 2): each request runs on a lane, warm-started from
+    the previous window's state.  Results are bit-identical whether the
+    stream runs alone or interleaved with plain short and long streams; the
+    cold first request equals admm_solve's, and every warm one reaches the
+    cold optimum."""
+    s = settings(precision=admm.F64, eps_primal=1e-6, eps_dual=1e-6)
+    streams = {
+        1: (W.RecedingStream(4601, 2, 600, 605, robust=True, q=5), 6),
+        2: (W.RecedingStream(4602, 2, 400, 405), 6),
+        3: (W.RecedingStream(4603, 4, 9000, 9003), 4),
+    }
+    print("[serve] robust q=5 n=600 receding stream, alone vs mix", flush=True)
+    ctx_a = admm.Context(0, hbm_budget_bytes=2 << 30)
+    alone, probs = _stream_run(ctx_a, {1: streams[1]}, s, interleave=False)
+    ctx_a.close()
+    ctx_b = admm.Context(0, hbm_budget_bytes=2 << 30)
+    mixed, _ = _stream_run(ctx_b, streams, s, interleave=True)
+    ctx_b.close()
+    cold = admm.Context(0, hbm_budget_bytes=1 << 30)
+    for key in alone:
+        xa, ia = alone[key]
+        xm, im = mixed[key]
+        assert ia["status"] == admm.OK, key
+        assert np.array_equal(xa, xm), key
+        assert ia["iters"] == im["iters"], key
+        xc, ic, _ = cold.solve(probs[key], s)
+        if key[1] == 0:
+            assert np.array_equal(xa.reshape(-1), xc.reshape(-1)) and ia["iters"] == ic["iters"]
+        else:
+            assert abs(ia["objective"] - ic["objective"]) <= 1e-6 * (1 + abs(ic["objective"])), key
+    cold.close()
+
+
+def test_general_requests_run_on_lanes():
+    """Per-step bounds, f0/g0, adaptive rho and device arrays are served
+    (on the lanes): each result equals admm_solve's for the same problem."""
+    import torch
+    s = settings(precision=admm.F64, eps_primal=1e-6, eps_dual=1e-6)
+    ps = W.uniform_problem(3, 700, 4701)
+    ps.xlo = np.zeros((3, 700))
+    ps.xhi = np.full((3, 700), 2.0)
+    ps.xhi[1, 100:200] = 0.5
+    pg = W.uniform_problem(2, 500, 4702)
+    rng = np.random.default_rng(4703)
+    pg.g0 = rng.uniform(-0.1, 0.1, size=pg.g2.shape)
+    pg.f0 = rng.uniform(0.0, 1.0, size=pg.f2.shape)
+    pa = W.uniform_problem(2, 300, 4704)
+    sa = settings(precision=admm.F64, eps_primal=1e-6, eps_dual=1e-6, adaptive_rho=True)
+    pd = W.uniform_problem(4, 1200, 4705)
+    dev = torch.device("cuda:0")
+    td = W.Problem(**{k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) and k != "c" else v)
+                      for k, v in vars(pd).items()})
+    td.c = pd.c
+    ctx = admm.Context(0, hbm_budget_bytes=2 << 30)
+    plain = admm.Context(0, hbm_budget_bytes=1 << 30)
+    try:
+        cases = [(ps, ps, s), (pg, pg, s), (pa, pa, sa)]
+        tickets = [ctx.submit(sub, st_) for sub, _, st_ in cases]
+        for (sub, host, st_), t in zip(cases, tickets):
+            x, inf = wait(ctx, t, host)
+            xr, ir, _ = plain.solve(host, st_)
+            assert inf["status"] == admm.OK
+            assert np.array_equal(x.reshape(-1), xr.reshape(-1))
+            assert inf["iters"] == ir["iters"] and inf["objective"] == ir["objective"]
+        # device arrays (a q = 1 instance the batched windows take): the
+        # same result as the same request from host arrays
+        xd, idv = wait(ctx, ctx.submit(td, s), pd)
+        xh, ih = wait(ctx, ctx.submit(pd, s), pd)
+        assert idv["status"] == admm.OK
+        assert np.array_equal(xd, xh) and idv["iters"] == ih["iters"]
+    finally:
+        ctx.close()
+        plain.close()
