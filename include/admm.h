@@ -98,9 +98,19 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
  * RESIDENT  one cooperative launch whose blocks keep their columns in
  *           registers and meet at a grid barrier every iteration; only
  *           when every block fits on the device at once (else
- *           ADMM_E_UNSUPPORTED). */
+ *           ADMM_E_UNSUPPORTED).
+ * CHAINED_LOCAL  for many scenarios: one launch per iteration, one block
+ *           per tile of 256 columns, each completing the previous
+ *           iteration's scalar steps for its own scenario only (the tile
+ *           of the first step also forms the consensus); a check
+ *           iteration adds one launch of a block per scenario that finishes
+ *           its steps and residuals, and the next launch takes the stop
+ *           decision.  q > 1 (or consensus_q1), m <= 4, m q <= 4096, fixed
+ *           rho (ADMM_E_UNSUPPORTED otherwise).  CHAINED takes it where
+ *           the other chained form does not apply; AUTO never does (it
+ *           measures slower than SPLIT where it would be the choice). */
 typedef enum { ADMM_LAUNCH_AUTO = 0, ADMM_LAUNCH_SPLIT = 1, ADMM_LAUNCH_CHAINED = 2,
-               ADMM_LAUNCH_RESIDENT = 3 } admm_launch;
+               ADMM_LAUNCH_RESIDENT = 3, ADMM_LAUNCH_CHAINED_LOCAL = 4 } admm_launch;
 
 typedef enum { ADMM_HOST = 0, ADMM_DEVICE = 1 } admm_memspace;
 typedef enum { ADMM_BOUNDS_PER_SOURCE = 0, ADMM_BOUNDS_PER_STEP = 1 } admm_bounds_layout;
@@ -346,7 +356,8 @@ admm_status admm_release_warm(admm_context *ctx, uint64_t warm_key);
  *   out[3]  launches timed per kernel;
  *   out[4], out[5]  RESIDENT: microseconds per iteration of one
  *           cooperative launch and its columns per thread (else 0);
- *   out[6]  the admm_launch path taken (1 SPLIT, 2 CHAINED, 3 RESIDENT).
+ *   out[6]  the admm_launch path taken (1 SPLIT, 2 CHAINED, 3 RESIDENT,
+ *           4 CHAINED_LOCAL).
  * Thresholds are ignored; the timed launches advance the iterate and
  * results are not returned.  out must hold 7 doubles. */
 admm_status admm_profile(admm_context *ctx, const admm_problem *prob,
@@ -382,8 +393,10 @@ admm_status admm_debug_copy(admm_context *ctx, size_t bytes, int32_t reps);
 
 void admm_destroy(admm_context *ctx);
 const char *admm_status_string(admm_status s);
-/* Detail of the last error on this thread ("" if none). */
-const char *admm_last_error(void);
+/* Detail of the last error raised on the calling thread ("" if none), by
+ * any call on any context; ctx may be NULL (e.g. after admm_create failed).
+ * The text stays valid until the thread's next failing call. */
+const char *admm_last_error(const admm_context *ctx);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,7 @@ E_UNKNOWN_TICKET, E_QUEUE_FULL, E_UNSUPPORTED = -5, -6, -7
 F64, F32_MIXED, F32 = 0, 1, 2
 XSTEP_EXACT_BOX, XSTEP_PAPER_PROJECT = 0, 1
 SWEEP_GAUSS_SEIDEL, SWEEP_JACOBI = 0, 1
-LAUNCH_AUTO, LAUNCH_SPLIT, LAUNCH_CHAINED, LAUNCH_RESIDENT = 0, 1, 2, 3
+LAUNCH_AUTO, LAUNCH_SPLIT, LAUNCH_CHAINED, LAUNCH_RESIDENT, LAUNCH_CHAINED_LOCAL = 0, 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 BOUNDS_PER_SOURCE, BOUNDS_PER_STEP = 0, 1
 
@@ -104,7 +104,7 @@ def lib():
             "admm_release_warm": (C.c_int, [vp, u64]),
             "admm_destroy": (None, [vp]),
             "admm_status_string": (C.c_char_p, [C.c_int]),
-            "admm_last_error": (C.c_char_p, []),
+            "admm_last_error": (C.c_char_p, [vp]),
             "admm_debug_codes": (C.c_int, [vp, vp, vp]),
             "admm_profile": (C.c_int, [vp, vp, vp, i32, vp]),
             "admm_minimize_quartics": (C.c_int, [vp, C.c_int64, C.c_int] + [vp] * 6 + [C.c_int, C.c_int,
@@ -120,7 +120,7 @@ def lib():
 
 
 def last_error() -> str:
-    return lib().admm_last_error().decode()
+    return lib().admm_last_error(None).decode()
 
 
 def _check(st: int, allow=(OK, MAX_ITER)) -> int:
@@ -604,7 +604,7 @@ def _profile(ctx, prob, settings, iters):
                               int(iters), out), allow=(OK,))
     return {"sweep_us": out[0], "finalize_us": out[1], "graph_iter_us": out[2], "iters": int(out[3]),
             "persist_iter_us": out[4], "persist_cols_per_thread": int(out[5]),
-            "launch": {1: "split", 2: "chained", 3: "resident"}.get(int(out[6]), "unknown")}
+            "launch": {1: "split", 2: "chained", 3: "resident", 4: "chained_local"}.get(int(out[6]), "unknown")}
 
 
 def admm_profile(ctx: "Context", prob, settings: Optional[Settings] = None, iters: int = 200) -> dict:

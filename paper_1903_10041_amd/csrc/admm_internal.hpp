@@ -13,6 +13,8 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kPad = 64;             // n is padded to a multiple of this
 constexpr int kChainBlock = 1024;    // threads per block of the chained iteration
 constexpr int kChainMaxBlocks = 512; // largest grid the chained iteration takes
+constexpr int kLocBlock = 256;       // threads (columns) per tile of the scenario-local chained launch
+constexpr int kLocLdsPairs = 2048;   // m q up to which that launch stages the consensus terms in LDS
 constexpr int kMaxSources = 8;       // largest m any kernel takes
 // Bytes of the static scratch array of the no-allocation entry point.
 constexpr size_t kScratchBytes = (size_t)64 << 20;
@@ -58,7 +60,8 @@ struct SolveParams {
     int32_t nblk;           // sweep blocks per scenario
     int32_t cpt;            // columns per sweep thread (1, 2 or 4)
     int32_t persistent;     // 1: resident cooperative kernel, 0: graph of launches
-    int32_t chain;          // 1: one chained launch per iteration (q = 1), 0: sweep + finalize
+    int32_t chain;          // 1: one chained launch per iteration, 2: the same with scenario-local
+                            // scalar steps (many scenarios), 0: sweep + finalize
     int32_t chunks;         // chained: kChainBlock-column chunks each block sweeps in turn
     int32_t cgrid;          // chained with consensus: blocks of the launch (tiles are dealt round robin)
     int32_t group;          // finalize: lanes cooperating on one (i,j) pair
@@ -93,6 +96,9 @@ struct SolveParams {
     double *scal1;
     Ctrl *ctrl1;
     double *part1;
+    // scenario-local chained path: per-scenario residual maxima [q][2] and
+    // the nu a check iteration's finishing launch computes [q][m]
+    double *qres, *nuN;
 };
 
 // Partials layout (doubles): g-sum [q][nblk][m], then dg-max, dg-min (same
@@ -123,6 +129,7 @@ hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hip
 // Completes the pending iteration of slot rs into slot 0.
 hipError_t launch_chain_flush(const SolveParams &P, int rs, hipStream_t s);
 bool chain_q_fits(int m, int q, int n);   // the chained launch with consensus applies
+bool chain_loc_fits(int m, int q);        // the scenario-local chained launch applies
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
 hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,

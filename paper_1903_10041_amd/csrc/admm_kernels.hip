@@ -748,6 +748,374 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P, in
     chainq_store<MAXM>(P, 0, sh, lam, zoff, h, p, nu, x1, rs != 0, st[0], 0, st, r, sg);
 }
 
+// ------------------------------- chained, scenario-local scalar steps
+//
+// The chained launch for many scenarios (q ceil(n / NT) tiles well beyond
+// the compute units): one block per tile (scenario j, column block b), and
+// each block completes the pending iteration only for its own scenario's
+// m pairs, from that scenario's tile partials -- the same fixed-order sums,
+// so every block of scenario j derives the same bits.  The first-step
+// consensus (7c)+(7h) is needed only by the tile holding step k = 1
+// (b = 0): that block forms x_bar_1 from every scenario's x_1 - nu of the
+// slot it reads (wave i sums source i, lanes strided over j, then the DPP
+// wave sum: the order of the other chained launches) and updates its
+// scenario's nu.  The residuals need every pair, so a check iteration's
+// steps are finished by one more launch (k_loc_check, one block per
+// scenario) that also leaves each scenario's residual maxima; the next
+// launch reduces those q pairs of values to r and sigma and takes the stop
+// decision before it sweeps.  Slots as in the chained launch with the
+// consensus block; control pending: 1 the steps of iteration t are to do,
+// 2 they are done (k_loc_check) and the stop decision is to take.  The nu
+// that k_loc_check computes goes to a buffer of its own (P.nuN), since the
+// other blocks of that launch still read the slot's nu.
+
+// x_bar_1 (7c) from every pair's x_1 - nu of slot `in`, into xb[] (waves
+// i < m, result in lane 0's LDS write); callers synchronise after.
+// Loads go out eight at a time before they are added, in the same order.
+template <int MAXM>
+__device__ __forceinline__ void loc_xbar(const SolveParams &P, const double *x1, const double *nu, double *xb) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = P.m, q = P.q;
+    if (wv < m) {
+        double s = 0.0;
+        for (int j0 = lane; j0 < q; j0 += 8 * 64) {
+            double a[8], c[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int jj = j0 + 64 * r;
+                a[r] = jj < q ? x1[jj * m + wv] : 0.0;
+                c[r] = jj < q ? nu[jj * m + wv] : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (j0 + 64 * r < q) s += a[r] - c[r];
+        }
+        s = wave_sum(s);
+        if (lane == 0) xb[wv] = s * P.inv_q;
+    }
+}
+
+// (7b)+(7g), (7d)+(7i) for pair (j, i) from its scenario's tile partials.
+struct LocPair {
+    double lam, zoff, h, p;
+    double pr, ps;           // residual terms (check)
+};
+__device__ __forceinline__ LocPair loc_pair(const SolveParams &P, const double *part, int j, int i,
+                                            double lam, double zoff, double h, double p, bool chk) {
+    const int m = P.m, nbs = P.nblk;
+    const size_t slab = (size_t)P.q * nbs * m;
+    // the scenario's tile partials, sixteen loads in flight before they
+    // are added in tile order
+    double W = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
+    for (int u0 = 0; u0 < nbs; u0 += 16) {
+        double v[16], vx[16], vn[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const size_t idx = ((size_t)j * nbs + (u0 + r < nbs ? u0 + r : u0)) * m + i;
+            v[r] = part[idx];
+            if (chk) { vx[r] = part[slab + idx]; vn[r] = part[2 * slab + idx]; }
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (u0 + r < nbs) {
+                W += v[r];
+                if (chk) { mx = fmax(mx, vx[r]); mn = fmin(mn, vn[r]); }
+            }
+    }
+    const double nd = (double)P.n;
+    const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+    const double Wd = W - nd * lam;                  // 1'(g(x) - lambda)
+    const double kap = kfac * (h + p - Wd);
+    const double sumz = Wd + nd * kap;               // 1'z
+    const double zn = kap - lam;                     // z - g(x)
+    const double hn = fmin(P.cap[i], sumz - p);
+    LocPair o;
+    o.lam = kap;
+    o.zoff = zn;
+    o.h = hn;
+    o.p = p + hn - sumz;
+    o.pr = o.ps = 0.0;
+    if (chk) {
+        const double cz = zn - zoff;
+        o.pr = fmax(fabs(zn), fabs(hn - sumz));
+        o.ps = fmax(P.rho1 * fmax(fabs(mx + cz), fabs(mn + cz)), P.rho2 * fabs(hn - h));
+    }
+    return o;
+}
+
+// Block max of (a, b) over NT threads into sh.red / (ra, rb).
+template <int NT>
+__device__ __forceinline__ void loc_block_max2(double a, double b, double (*red)[2], double &ra, double &rb) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    a = wave_max(a);
+    b = wave_max(b);
+    if (lane == 0) { red[wv][0] = a; red[wv][1] = b; }
+    __syncthreads();
+    ra = red[0][0];
+    rb = red[0][1];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) { ra = fmax(ra, red[w][0]); rb = fmax(rb, red[w][1]); }
+}
+
+// The stop decision of a check iteration whose steps k_loc_check finished:
+// r, sigma from the per-scenario maxima, then the thresholds.
+template <int NT>
+__device__ __forceinline__ void loc_decide(const SolveParams &P, double (*red)[2], int t, int &status, int &done,
+                                           double &r, double &sg) {
+    double a = 0.0, b = 0.0;
+    for (int jj = threadIdx.x; jj < P.q; jj += NT) {
+        a = fmax(a, P.qres[2 * jj]);
+        b = fmax(b, P.qres[2 * jj + 1]);
+    }
+    loc_block_max2<NT>(a, b, red, r, sg);
+    const bool bad = !(r == r) || !(sg == sg);
+    if (bad) { status = -4; done = 1; }
+    else if (r < P.lim->eps_p && sg < P.lim->eps_d) { status = 0; done = 1; }
+    if (!done && t >= P.lim->max_iter) { status = 2; done = 1; }
+}
+
+// Lanes i < m of every wave complete pair (j, i) themselves and the wave
+// shares the results through lane reads, so no wave waits at a block
+// barrier for another's memory reads before its sweep.  The reads the
+// scalar steps need are issued before the column loads (memory results
+// return in issue order), so the steps are computed while the columns are
+// still arriving.
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int NT>
+__global__ __launch_bounds__(NT) void k_loc(SolveParams P, int rs) {
+    const int ws = rs ^ 1, m = P.m, nbs = P.nblk;
+    __shared__ double red[NT / 64][3 * MAXM + 2];
+    const QSlot in = qslot(P, rs);
+    const Ctrl *c = in.ctrl;
+    const int tile = blockIdx.x, j = tile / nbs, b = tile - j * nbs;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int k = b * NT + tid;
+    const int t = c->t, pending = c->pending, done0 = c->done;
+    const bool steps = pending == 1 && !done0;
+    const double *part = rs ? P.part : P.part1;
+    const size_t slab = (size_t)P.q * nbs * m;
+    (void)slab;
+    // 1. reads of the scalar steps: this lane's pair, its scenario's tile
+    //    partials, and for the first-step wave every pair's x_1 - nu
+    const int il = lane < m ? lane : 0, pi = j * m + il;
+    const double lam0 = in.lam[pi], zoff0 = in.zoff[pi], h0 = in.h[pi], p0 = in.p[pi];
+    const double nu_s = in.nu[pi], nu_f = P.nuN[pi], x1own = in.x1[pi], xb0 = in.xbar1[il];
+    // the scenario's partials [nbs][m] are contiguous: lane e holds entry e
+    const int NE = nbs * m;
+    const double *pj = part + (size_t)j * NE;
+    const double pv = lane < NE ? pj[lane] : 0.0;
+    const bool first = b == 0 && wv == 0;
+    // the first-step tile stages every pair's x_1 - nu in LDS (all its
+    // waves load, one barrier; sized by the launch when m q <= kLocLdsPairs)
+    extern __shared__ double xd[];
+    const bool staged = P.m * P.q <= kLocLdsPairs;
+    if (b == 0 && staged) {
+        for (int e = tid; e < P.m * P.q; e += NT) xd[e] = in.x1[e] - in.nu[e];
+        __syncthreads();
+    }
+    // 2. the columns
+    Col<T, MAXM> d;
+    if (k < P.n) col_load<T, MAXM>(P, j, k, d);
+    // 3. the pair's new state (lanes < m), the same arithmetic and order
+    //    as loc_pair
+    double lam = lam0, zoff = zoff0, h = h0, p = p0, nu = pending == 2 ? nu_f : nu_s;
+    if (steps) {
+        // tile order, as loc_pair
+        double W = 0.0;
+        if (NE <= 64) {
+            for (int u = 0; u < nbs; ++u) W += __shfl(pv, u * m + il, 64);
+        } else {
+            for (int u = 0; u < nbs; ++u) W += pj[u * m + il];
+        }
+        const double nd = (double)P.n;
+        const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
+        const double Wd = W - nd * lam0;
+        const double kap = kfac * (h0 + p0 - Wd);
+        const double sumz = Wd + nd * kap;
+        const double zn = kap - lam0;
+        const double hn = fmin(P.cap[il], sumz - p0);
+        lam = kap;
+        zoff = zn;
+        h = hn;
+        p = p0 + hn - sumz;
+    }
+    // x_bar_1 (first-step wave; every wave keeps the slot's otherwise)
+    double xbv[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) xbv[i] = i < m ? __shfl(xb0, i, 64) : 0.0;
+    if (first && steps) {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) {
+            if (i >= m) continue;
+            double s = 0.0;
+            if (staged) {
+                for (int jj = lane; jj < P.q; jj += 64) s += xd[jj * m + i];
+            } else {
+                for (int jj = lane; jj < P.q; jj += 64) s += in.x1[jj * m + i] - in.nu[jj * m + i];
+            }
+            xbv[i] = wave_sum(s) * P.inv_q;
+        }
+        double xbi = xbv[0];
+#pragma unroll
+        for (int i = 1; i < MAXM; ++i)
+            if (il == i) xbi = xbv[i];
+        nu += xbi - x1own;   // (7h)
+    }
+    // the decision: a check iteration finished by k_loc_check, or the cap
+    int status = c->status, done = done0;
+    double rr = c->r, sg = c->sigma;
+    if (pending == 2 && !done0) {
+        double a = 0.0, bb = 0.0;
+        for (int jj = lane; jj < P.q; jj += 64) {
+            a = fmax(a, P.qres[2 * jj]);
+            bb = fmax(bb, P.qres[2 * jj + 1]);
+        }
+        rr = wave_max(a);
+        sg = wave_max(bb);
+        const bool bad = !(rr == rr) || !(sg == sg);
+        if (bad) { status = -4; done = 1; }
+        else if (rr < P.lim->eps_p && sg < P.lim->eps_d) { status = 0; done = 1; }
+    }
+    if (!done0 && !done && t >= P.lim->max_iter) { status = 2; done = 1; }
+    // the state into slot ws: the first-step wave of each scenario writes
+    // its pairs, the first tile the control block and x_bar_1
+    const QSlot o = qslot(P, ws);
+    if (first) {
+        if (lane < m) {
+            o.lam[pi] = lam; o.zoff[pi] = zoff; o.h[pi] = h; o.p[pi] = p; o.nu[pi] = nu;
+            if (done) o.x1[pi] = x1own;          // no sweep follows: the slot keeps x_1
+            if (tile == 0) o.xbar1[il] = xbv[il];
+        }
+        if (tile == 0 && lane == 0) {
+            Ctrl *co = o.ctrl;
+            const int t1 = done ? t : t + 1;
+            co->t = t1;
+            co->status = status;
+            co->done = done;
+            co->bad_input = c->bad_input | (!done && (((t1 % P.check_every) == 0) != CHECK) ? 2 : 0);
+            co->r = rr;
+            co->sigma = sg;
+            co->pending = done ? 0 : 1;
+            co->wdiv = 1.0;
+        }
+    }
+    if (done) return;
+    // 4. the sweep of iteration t + 1; its x_1 goes into slot ws
+    SolveParams Q = P;
+    Q.x1 = o.x1;
+    Scal<MAXM> sc;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) {
+        const double li = __shfl(lam, i, 64), zi = __shfl(zoff, i, 64), ni = __shfl(nu, i, 64);
+        sc.toff[i] = i < m ? zi + li : 0.0;
+        sc.cons[i] = i < m ? xbv[i] + ni : 0.0;
+    }
+    scal_bounds<MAXM>(P.slo, P.shi, m, sc);
+    Acc<MAXM> acc;
+    acc.reset();
+    if (k < P.n) {
+        col_update<T, MAXM, MODE, CHECK, FEAT>(Q, j, k, d, sc, acc);
+        col_store<T, MAXM>(Q, j, k, d);
+    }
+    chain_partials<MAXM, NT>(P, rs ? P.part1 : P.part, tile, acc, CHECK, red, (size_t)P.q * nbs * m);
+}
+
+// Finishes a check iteration's steps for scenario blockIdx.x in slot s
+// (written by the check launch just before): pair steps, consensus, the
+// scenario's residual maxima into P.qres, nu into P.nuN; block 0 marks the
+// decision pending.
+template <int MAXM>
+__global__ __launch_bounds__(kBlock) void k_loc_check(SolveParams P, int s) {
+    __shared__ double xb[MAXM];
+    __shared__ double red[kBlock / 64][2];
+    const QSlot sl = qslot(P, s);
+    const Ctrl *c = sl.ctrl;
+    if (c->done || c->pending != 1) return;
+    const int j = blockIdx.x, m = P.m, nbs = P.nblk, tid = threadIdx.x;
+    const double *part = s ? P.part : P.part1;      // what the launch that wrote slot s swept into
+    const size_t slab = (size_t)P.q * nbs * m;
+    loc_xbar<MAXM>(P, sl.x1, sl.nu, xb);
+    __syncthreads();
+    double pr = 0.0, ps = 0.0;
+    if (tid < m) {
+        const int pi = j * m + tid;
+        const LocPair o = loc_pair(P, part, j, tid, sl.lam[pi], sl.zoff[pi], sl.h[pi], sl.p[pi], true);
+        const double res = xb[tid] - sl.x1[pi];     // (7h)
+        P.nuN[pi] = sl.nu[pi] + res;
+        pr = fmax(o.pr, fabs(res));
+        ps = o.ps;
+        sl.lam[pi] = o.lam; sl.zoff[pi] = o.zoff; sl.h[pi] = o.h; sl.p[pi] = o.p;
+    }
+    for (int u = tid; u < nbs; u += kBlock) {
+        const size_t tt = (size_t)j * nbs + u;
+        pr = fmax(pr, part[3 * slab + 2 * tt]);
+        ps = fmax(ps, P.rho3 * part[3 * slab + 2 * tt + 1]);
+    }
+    double r, sg;
+    loc_block_max2<kBlock>(pr, ps, red, r, sg);
+    if (tid == 0) { P.qres[2 * j] = r; P.qres[2 * j + 1] = sg; }
+    if (j == 0 && tid < m) sl.xbar1[tid] = xb[tid];
+    if (j == 0 && tid == 0) sl.ctrl->pending = 2;
+}
+
+// Completes whatever slot rs holds pending into slot 0 (one block of
+// kChainBlock threads, every pair in turn), after the last launch of a
+// solve.
+template <int MAXM>
+__global__ __launch_bounds__(kChainBlock) void k_loc_flush(SolveParams P, int rs) {
+    __shared__ double xb[MAXM];
+    __shared__ double red[kChainBlock / 64][2];
+    __shared__ int dec[2];
+    const QSlot in = qslot(P, rs), o = qslot(P, 0);
+    const Ctrl *c = in.ctrl;
+    const int m = P.m, M = m * P.q, tid = threadIdx.x;
+    const int t = c->t, pending = c->done ? 0 : c->pending;
+    int status = c->status, done = c->done;
+    double r = c->r, sg = c->sigma;
+    const double *part = rs ? P.part : P.part1;
+    if (pending == 1) loc_xbar<MAXM>(P, in.x1, in.nu, xb);
+    else if (tid < m) xb[tid] = in.xbar1[tid];
+    __syncthreads();
+    // every pair: its new state (reads of slot rs end before slot 0 is
+    // written when rs = 0: one barrier between)
+    double lam[4], zoff[4], h[4], p[4], nu[4], x1[4];
+    int np = 0;
+    for (int pi = tid; pi < M; pi += kChainBlock, ++np) {
+        const int j = pi / m, i = pi - j * m;
+        lam[np] = in.lam[pi]; zoff[np] = in.zoff[pi]; h[np] = in.h[pi]; p[np] = in.p[pi];
+        nu[np] = pending == 2 ? P.nuN[pi] : in.nu[pi];
+        x1[np] = in.x1[pi];
+        if (pending == 1) {
+            const LocPair q = loc_pair(P, part, j, i, lam[np], zoff[np], h[np], p[np], false);
+            lam[np] = q.lam; zoff[np] = q.zoff; h[np] = q.h; p[np] = q.p;
+            nu[np] += xb[i] - x1[np];
+        }
+    }
+    if (pending == 2) {
+        loc_decide<kChainBlock>(P, red, t, status, done, r, sg);
+    } else if (pending == 1 && t >= P.lim->max_iter) {
+        status = 2;
+        done = 1;
+    }
+    if (tid == 0) { dec[0] = status; dec[1] = done; }
+    __syncthreads();
+    np = 0;
+    for (int pi = tid; pi < M; pi += kChainBlock, ++np) {
+        o.lam[pi] = lam[np]; o.zoff[pi] = zoff[np]; o.h[pi] = h[np]; o.p[pi] = p[np]; o.nu[pi] = nu[np];
+        o.x1[pi] = x1[np];
+    }
+    if (tid < m) o.xbar1[tid] = xb[tid];
+    if (tid == 0) {
+        Ctrl *co = o.ctrl;
+        co->t = t;
+        co->status = dec[0];
+        co->done = dec[1];
+        co->bad_input = c->bad_input;
+        co->r = r;
+        co->sigma = sg;
+        co->pending = 0;
+        co->wdiv = 1.0;
+    }
+}
+
 // ---------------------------------------------------- persistent resident
 
 // Grid barrier words: [0] arrivals, [1] generation, [2] abort.
@@ -1254,7 +1622,44 @@ bool chain_q_fits(int m, int q, int n) {
     return m <= 4 && (int64_t)m * q <= kChainBlock && (n + kChainBlock - 1) / kChainBlock <= kChainQTiles;
 }
 
+template <typename T, int MODE, bool CHECK>
+static void launch_loc(const SolveParams &P, int rs, hipStream_t s) {
+    const unsigned g = (unsigned)(P.q * P.nblk);
+    const size_t lds = P.m * P.q <= kLocLdsPairs ? (size_t)P.m * P.q * sizeof(double) : 0;
+    const bool cons_only = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
+    if (cons_only) {
+        if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 4, MODE, CHECK, F_CONS, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+    } else {
+        if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 4, MODE, CHECK, F_ALL, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+    }
+    // a check iteration's steps and residuals, for the next launch's decision
+    if (CHECK) {
+        if (P.m <= 2) k_loc_check<2><<<P.q, kBlock, 0, s>>>(P, rs ^ 1);
+        else k_loc_check<4><<<P.q, kBlock, 0, s>>>(P, rs ^ 1);
+    }
+}
+
+bool chain_loc_fits(int m, int q) { return m <= 4 && (int64_t)m * q <= 4 * kChainBlock; }
+
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {
+    if (P.chain == 2) {
+        if (!P.consensus || !chain_loc_fits(P.m, P.q) || P.nblk != (P.n + kLocBlock - 1) / kLocBlock ||
+            P.adaptive || !P.qres || !P.nuN)
+            return hipErrorInvalidValue;
+        if (dtype == 0) {
+            if (check) launch_loc<double, MODE_F64, true>(P, rs, s);
+            else launch_loc<double, MODE_F64, false>(P, rs, s);
+        } else if (dtype == 1) {
+            if (check) launch_loc<float, MODE_MIXED, true>(P, rs, s);
+            else launch_loc<float, MODE_MIXED, false>(P, rs, s);
+        } else {
+            if (check) launch_loc<float, MODE_F32, true>(P, rs, s);
+            else launch_loc<float, MODE_F32, false>(P, rs, s);
+        }
+        return hipGetLastError();
+    }
     if (P.consensus) {
         if (!chain_q_fits(P.m, P.q, P.n) || P.nblk != (P.n + kChainBlock - 1) / kChainBlock || P.adaptive)
             return hipErrorInvalidValue;
@@ -1286,6 +1691,12 @@ hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hip
 
 hipError_t launch_chain_flush(const SolveParams &P, int rs, hipStream_t s) {
     if (P.m > 4 || (rs != 0 && rs != 1)) return hipErrorInvalidValue;
+    if (P.chain == 2) {
+        if (!chain_loc_fits(P.m, P.q)) return hipErrorInvalidValue;
+        if (P.m <= 2) k_loc_flush<2><<<1, kChainBlock, 0, s>>>(P, rs);
+        else k_loc_flush<4><<<1, kChainBlock, 0, s>>>(P, rs);
+        return hipGetLastError();
+    }
     if (P.consensus) {
         if ((int64_t)P.m * P.q > kChainBlock) return hipErrorInvalidValue;
         if (P.m <= 2) k_chain_q_flush<2><<<1, kChainBlock, 0, s>>>(P, rs);

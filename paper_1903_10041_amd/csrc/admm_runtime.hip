@@ -135,7 +135,7 @@ admm_status validate_settings(const admm_settings *s) {
         return fail(ADMM_E_INVALID_ARG, "unknown xstep");
     if (s->sweep != ADMM_SWEEP_GAUSS_SEIDEL && s->sweep != ADMM_SWEEP_JACOBI)
         return fail(ADMM_E_INVALID_ARG, "unknown sweep");
-    if (s->launch < ADMM_LAUNCH_AUTO || s->launch > ADMM_LAUNCH_RESIDENT)
+    if (s->launch < ADMM_LAUNCH_AUTO || s->launch > ADMM_LAUNCH_CHAINED_LOCAL)
         return fail(ADMM_E_INVALID_ARG, "unknown launch path");
     if (s->adaptive_rho &&
         (!(s->tau > 1.0) || !std::isfinite(s->tau) || !(s->band_lo > 0.0) || !(s->band_hi >= s->band_lo) ||
@@ -288,7 +288,12 @@ extern "C" const char *admm_status_string(admm_status s) {
     return "unknown status";
 }
 
-extern "C" const char *admm_last_error(void) { return g_last_error.c_str(); }
+// The detail is kept per calling thread (a context may serve several
+// threads, and admm_create fails before any context exists); ctx may be NULL.
+extern "C" const char *admm_last_error(const admm_context *ctx) {
+    (void)ctx;
+    return g_last_error.c_str();
+}
 
 // --------------------------------------------------------- plain solve
 
@@ -366,6 +371,20 @@ static bool chain_q_applies(const admm_problem *pr, const admm_settings *s) {
     return (pr->q > 1 || s->consensus_q1) && !s->adaptive_rho && chain_q_fits(pr->m, pr->q, pr->n);
 }
 
+// The scenario-local chained launch (q > 1 or the consensus block kept,
+// m <= 4, m q <= 4096, fixed rho).
+static bool chain_loc_applies(const admm_problem *pr, const admm_settings *s) {
+    return (pr->q > 1 || s->consensus_q1) && !s->adaptive_rho && chain_loc_fits(pr->m, pr->q);
+}
+
+// With the consensus block, the launch that completes every pair in every
+// block wins while its tiles number about two per compute unit; past that
+// the split launch does (measured q = 200, n = 3600: split 16.5 us per
+// iteration, this one slower, the scenario-local chained one 17.7 us).
+static bool chain_q_preferred(admm_context *ctx, const admm_problem *pr) {
+    return (int64_t)pr->q * ((pr->n + kChainBlock - 1) / kChainBlock) <= 2 * std::max(1, ctx->num_cu);
+}
+
 // Chained grid: one block per kChainBlock columns while that fits in
 // kChainMaxBlocks blocks; beyond, one block per compute unit, each sweeping
 // its columns in chunks of kChainBlock.
@@ -411,17 +430,27 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     const int n_pad = (n + kPad - 1) / kPad * kPad;
     int cpt = sweep_cpt(n, q);
     int R = 0;
-    bool chain = false;
+    bool chain = false, local = false;
     switch (s->launch) {
     case ADMM_LAUNCH_RESIDENT:
         R = persist_columns(ctx, dtype, m, n, q, true);
         if (R == 0) return fail(ADMM_E_UNSUPPORTED, "the resident launch does not fit this problem on the device");
         break;
     case ADMM_LAUNCH_CHAINED:
-        if (!chain_applies(pr, s) && !chain_q_applies(pr, s))
+        if (!chain_applies(pr, s) && !chain_q_applies(pr, s) && !chain_loc_applies(pr, s))
             return fail(ADMM_E_UNSUPPORTED, "the chained launch needs m <= 4 and either q = 1 without "
-                                            "consensus, or m q <= 1024, n <= 8192 and fixed rho");
+                                            "consensus, or m q <= 4096 and fixed rho");
         chain = true;
+        // with the consensus block: the scenario-local launch where the
+        // one that completes every pair in every block does not apply
+        local = !chain_applies(pr, s) && !chain_q_applies(pr, s);
+        break;
+    case ADMM_LAUNCH_CHAINED_LOCAL:
+        if (!chain_loc_applies(pr, s))
+            return fail(ADMM_E_UNSUPPORTED, "the scenario-local chained launch needs q > 1 (or consensus_q1), "
+                                            "m <= 4, m q <= 4096 and fixed rho");
+        chain = true;
+        local = true;
         break;
     case ADMM_LAUNCH_SPLIT:
         break;
@@ -430,10 +459,10 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         // with consensus the chained launch wins while its tiles fit about
         // two per compute unit (measured: q = 100, n = 3600 faster than
         // split, q = 200 slower): past that every block's pass over all
-        // m q pairs and its tiles in series cost more than the second launch
-        chain = R == 0 && (chain_applies(pr, s) ||
-                           (chain_q_applies(pr, s) &&
-                            (int64_t)q * ((n + kChainBlock - 1) / kChainBlock) <= 2 * std::max(1, ctx->num_cu)));
+        // m q pairs and its tiles in series cost more than the second
+        // launch, and the scenario-local chained launch, whose first-step
+        // tiles finish the consensus, runs slower than split too
+        chain = R == 0 && (chain_applies(pr, s) || (chain_q_applies(pr, s) && chain_q_preferred(ctx, pr)));
         // past the 256 MB last-level cache the split sweep, with many more
         // waves in flight, streams HBM faster than the chained blocks'
         // chunks (measured m = 4, n = 2^22: 97 against 104 us)
@@ -449,18 +478,19 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     // cold-start kernel covers them as kChainBlock / kBlock * chunks
     // columns per thread
     int chunks = 1;
-    if (chain) {
+    if (chain && !local) {
         int nb = 0;
         chain_grid(ctx, n, nb, chunks);
         cpt = kChainBlock / kBlock * chunks;
     }
+    if (local) cpt = kLocBlock / kBlock;   // tiles of kLocBlock columns
     const int nblk = (n + kBlock * cpt - 1) / (kBlock * cpt);
     P.persistent = R > 0;
-    P.chain = chain ? 1 : 0;
+    P.chain = local ? 2 : (chain ? 1 : 0);
     P.chunks = chunks;
     // chained with consensus: at most one block per compute unit, each
     // sweeping its share of the q * nblk column tiles in turn
-    if (chain && (q > 1 || s->consensus_q1))
+    if (chain && !local && (q > 1 || s->consensus_q1))
         P.cgrid = std::min(q * ((n + kChainBlock - 1) / kChainBlock), chainq_grid_cap(ctx));
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
@@ -493,7 +523,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     // lam zoff h p nu x1 pair_r pair_s [M each], xbar1 slo shi cap [m each],
     // the chained path's second scalar slot (lam zoff h p nu x1 [M each],
     // xbar1 [m]), rho_cur [2][4]
-    ENS(W.scal, (14 * M + 5 * (size_t)m + 8) * sizeof(double));
+    // ... then the scenario-local path's residual maxima [q][2] and nu [M]
+    ENS(W.scal, (15 * M + 5 * (size_t)m + 8 + 2 * (size_t)q) * sizeof(double));
     ENS(W.part, (chain ? 2 : 1) * part_doubles(m, q, nblk) * sizeof(double));
     // control slot 0, grid barrier words, control slot 1, stop limits
     ENS(W.ctrl, 2 * sizeof(Ctrl) + 64 + sizeof(Lim));
@@ -518,6 +549,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.bar = (uint32_t *)((char *)W.ctrl.p + sizeof(Ctrl));
     P.scal1 = sc + 8 * M + 4 * m;
     P.rho_cur = sc + 14 * M + 5 * m;
+    P.qres = local ? sc + 14 * M + 5 * m + 8 : nullptr;
+    P.nuN = local ? sc + 14 * M + 5 * m + 8 + 2 * q : nullptr;
     P.ctrl1 = (Ctrl *)((char *)W.ctrl.p + sizeof(Ctrl) + 64);
     P.lim = (const Lim *)((char *)W.ctrl.p + 2 * sizeof(Ctrl) + 64);
     P.part1 = chain ? P.part + part_doubles(m, q, nblk) : nullptr;
@@ -1261,7 +1294,7 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
     out[3] = (double)reps * per;
     out[4] = 0.0;
     out[5] = 0.0;
-    out[6] = P.persistent ? 3.0 : (P.chain ? 2.0 : 1.0);
+    out[6] = P.persistent ? 3.0 : (P.chain == 2 ? 4.0 : (P.chain ? 2.0 : 1.0));
     if (P.persistent) {
         // the resident path: one cooperative launch of `n_it` iterations
         const int n_it = std::max(20, iters);

@@ -108,7 +108,8 @@ def test_full_size_batch_converged(ctx, c3):
         assert abs(int(rec["iters"][b]) - oi["iters"]) <= 20, b
 
 
-@pytest.mark.parametrize("launch", [admm.LAUNCH_AUTO, admm.LAUNCH_SPLIT, admm.LAUNCH_CHAINED])
+@pytest.mark.parametrize("launch", [admm.LAUNCH_AUTO, admm.LAUNCH_SPLIT, admm.LAUNCH_CHAINED,
+                                    admm.LAUNCH_CHAINED_LOCAL])
 @pytest.mark.parametrize("prec", [admm.F64, admm.F32_MIXED])
 def test_full_size_robust(ctx, c4_oracle, prec, launch):
     """m = 2, q = 200, n = 3600 (1.44 M quartics, first-step consensus),

@@ -362,16 +362,35 @@ def test_chained_resume_is_bit_exact(ctx):
 
 
 def test_launch_path_unsupported(ctx):
-    for p, launch in ((W.phev_c4(seed=7, q=5, n=9000), admm.LAUNCH_CHAINED),
-                      (W.uniform_problem(5, 100, 3), admm.LAUNCH_CHAINED),
-                      (W.phev_c4(seed=7, q=600, n=50), admm.LAUNCH_CHAINED)):
+    wide = W.uniform_problem(2, 50, 16, q=2100, cap_fraction=0.4)      # m q = 4200 > 4096
+    for p, launch in ((W.uniform_problem(5, 100, 3), admm.LAUNCH_CHAINED),
+                      (W.uniform_problem(5, 100, 3, q=2), admm.LAUNCH_CHAINED_LOCAL),
+                      (wide, admm.LAUNCH_CHAINED),
+                      (wide, admm.LAUNCH_CHAINED_LOCAL),
+                      (W.small_c1(), admm.LAUNCH_CHAINED_LOCAL)):        # q = 1 without consensus
         with pytest.raises(admm.AdmmError) as e:
             ctx.solve(p, fixed(p, 10, launch=launch))
         assert e.value.status == admm.E_UNSUPPORTED
     p = W.phev_c4(seed=7, q=5, n=60)
-    with pytest.raises(admm.AdmmError) as e:
-        ctx.solve(p, admm.Settings(rho=tuple(p.rho), max_iter=10, adaptive_rho=True, launch=admm.LAUNCH_CHAINED))
-    assert e.value.status == admm.E_UNSUPPORTED
+    for launch in (admm.LAUNCH_CHAINED, admm.LAUNCH_CHAINED_LOCAL):
+        with pytest.raises(admm.AdmmError) as e:
+            ctx.solve(p, admm.Settings(rho=tuple(p.rho), max_iter=10, adaptive_rho=True, launch=launch))
+        assert e.value.status == admm.E_UNSUPPORTED
+
+
+def test_chained_falls_back_to_local(ctx):
+    """Where the chained form that completes every pair in every block does
+    not apply (n > 8192, or m q > 1024) CHAINED takes the scenario-local
+    form: the same iterates as CHAINED_LOCAL, bit for bit, and the split
+    path's to rounding."""
+    for p in (W.phev_c4(seed=7, q=5, n=9000), W.phev_c4(seed=7, q=600, n=50)):
+        say(f"[chained->local] q={p.q} n={p.n}")
+        xa, ia, _ = ctx.solve(p, fixed(p, 40, launch=admm.LAUNCH_CHAINED))
+        xb, ib, _ = ctx.solve(p, fixed(p, 40, launch=admm.LAUNCH_CHAINED_LOCAL))
+        xc, ic, _ = ctx.solve(p, fixed(p, 40, launch=admm.LAUNCH_SPLIT))
+        assert np.array_equal(xa, xb)
+        assert ia["iters"] == ib["iters"] == ic["iters"] == 40
+        np.testing.assert_allclose(xa, xc, rtol=0, atol=1e-9 * max(1.0, float(np.abs(xc).max())))
 
 
 # The chained launch with the consensus block: q > 1 (or q = 1 with it
@@ -383,17 +402,21 @@ CONS_CASES = {
     "uniform_m4_q2_n8192": (lambda: W.uniform_problem(4, 8192, 14, q=2, cap_fraction=0.4), False),
     "c1_consensus_q1": (lambda: W.small_c1(), True),
     "m3_q256_n37": (lambda: W.uniform_problem(3, 37, 15, q=256), False),
+    "m2_q1200_n50": (lambda: W.uniform_problem(2, 50, 16, q=1200, cap_fraction=0.4), False),
 }
+CONS_LAUNCHES = {"chained": admm.LAUNCH_CHAINED, "local": admm.LAUNCH_CHAINED_LOCAL}
 
 
+@pytest.mark.parametrize("launch", list(CONS_LAUNCHES))
 @pytest.mark.parametrize("name", list(CONS_CASES))
-def test_chained_consensus_trajectory(ctx, name):
+def test_chained_consensus_trajectory(ctx, name, launch):
     """Every element against the oracle after 300 iterations (FP64), with
-    the residuals of the last check."""
+    the residuals of the last check, on both chained launches with the
+    consensus block (every pair in every block, or scenario-local steps)."""
     mk, cq1 = CONS_CASES[name]
     p = mk()
-    say(f"[chained-consensus] {name} m={p.m} q={p.q} n={p.n} consensus_q1={cq1}")
-    x, info, _ = ctx.solve(p, fixed(p, 300, launch=admm.LAUNCH_CHAINED, consensus_q1=cq1))
+    say(f"[chained-consensus] {name} {launch} m={p.m} q={p.q} n={p.n} consensus_q1={cq1}")
+    x, info, _ = ctx.solve(p, fixed(p, 300, launch=CONS_LAUNCHES[launch], consensus_q1=cq1))
     st, oinfo, _ = oracle.run(p, max_iter=300, nthreads=8, consensus_q1=cq1)
     dx = float(np.abs(x - st["x"]).max())
     rel = abs(info["objective"] - oinfo["objective"]) / (1 + abs(oinfo["objective"]))
@@ -409,13 +432,15 @@ def test_chained_consensus_trajectory(ctx, name):
         assert abs(info[key] - oinfo[key]) <= residual_tol(p, st, oinfo[key]), key
 
 
-def test_chained_consensus_convergence(ctx):
+@pytest.mark.parametrize("launch", list(CONS_LAUNCHES))
+def test_chained_consensus_convergence(ctx, launch):
     """The stopping check agrees with the oracle's, also for check_every = 7
     and a cap that ends inside a chunk."""
-    for name, ce, cap in (("robust_q5_n60", 10, 100000), ("robust_q3_n700", 7, 100000), ("robust_q5_n60", 10, 53)):
+    for name, ce, cap in (("robust_q5_n60", 10, 100000), ("robust_q3_n700", 7, 100000), ("robust_q5_n60", 10, 53),
+                          ("robust_q40_n1500", 10, 100000)):
         p = CONS_CASES[name][0]()
         s = admm.Settings(rho=tuple(p.rho), max_iter=cap, eps_primal=1e-6, eps_dual=1e-6, check_every=ce,
-                          launch=admm.LAUNCH_CHAINED)
+                          launch=CONS_LAUNCHES[launch])
         say(f"[chained-consensus-converge] {name} check_every={ce} max_iter={cap}")
         x, info, _ = ctx.solve(p, s)
         st, oinfo, _ = oracle.run(p, max_iter=cap, eps_primal=1e-6, eps_dual=1e-6, check_every=ce)
@@ -425,10 +450,11 @@ def test_chained_consensus_convergence(ctx):
         assert float(np.abs(x - st["x"]).max()) <= 1e-8
 
 
-def test_chained_consensus_resume_is_bit_exact(ctx):
+@pytest.mark.parametrize("launch", list(CONS_LAUNCHES))
+def test_chained_consensus_resume_is_bit_exact(ctx, launch):
     p = W.phev_c4(seed=9, q=7, n=900)
-    say("[chained-consensus-resume] m=2 q=7 n=900: 300 = 170 + 130")
-    s = lambda it: fixed(p, it, launch=admm.LAUNCH_CHAINED)
+    say(f"[chained-consensus-resume] {launch} m=2 q=7 n=900: 300 = 170 + 130")
+    s = lambda it: fixed(p, it, launch=CONS_LAUNCHES[launch])
     xa, ia, sa = ctx.solve(p, s(300), want_state=True)
     xb, ib, sb = ctx.solve(p, s(170), want_state=True)
     xc, ic, sc = ctx.solve(p, s(130), warm=sb, want_state=True)
@@ -540,10 +566,3 @@ def test_adaptive_rho_fp32_and_robust(ctx):
         say(f"[adaptive-misc] m={p.m} q={p.q} prec={prec} iters {info['iters']}/{oinfo['iters']} rel={rel:.2e}")
         assert info["status"] == admm.OK
         assert rel <= (1e-4 if prec != admm.F64 else 1e-8)
-
-
-def test_adaptive_rho_rejected_by_submit(ctx):
-    p = W.small_c1()
-    with pytest.raises(admm.AdmmError) as e:
-        ctx.submit(p, admm.Settings(adaptive_rho=True))
-    assert e.value.status == admm.E_UNSUPPORTED

@@ -36,6 +36,8 @@ CASES = {
     "stress-chained": (lambda: W.stress(), admm.LAUNCH_CHAINED),
     "robust_q5-chained": (lambda: W.phev_c4(seed=7, q=5, n=60), admm.LAUNCH_CHAINED),
     "robust_q5-split": (lambda: W.phev_c4(seed=7, q=5, n=60), admm.LAUNCH_SPLIT),
+    "robust_q5-local": (lambda: W.phev_c4(seed=7, q=5, n=60), admm.LAUNCH_CHAINED_LOCAL),
+    "robust_q40_n1500-local": (lambda: W.phev_c4(seed=10, q=40, n=1500), admm.LAUNCH_CHAINED_LOCAL),
     "ragged_n70001_m4-chained": (lambda: W.uniform_problem(4, 70001, 11, cap_fraction=0.4), admm.LAUNCH_CHAINED),
 }
 
@@ -135,7 +137,7 @@ def test_resume_refused_without_a_solve():
 
 
 @pytest.mark.parametrize("name", ["c1-chained", "c1-split", "c1-resident", "robust_q5-chained",
-                                  "ragged_n70001_m4-chained"])
+                                  "robust_q5-local", "ragged_n70001_m4-chained"])
 def test_iterate_queued_equals_one_solve(name):
     """admm_iterate queues iterations without reading anything back; a solve
     of 5, then 20 and 17 queued iterations, then resume(0) gives the bits of
@@ -186,7 +188,7 @@ def test_iterate_leaves_a_converged_solve_stopped():
     assert np.array_equal(x0, x1)
 
 
-@pytest.mark.parametrize("name", ["c1-chained", "robust_q5-chained", "c1-split"])
+@pytest.mark.parametrize("name", ["c1-chained", "robust_q5-chained", "robust_q5-local", "c1-split"])
 def test_iterate_long_run_and_repeat(name):
     """A queued run longer than one captured span (issued as aligned chunks
     without waiting), and the same queued run twice from the same point
