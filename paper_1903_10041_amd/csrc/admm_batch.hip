@@ -162,17 +162,23 @@ static admm_status batch_state(admm_context *ctx, BatchState *&bs) {
     return ADMM_OK;
 }
 
+// Teardown in dependency order: the class streams drain, then the captured
+// graph that names the buffers and streams goes, then the streams and
+// events, and only then the device buffers.
 void batch_release(admm_context *ctx) {
     BatchState *bs = ctx->batch;
     if (!bs) return;
-    for (DevBuf *b : {&bs->coef, &bs->x, &bs->y, &bs->w, &bs->pool, &bs->inst, &bs->order, &bs->next, &bs->bad,
-                      &bs->src, &bs->stage, &bs->outp})
-        ctx->arena.release(*b);
+    for (auto s : bs->cs)
+        if (s) (void)hipStreamSynchronize(s);
     if (bs->gexec) (void)hipGraphExecDestroy(bs->gexec);
+    bs->gexec = nullptr;
     for (auto s : bs->cs)
         if (s) (void)hipStreamDestroy(s);
     for (auto e : bs->ev)
         if (e) (void)hipEventDestroy(e);
+    for (DevBuf *b : {&bs->coef, &bs->x, &bs->y, &bs->w, &bs->pool, &bs->inst, &bs->order, &bs->next, &bs->bad,
+                      &bs->src, &bs->stage, &bs->outp})
+        ctx->arena.release(*b);
     delete bs;
     ctx->batch = nullptr;
 }

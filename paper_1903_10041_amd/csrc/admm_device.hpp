@@ -443,15 +443,58 @@ __device__ __forceinline__ double block_max(double v, double *lds) {
 // the consensus (7c)+(7h), the residuals on check iterations and the stop
 // flag.  Sums over tiles run in a fixed order.  With LDS (M <= kFinalLdsPairs)
 // the per-pair values the later phases need (x_1, nu and the residual terms)
-// stay in shared memory, and every global read is issued in the first phase,
-// so the block waits for memory once instead of once per phase.
+// stay in shared memory.  CK = 0 / 1: the launch states whether the
+// iteration checks (as it chose the sweep's variant), so every read of the
+// first pass of pairs (the first kFinalChunk tiles' partials, the pair
+// state, x_1 and nu), the tiles' residual partials and the stop limits are
+// issued before the control block is used and the block waits for memory
+// once, not once per dependent step; CK < 0: the iteration counter decides.
+// GUARD: the block reads the stop flag itself (with those reads) and returns
+// when it is set.
 constexpr int kFinalLdsPairs = 1024;
+constexpr int kFinalChunk = 8;
 
-template <int NT = kBlock, bool LDS = false>
+// One double at element offset e of a buffer whose byte size fits 32 bits
+// (the offset then rides in one VGPR beside a scalar base).
+__device__ __forceinline__ double ld32(const double *base, unsigned e) {
+    return *(const double *)((const char *)base + e * 8u);
+}
+
+// The reads of one pair's first kFinalChunk * G tiles and its state.
+struct FinPair {
+    double v[kFinalChunk], vx[kFinalChunk], vn[kFinalChunk];
+    double lam, zoff, h, p, x1, nu, cap;
+};
+
+__device__ __forceinline__ void fin_pair_load(const SolveParams &P, int pi, int gl, int G, bool check,
+                                              FinPair &a) {
+    const int m = P.m, nblk = P.nblk;
+    const int M = m * P.q;
+    const int pc = pi < M ? pi : 0, j = pc / m, i = pc - j * m;
+    const unsigned slab = (unsigned)P.q * nblk * m;
+    const double *pg = P.part, *pmax = P.part + slab, *pmin = P.part + 2 * (size_t)slab;
+#pragma unroll
+    for (int u = 0; u < kFinalChunk; ++u) {
+        const int bb = gl + u * G;
+        const unsigned e = ((unsigned)j * nblk + (bb < nblk ? bb : 0)) * m + i;
+        a.v[u] = ld32(pg, e);
+        if (check) {
+            a.vx[u] = ld32(pmax, e);
+            a.vn[u] = ld32(pmin, e);
+        }
+    }
+    a.lam = P.lam[pc];
+    a.zoff = P.zoff[pc];
+    a.h = P.h[pc];
+    a.p = P.p[pc];
+    a.cap = P.cap[i];
+    a.x1 = P.consensus ? P.x1[pc] : 0.0;
+    a.nu = P.consensus ? P.nu[pc] : 0.0;
+}
+
+template <int NT = kBlock, bool LDS = false, bool GUARD = false, int CK = -1>
 __device__ inline void finalize_body(const SolveParams &P) {
     Ctrl *ctrl = P.ctrl;
-    const int t1 = ctrl->t + 1;
-    const bool check = (t1 % P.check_every) == 0;
     const int m = P.m, q = P.q, M = m * q, nblk = P.nblk, G = P.group;
     const int tid = threadIdx.x, gl = tid & (G - 1), gid = tid / G, ngroups = NT / G;
     const size_t slab = (size_t)q * nblk * m;
@@ -464,34 +507,40 @@ __device__ inline void finalize_body(const SolveParams &P) {
     __shared__ double s_gw[NT / 64][3];
     double *pair_r = LDS ? s_pr : P.pair_r, *pair_s = LDS ? s_ps : P.pair_s;
 
-    // residual partials of the tiles (checks only), read up front
+    // t, status and done in one read (the block's first 16 bytes)
+    const int4 c4 = *(const int4 *)ctrl;
+    const int t1 = c4.x + 1, done_in = c4.z;
+    const double eps_p = P.lim->eps_p, eps_d = P.lim->eps_d;
+    const int max_iter = P.lim->max_iter;
+    const bool check = CK < 0 ? (t1 % P.check_every) == 0 : CK != 0;
+    FinPair a;
+    fin_pair_load(P, gid, gl, G, check, a);
+    // a compiler barrier: the reads above stay issued before the test
+    // rather than being moved into the code that uses them
+    asm volatile("" ::: "memory");
+    if (GUARD && done_in) return;
+    bool stopped = done_in != 0;
     const int nres = q * nblk;
-    double ra[4], rc[4];
-    const bool res_here = check && tid < nres;
-    if (res_here) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int bb = tid + u * NT < nres ? tid + u * NT : tid;
-            ra[u] = pr[2 * bb];
-            rc[u] = pr[2 * bb + 1];
-        }
-    }
 
     for (int base = 0; base < M; base += ngroups) {
         const int pi = base + gid;
         const bool active = pi < M;
         const int j = active ? pi / m : 0, i = active ? pi % m : 0;
-        double x1v = 0.0, nuv = 0.0;
-        if (LDS && P.consensus && active && gl == 0) {
-            x1v = P.x1[pi];
-            nuv = P.nu[pi];
-        }
+        if (base > 0) fin_pair_load(P, pi, gl, G, check, a);
         double s = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
         if (active) {
-            // eight partials loaded before they are summed, in the same
-            // ascending order, so the loads overlap and the sum is unchanged
-            constexpr int U = 8;
-            for (int b0 = gl; b0 < nblk; b0 += U * G) {
+            // the first chunk from the reads above; later ones (more than
+            // kFinalChunk * G tiles) loaded four at a time before they are
+            // summed, in the same ascending order
+#pragma unroll
+            for (int u = 0; u < kFinalChunk; ++u) {
+                if (gl + u * G < nblk) {
+                    s += a.v[u];
+                    if (check) { mx = fmax(mx, a.vx[u]); mn = fmin(mn, a.vn[u]); }
+                }
+            }
+            constexpr int U = 4;
+            for (int b0 = gl + kFinalChunk * G; b0 < nblk; b0 += U * G) {
                 double v[U], vx[U], vn[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -529,13 +578,13 @@ __device__ inline void finalize_body(const SolveParams &P) {
             }
         }
         if (active && gl == 0) {
-            const double lam_old = P.lam[pi], zoff_old = P.zoff[pi];
-            const double h_old = P.h[pi], p_old = P.p[pi];
+            const double lam_old = a.lam, zoff_old = a.zoff;
+            const double h_old = a.h, p_old = a.p;
             const double W = s - nd * lam_old;              // 1'(g(x) - lambda)
             const double kap = kfac * (h_old + p_old - W);
             const double sumz = W + nd * kap;               // 1'z
             const double zoff_new = kap - lam_old;          // z - g(x)
-            const double hn = fmin(P.cap[i], sumz - p_old);
+            const double hn = fmin(a.cap, sumz - p_old);
             const double pn = p_old + hn - sumz;
             P.lam[pi] = kap;
             P.zoff[pi] = zoff_new;
@@ -548,8 +597,8 @@ __device__ inline void finalize_body(const SolveParams &P) {
                                   P.rho2 * fabs(hn - h_old));
             }
             if (LDS) {
-                s_x1[pi] = x1v;
-                s_nu[pi] = nuv;
+                s_x1[pi] = a.x1;
+                s_nu[pi] = a.nu;
             }
         }
     }
@@ -591,22 +640,16 @@ __device__ inline void finalize_body(const SolveParams &P) {
             r = fmax(r, pair_r[pi]);
             sg = fmax(sg, pair_s[pi]);
         }
-        if (res_here) {
-            // the first four strides, read above (entries past the end
-            // repeat this thread's first one, which leaves the maximum alone)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                r = fmax(r, ra[u]);
-                sg = fmax(sg, P.rho3 * rc[u]);
-            }
-        }
-        for (int b0 = tid + 4 * NT; b0 < nres; b0 += 4 * NT) {
+        // the tiles' residual partials, four strides at a time (entries
+        // past the end repeat the stride's first, which leaves the maximum
+        // alone)
+        for (int b0 = tid; b0 < nres; b0 += 4 * NT) {
             double a[4], c[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int bb = b0 + u * NT < nres ? b0 + u * NT : b0;
-                a[u] = pr[2 * bb];
-                c[u] = pr[2 * bb + 1];
+                a[u] = ld32(pr, 2 * bb);
+                c[u] = ld32(pr, 2 * bb + 1);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -617,7 +660,8 @@ __device__ inline void finalize_body(const SolveParams &P) {
         r = block_max<NT / 64>(r, lds);
         sg = block_max<NT / 64>(sg, lds);
         const bool bad = !(r == r) || !(sg == sg);
-        const bool stop = bad || (r < P.lim->eps_p && sg < P.lim->eps_d);
+        const bool stop = bad || (r < eps_p && sg < eps_d);
+        stopped = stopped || stop;
         if (tid == 0) {
             ctrl->r = r;
             ctrl->sigma = sg;
@@ -644,7 +688,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
     __syncthreads();
     if (tid == 0) {
         ctrl->t = t1;
-        if (!ctrl->done && t1 >= P.lim->max_iter) { ctrl->status = 2; ctrl->done = 1; }
+        if (!stopped && t1 >= max_iter) { ctrl->status = 2; ctrl->done = 1; }
     }
 }
 

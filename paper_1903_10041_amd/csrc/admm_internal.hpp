@@ -123,7 +123,7 @@ hipError_t launch_set_run(const SolveParams &P, const Lim &v, int unstop, hipStr
 hipError_t launch_set_run_more(const SolveParams &P, int more, hipStream_t s);
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s);
 hipError_t launch_sweep(const SolveParams &P, int dtype, bool check, hipStream_t s);
-hipError_t launch_finalize(const SolveParams &P, hipStream_t s);
+hipError_t launch_finalize(const SolveParams &P, bool check, hipStream_t s);
 // Chained path: launch at graph position c reads slot c & 1 (rs).
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s);
 // Completes the pending iteration of slot rs into slot 0.

@@ -34,20 +34,29 @@ template <typename T, int MAXM, int CPT, int MODE, bool CHECK, int FEAT, int ME 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(MAXM <= 4 ? 4 : 2)))
 void k_sweep(SolveParams P0) {
     Ctrl *ctrl = P0.ctrl;
-    if (ctrl->done) return;
+    // the stop flag, the scenario's scalars and the first column are read
+    // together and the flag tested after them (a compiler barrier keeps the
+    // reads ahead of the test): one wait for memory instead of two
+    const int done = ctrl->done;
     SolveParams P = P0;
-    adapt_load<false>(P, P0.rho_cur, ctrl);
+    if (FEAT == F_ALL) adapt_load<false>(P, P0.rho_cur, ctrl);   // the others run at fixed rho
     const int j = blockIdx.y;
     Scal<MAXM> sc;
     scal_load<MAXM, false>(P, j, sc);
+    const int k0 = blockIdx.x * (kBlock * CPT) + threadIdx.x;
+    Col<T, MAXM> d0;
+    col_load<T, MAXM, ME>(P, j, k0 < P.n ? k0 : P.n - 1, d0);   // past the end: a valid column, unused
+    asm volatile("" ::: "memory");
+    if (done) return;
     Acc<MAXM> acc;
     acc.reset();
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
-        const int k = blockIdx.x * (kBlock * CPT) + cc * kBlock + threadIdx.x;
+        const int k = k0 + cc * kBlock;
         if (k < P.n) {
             Col<T, MAXM> d;
-            col_load<T, MAXM, ME>(P, j, k, d);
+            if (cc == 0) d = d0;
+            else col_load<T, MAXM, ME>(P, j, k, d);
             if (P.wdiv != 1.0) col_rescale_mu(d, P.wdiv);
             col_update<T, MAXM, MODE, CHECK, FEAT, ME>(P, j, k, d, sc, acc);
             col_store<T, MAXM, ME>(P, j, k, d);
@@ -110,12 +119,13 @@ __global__ __launch_bounds__(kBlock) void k_quartic(int64_t N, const double *A, 
     if (flag) atomicOr(bad, 1);
 }
 
+// CHECK as the launch's sweep; the body tests the stop flag itself, after
+// issuing its reads.
+template <bool CHECK, bool LDS>
 __global__ __launch_bounds__(kFinalBlock) void k_finalize(SolveParams P0) {
-    if (P0.ctrl->done) return;
     SolveParams P = P0;
     adapt_load<false>(P, P0.rho_cur, P0.ctrl);
-    if (P.m * P.q <= kFinalLdsPairs) finalize_body<kFinalBlock, true>(P);
-    else finalize_body<kFinalBlock, false>(P);
+    finalize_body<kFinalBlock, LDS, true, CHECK ? 1 : 0>(P);
 }
 
 // ------------------------------------------------------ chained iteration
@@ -1506,12 +1516,12 @@ static void launch_sweep_c(const SolveParams &P, hipStream_t s) {
 }
 
 // One column per thread without the optional features (no g0, per-source
-// bounds, no branch codes, Gauss-Seidel, EXACT_BOX) is the common case and
+// bounds, no branch codes, Gauss-Seidel, EXACT_BOX, fixed rho) is the common case and
 // gets its own kernels, without or with the consensus block (scenario
 // programs); everything else the general one.
 template <typename T, int MODE, bool CHECK>
 static void launch_sweep_k(const SolveParams &P, hipStream_t s) {
-    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
+    const bool plain = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project && !P.adaptive;
     switch (P.cpt) {
     case 1:
         if (plain && !P.consensus) launch_sweep_c<T, MODE, 1, CHECK, 0>(P, s);
@@ -1708,8 +1718,12 @@ hipError_t launch_chain_flush(const SolveParams &P, int rs, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
-    k_finalize<<<1, kFinalBlock, 0, s>>>(P);
+hipError_t launch_finalize(const SolveParams &P, bool check, hipStream_t s) {
+    const bool lds = P.m * P.q <= kFinalLdsPairs;
+    if (check && lds) k_finalize<true, true><<<1, kFinalBlock, 0, s>>>(P);
+    else if (check) k_finalize<true, false><<<1, kFinalBlock, 0, s>>>(P);
+    else if (lds) k_finalize<false, true><<<1, kFinalBlock, 0, s>>>(P);
+    else k_finalize<false, false><<<1, kFinalBlock, 0, s>>>(P);
     return hipGetLastError();
 }
 
@@ -1717,7 +1731,7 @@ hipError_t launch_finalize(const SolveParams &P, hipStream_t s) {
 hipError_t launch_iteration(const SolveParams &P, int dtype, bool check, hipStream_t s) {
     hipError_t e = launch_sweep(P, dtype, check, s);
     if (e != hipSuccess) return e;
-    return launch_finalize(P, s);
+    return launch_finalize(P, check, s);
 }
 
 template <typename T>

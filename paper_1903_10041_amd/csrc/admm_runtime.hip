@@ -258,10 +258,13 @@ extern "C" void admm_destroy(admm_context *ctx) {
     serve_shutdown(ctx);
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->own);
+    // work queued on the caller's stream ends with one of these events
+    for (hipEvent_t e : {ctx->join, ctx->fev[0], ctx->fev[1]})
+        if (e) (void)hipEventSynchronize(e);
     for (GraphEntry &g : ctx->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    for (DevBuf *b : ctx->ws.all()) ctx->arena.release(*b);
     batch_release(ctx);
+    for (DevBuf *b : ctx->ws.all()) ctx->arena.release(*b);
     if (ctx->hctrl) (void)hipHostFree(ctx->hctrl);
     (void)hipEventDestroy(ctx->join);
     (void)hipEventDestroy(ctx->ev0);
@@ -493,6 +496,10 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     if (chain && !local && (q > 1 || s->consensus_q1))
         P.cgrid = std::min(q * ((n + kChainBlock - 1) / kChainBlock), chainq_grid_cap(ctx));
     const size_t E = (size_t)q * m * n_pad, K = (size_t)q * n_pad, M = (size_t)q * m;
+    // the scalar-step block addresses the tile partials with 32-bit byte
+    // offsets: five slabs of q nblk m doubles
+    if ((size_t)q * nblk * m * 5 * sizeof(double) >= ((size_t)1 << 32))
+        return fail(ADMM_E_UNSUPPORTED, "too many column tiles for the partial sums (q m ceil(n / 256) >= 2^26)");
     P.m = m; P.n = n; P.q = q; P.n_pad = n_pad; P.nblk = nblk; P.cpt = cpt;
     // lanes per (i,j) pair in the scalar steps: the split path runs them in
     // one block of kFinalBlock threads, the resident path in one of kBlock
@@ -1285,7 +1292,7 @@ extern "C" admm_status admm_profile(admm_context *ctx, const admm_problem *pr, c
         fi = 0.0;
     } else {
         if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_sweep(P, dtype, (++c1 % 10) == 0, s); }, &sw)) != ADMM_OK) return st;
-        if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, s); }, &fi)) != ADMM_OK) return st;
+        if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_finalize(P, false, s); }, &fi)) != ADMM_OK) return st;
         if ((st = time_graph(ctx, s, reps, per, [&] { (void)launch_iteration(P, dtype, (++c3 % 10) == 0, s); }, &it)) != ADMM_OK) return st;
     }
     out[0] = sw;
