@@ -192,7 +192,8 @@ def run_gpu(args, precision_name):
             x, info, _ = ctx.solve(pd, s)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            res["solve"][tag] = {"residual": eps, "status": info["status"], "iters": info["iters"],
+            res["solve"][tag] = {"rho": "rho_2 = rho_1 / n" if r2 else "rho = 1 as configured",
+                                 "residual": eps, "status": info["status"], "iters": info["iters"],
                                  "r": info["r"], "sigma": info["sigma"], "objective": info["objective"],
                                  "solve_ms": 1000.0 * (t1 - t0), "solves_per_s": 1.0 / (t1 - t0)}
             if r2:
@@ -282,8 +283,9 @@ def run_qsweep(args):
     """Scenario-count sweep on the robust shape (m = 2, n = 3600, q in
     --q-list; the paper's second experiment): iterations and solve time to
     r, sigma < 1e-4 with rho = 1, with rho_2 / n, and with adaptive rho
-    (Sec. IV-A), mixed precision; the FP64 oracle's iteration counts for
-    the smallest q values (rho_2 / n)."""
+    (Sec. IV-A) started from each of the two, at every check or frozen
+    after 1000 iterations, mixed precision; the FP64 oracle's iteration
+    counts for the smallest q values (rho_2 / n)."""
     import torch
     import oracle
     from paper_1903_10041_amd import admm
@@ -295,7 +297,11 @@ def run_qsweep(args):
         pd = _device_problem(p, torch.float32)
         row = {"q": q, "elements": p.m * p.n * q}
         for tag, kw in (("rho1", {}), ("rho2_per_step", {"rho2_per_step": True}),
-                        ("adaptive", {"adaptive_rho": True})):
+                        ("adaptive_from_rho1", {"adaptive_rho": True}),
+                        ("adaptive_from_rho2_per_step", {"adaptive_rho": True, "rho2_per_step": True}),
+                        ("adaptive_from_rho1_until_1000", {"adaptive_rho": True, "adapt_until": 1000}),
+                        ("adaptive_from_rho2_per_step_until_1000",
+                         {"adaptive_rho": True, "rho2_per_step": True, "adapt_until": 1000})):
             s = admm.Settings(max_iter=args.q_max_iter, eps_primal=1e-4, eps_dual=1e-4,
                               precision=admm.F32_MIXED, **kw)
             torch.cuda.synchronize()

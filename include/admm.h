@@ -65,7 +65,11 @@ typedef enum {
  * ADMM_F32: FP32 storage, x-step assembly and closed form in FP32, no
  * polish; FP64 reductions and scalars.  Both FP32 modes fall back to the
  * FP64 closed form near repeated roots and for three real roots.  Device
- * arrays of a problem are double for ADMM_F64 and float otherwise. */
+ * arrays of a problem are double for ADMM_F64 and float otherwise.
+ * Accuracy: without the polish ADMM_F32's x is good to about 1e-6
+ * relative, so residual thresholds near 1e-4 may not be reached (measured
+ * on m = 4, n = 262144 with rho_2 / n: sigma stalls at 1.4e-4 and the solve
+ * ends at max_iter); ADMM_F32_MIXED or ADMM_F64 reach tighter thresholds. */
 typedef enum { ADMM_F64 = 0, ADMM_F32_MIXED = 1, ADMM_F32 = 2 } admm_precision;
 
 /* Box semantics of the x-step (7a).  EXACT_BOX minimises the quartic over
@@ -152,10 +156,22 @@ typedef struct {
      * the scaled duals mu, lambda, nu, p are divided by the same factor, so
      * the unscaled multipliers do not change.  Run by admm_solve (batched
      * instances with it run through admm_solve; served requests with it run
-     * on a serving lane).
-     * Defaults 0, 1.1, 1.2, 0.8; tau > 1, 0 < band_lo <= band_hi. */
+     * on a serving lane).  Balancing scales every rho_i by one factor, so
+     * it does not correct the capacity block's scale: start it with
+     * rho2_per_step = 1 (measured on the robust program, n = 3600: from
+     * rho = 1 it does not converge in 20000 iterations from q = 50, from
+     * rho_2 / n it converges about as fixed rho_2 / n does).
+     * adapt_until > 0: no change after iteration adapt_until, so rho is
+     * fixed after finitely many iterations, the condition under which the
+     * varying-penalty discussion the paper cites (Boyd et al., Sec. 3.4.1)
+     * keeps convergence; 0 adapts at every check.  Measured on the robust
+     * program with adaptation at every check from q = 200 (rho_2 / n
+     * start) it does not converge, frozen after 1000 iterations it does.
+     * Defaults 0, 1.1, 1.2, 0.8, 0; tau > 1, 0 < band_lo <= band_hi,
+     * adapt_until >= 0. */
     int32_t adaptive_rho;
     double tau, band_hi, band_lo;
+    int32_t adapt_until;
 } admm_settings;
 
 /* Iterate of (7a)-(7i), in the paper's variables, host doubles.  Any NULL
@@ -188,7 +204,7 @@ typedef struct {
 
 /* Defaults: rho = 1, eps = 1e-6, max_iter = 10000, check_every = 10, F64,
  * EXACT_BOX, GAUSS_SEIDEL, consensus_q1 = 0, no branch codes,
- * rho2_per_step = 0, launch AUTO, adaptive_rho = 0 (tau 1.1, bands 1.2 / 0.8).  rho2_per_step scales the penalty of the capacity
+ * rho2_per_step = 0, launch AUTO, adaptive_rho = 0 (tau 1.1, bands 1.2 / 0.8, adapt_until 0).  rho2_per_step scales the penalty of the capacity
  * constraint sum_k z_k = h (one constraint over n terms) by 1/n per
  * instance; with rho_2 = rho_1 the iteration count grows about linearly in
  * n, with rho_2 = rho_1 / n it stays near a hundred for any n. */

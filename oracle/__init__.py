@@ -51,7 +51,8 @@ class _Settings(C.Structure):
                 ("check_every", C.c_int32), ("paper_project", C.c_int32),
                 ("jacobi", C.c_int32), ("consensus_q1", C.c_int32),
                 ("nthreads", C.c_int32), ("adaptive_rho", C.c_int32),
-                ("tau", C.c_double), ("band_hi", C.c_double), ("band_lo", C.c_double)]
+                ("tau", C.c_double), ("band_hi", C.c_double), ("band_lo", C.c_double),
+                ("adapt_until", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -159,7 +160,7 @@ def objective(prob, x) -> float:
 
 def validate(prob, rho=(1.0, 1.0, 1.0, 1.0)) -> bool:
     keep = _Keep(prob)
-    s = _Settings((C.c_double * 4)(*rho), 0.0, 0.0, 1, 10, 0, 0, 0, 1, 0, 1.1, 1.2, 0.8)
+    s = _Settings((C.c_double * 4)(*rho), 0.0, 0.0, 1, 10, 0, 0, 0, 1, 0, 1.1, 1.2, 0.8, 0)
     return lib().oracle_validate(C.byref(keep.st), C.byref(s)) == 0
 
 
@@ -168,7 +169,7 @@ def run(prob, *, max_iter: int = 500, eps_primal: float = 0.0, eps_dual: float =
         jacobi: bool = False, consensus_q1: bool = False, nthreads: int = 1,
         state: dict | None = None, want_codes: bool = False,
         want_coef: bool = False, adaptive_rho: bool = False, tau: float = 1.1,
-        band_hi: float = 1.2, band_lo: float = 0.8):
+        band_hi: float = 1.2, band_lo: float = 0.8, adapt_until: int = 0):
     """Run (7a)-(7i) from ``state`` (cold start if None).
 
     Returns (state, info dict, history array of rows (t, r, sigma)).  The
@@ -184,7 +185,7 @@ def run(prob, *, max_iter: int = 500, eps_primal: float = 0.0, eps_dual: float =
     S = _Settings((C.c_double * 4)(*rho), float(eps_primal), float(eps_dual),
                   int(max_iter), int(check_every), int(paper_project), int(jacobi),
                   int(consensus_q1), int(nthreads), int(adaptive_rho), float(tau),
-                  float(band_hi), float(band_lo))
+                  float(band_hi), float(band_lo), int(adapt_until))
     nh = max(1, max_iter // max(1, check_every))
     hist = np.zeros((nh, 3))
     E = prob.m * prob.n * prob.q

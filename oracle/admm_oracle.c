@@ -43,7 +43,10 @@
  *       all rho_i are multiplied by tau when r/sigma > band_hi * rbar/sbar
  *       and divided by tau when r/sigma < band_lo * rbar/sbar; the scaled
  *       multipliers mu, lambda, nu, p are divided by the same factor, so the
- *       unscaled multipliers rho * (.) are unchanged.
+ *       unscaled multipliers rho * (.) are unchanged.  With adapt_until > 0
+ *       no change is made after iteration adapt_until, so rho is fixed
+ *       after finitely many iterations (the condition under which the
+ *       varying-penalty discussion the paper cites keeps convergence).
  */
 #include <math.h>
 #include <stdint.h>
@@ -221,6 +224,7 @@ typedef struct {
     int32_t nthreads;
     int32_t adaptive_rho;            /* R12: residual balancing at check iterations */
     double tau, band_hi, band_lo;    /* Sec. IV-A: 1.1, 1.2, 0.8 */
+    int32_t adapt_until;             /* R12: no change after iteration adapt_until (0: never stop) */
 } oracle_settings;
 
 typedef struct {
@@ -515,7 +519,7 @@ int oracle_run(const oracle_problem *P, const oracle_settings *S,
             }
             ++nh;
             if (r < S->eps_primal && sigma < S->eps_dual) { status = 0; break; }
-            if (S->adaptive_rho) {
+            if (S->adaptive_rho && (S->adapt_until <= 0 || t <= S->adapt_until)) {
                 const double target = (S->eps_primal > 0.0 && S->eps_dual > 0.0)
                                     ? S->eps_primal / S->eps_dual : 1.0;
                 const double ratio = sigma > 0.0 ? r / sigma : INFINITY;

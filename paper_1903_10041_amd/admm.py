@@ -54,7 +54,7 @@ class admm_settings(C.Structure):
                 ("xstep", C.c_int), ("sweep", C.c_int), ("consensus_q1", C.c_int32),
                 ("debug_branch_codes", C.c_int32), ("rho2_per_step", C.c_int32),
                 ("launch", C.c_int), ("adaptive_rho", C.c_int32), ("tau", C.c_double),
-                ("band_hi", C.c_double), ("band_lo", C.c_double)]
+                ("band_hi", C.c_double), ("band_lo", C.c_double), ("adapt_until", C.c_int32)]
 
 
 class admm_state(C.Structure):
@@ -147,6 +147,7 @@ class Settings:
     tau: float = 1.1
     band_hi: float = 1.2
     band_lo: float = 0.8
+    adapt_until: int = 0
 
     def to_c(self) -> admm_settings:
         return admm_settings((C.c_double * 4)(*[float(r) for r in self.rho]),
@@ -155,7 +156,7 @@ class Settings:
                              int(self.sweep), int(bool(self.consensus_q1)),
                              int(bool(self.debug_branch_codes)), int(bool(self.rho2_per_step)),
                              int(self.launch), int(bool(self.adaptive_rho)), float(self.tau),
-                             float(self.band_hi), float(self.band_lo))
+                             float(self.band_hi), float(self.band_lo), int(self.adapt_until))
 
 
 def _is_torch(a) -> bool:

@@ -63,6 +63,7 @@ __device__ __forceinline__ SolveParams inst_params(const BatchParams &B, const B
     P.rho4 = I.rho[3];
     P.inv_q = 1.0;
     P.adaptive = 0;
+    P.adapt_until = 0;
     P.tau = P.band_hi = P.band_lo = 1.0;
     P.wdiv = 1.0;
     P.rho_cur = nullptr;

@@ -414,7 +414,9 @@ __device__ __forceinline__ void adapt_load(SolveParams &Q, const double *rho, co
 
 // Residual balancing at a check iteration that does not stop (Sec. IV-A):
 // the factor applied to every rho_i (the scaled duals are divided by it).
-__device__ __forceinline__ double adapt_factor(const SolveParams &P, double r, double sigma) {
+// t: the iteration whose check this is; none after P.adapt_until (> 0).
+__device__ __forceinline__ double adapt_factor(const SolveParams &P, double r, double sigma, int t) {
+    if (P.adapt_until > 0 && t > P.adapt_until) return 1.0;
     const double ep = P.lim->eps_p, ed = P.lim->eps_d;
     const double target = (ep > 0.0 && ed > 0.0) ? ep / ed : 1.0;
     const double ratio = sigma > 0.0 ? r / sigma : INFINITY;
@@ -670,7 +672,7 @@ __device__ inline void finalize_body(const SolveParams &P) {
         }
         if (P.adaptive) {
             // r and sg are the same in every thread: so is f
-            const double f = stop ? 1.0 : adapt_factor(P, r, sg);
+            const double f = stop ? 1.0 : adapt_factor(P, r, sg, t1);
             if (f != 1.0) {
                 for (int pi = tid; pi < M; pi += NT) {
                     P.lam[pi] /= f;

@@ -72,7 +72,7 @@ struct SolveParams {
     // adaptive rho (Sec. IV-A): the current rho_1..4 live in rho_cur ([4],
     // a second [4] for the chained path's other slot); a kernel copies them
     // into its own rho1..4 and the pending mu divisor into wdiv
-    int32_t adaptive;
+    int32_t adaptive, adapt_until;   // adapt_until > 0: no rho change after that iteration
     double tau, band_hi, band_lo, wdiv;
     double *rho_cur;
     const void *coef;       // vec4 of T

@@ -317,7 +317,7 @@ __device__ __forceinline__ void chain_finish(const SolveParams &P, int rs, const
                 const bool stop = bad || (r < P.lim->eps_p && sg < P.lim->eps_d);
                 if (bad) { status = -4; dn = 1; }
                 else if (stop) { status = 0; dn = 1; }
-                if (P.adaptive && !stop) f = adapt_factor(P, r, sg);
+                if (P.adaptive && !stop) f = adapt_factor(P, r, sg, t);
             }
             if (!dn && t >= P.lim->max_iter) { status = 2; dn = 1; }
         }

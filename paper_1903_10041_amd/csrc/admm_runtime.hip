@@ -141,6 +141,7 @@ admm_status validate_settings(const admm_settings *s) {
         (!(s->tau > 1.0) || !std::isfinite(s->tau) || !(s->band_lo > 0.0) || !(s->band_hi >= s->band_lo) ||
          !std::isfinite(s->band_hi)))
         return fail(ADMM_E_INVALID_ARG, "adaptive rho needs tau > 1 and 0 < band_lo <= band_hi");
+    if (s->adapt_until < 0) return fail(ADMM_E_INVALID_ARG, "adapt_until must be >= 0");
     return ADMM_OK;
 }
 
@@ -199,6 +200,7 @@ extern "C" void admm_default_settings(admm_settings *s) {
     s->tau = 1.1;
     s->band_hi = 1.2;
     s->band_lo = 0.8;
+    s->adapt_until = 0;
 }
 
 extern "C" admm_status admm_create(admm_context **out, int device, size_t budget,
@@ -520,6 +522,7 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
     P.tau = s->tau;
     P.band_hi = s->band_hi;
     P.band_lo = s->band_lo;
+    P.adapt_until = s->adapt_until;
     P.wdiv = 1.0;
     admm_status st;
 #define ENS(buf, bytes) if ((st = cv ? cv->take(buf, bytes) : A.ensure(buf, bytes)) != ADMM_OK) return st

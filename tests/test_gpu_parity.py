@@ -541,6 +541,24 @@ def test_adaptive_rho_follows_oracle(ctx, launch):
 
 
 @pytest.mark.parametrize("launch", list(LAUNCHES))
+def test_adapt_until_follows_oracle(ctx, launch):
+    """Adaptation frozen after iteration 100 (adapt_until, reading R12) on
+    every launch path: the oracle's rho and iterates after 300 iterations."""
+    for name in ("c1", "stress"):
+        p = LAUNCH_CASES[name]()
+        s = admm.Settings(rho=tuple(p.rho), max_iter=300, eps_primal=1e-9, eps_dual=1e-9,
+                          adaptive_rho=True, adapt_until=100, launch=LAUNCHES[launch])
+        say(f"[adapt-until] {name} {launch}")
+        x, info, _ = ctx.solve(p, s)
+        so, oinfo, _ = oracle.run(p, max_iter=300, eps_primal=1e-9, eps_dual=1e-9, adaptive_rho=True,
+                                  adapt_until=100)
+        say(f"   rho gpu={info['rho']} oracle={oinfo['rho']}")
+        assert info["iters"] == oinfo["iters"]
+        assert np.allclose(info["rho"], oinfo["rho"], rtol=1e-15, atol=0)
+        assert float(np.abs(x - so["x"]).max()) <= 1e-9
+
+
+@pytest.mark.parametrize("launch", list(LAUNCHES))
 def test_adaptive_rho_convergence(ctx, launch):
     for name in ("c1", "stress"):
         p = LAUNCH_CASES[name]()
@@ -566,3 +584,40 @@ def test_adaptive_rho_fp32_and_robust(ctx):
         say(f"[adaptive-misc] m={p.m} q={p.q} prec={prec} iters {info['iters']}/{oinfo['iters']} rel={rel:.2e}")
         assert info["status"] == admm.OK
         assert rel <= (1e-4 if prec != admm.F64 else 1e-8)
+
+
+def test_adaptive_rho_from_rho2_per_step_at_q50(ctx):
+    """Adaptive rho started from rho_2 / n (Sec. IV-A with reading R13) on
+    the robust program at q = 50, n = 3600, where adaptation from rho = 1
+    does not converge: FP64 on the GPU stops at the oracle's check (the
+    rho decisions agree), at its objective and its final rho."""
+    p = W.phev_c4(q=50)
+    say(f"[adaptive-rho2n] q={p.q} n={p.n}")
+    s = admm.Settings(rho=(1.0, 1.0, 1.0, 1.0), max_iter=20000, eps_primal=1e-4, eps_dual=1e-4,
+                      adaptive_rho=True, rho2_per_step=True, precision=admm.F64)
+    x, info, _ = ctx.solve(p, s)
+    so, oinfo, _ = oracle.run(p, max_iter=20000, eps_primal=1e-4, eps_dual=1e-4, adaptive_rho=True,
+                              rho=(1.0, 1.0 / p.n, 1.0, 1.0), nthreads=16)
+    say(f"   iters gpu={info['iters']} oracle={oinfo['iters']} rho gpu={info['rho']} oracle={oinfo['rho']}")
+    assert oinfo["status"] == 0 and info["status"] == admm.OK
+    assert abs(info["iters"] - oinfo["iters"]) <= 10
+    assert np.allclose(info["rho"], oinfo["rho"], rtol=1e-12, atol=0)
+    assert abs(info["objective"] - oinfo["objective"]) <= 1e-8 * (1 + abs(oinfo["objective"]))
+
+
+def test_adaptive_rho_frozen_converges_at_q200(ctx):
+    """At q = 200 adaptation at every check does not converge (it keeps
+    moving rho by tau); frozen after 1000 iterations (adapt_until) it does,
+    to the optimum of the fixed rho_2 / n solve (mixed precision)."""
+    import torch
+    p = W.phev_c4(q=200)
+    dev = torch.device("cuda:0")
+    pd = W.Problem(**{k: (torch.from_numpy(v).to(dev, torch.float32) if isinstance(v, np.ndarray) and k != "c" else v)
+                      for k, v in vars(p).items()})
+    say(f"[adaptive-frozen] q={p.q} n={p.n}")
+    base = dict(max_iter=50000, eps_primal=1e-4, eps_dual=1e-4, precision=admm.F32_MIXED, rho2_per_step=True)
+    _, fi, _ = ctx.solve(pd, admm.Settings(**base))
+    _, ai, _ = ctx.solve(pd, admm.Settings(adaptive_rho=True, adapt_until=1000, **base))
+    say(f"   fixed {fi['iters']} frozen-adaptive {ai['iters']} objectives {fi['objective']} {ai['objective']}")
+    assert fi["status"] == admm.OK and ai["status"] == admm.OK
+    assert abs(ai["objective"] - fi["objective"]) <= 1e-4 * (1 + abs(fi["objective"]))

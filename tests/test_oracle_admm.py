@@ -301,6 +301,25 @@ def test_adaptive_rho_step_is_a_rescaled_fixed_step():
         assert np.array_equal(a[k], b[k] / f), k
 
 
+def test_adapt_until_freezes_rho_after_that_iteration():
+    """adapt_until = N (R12): the run adapts as an unfrozen one up to
+    iteration N, then continues exactly as a fixed-rho run from the state
+    and rho it had at N (iterates bit for bit), while the unfrozen run goes
+    on changing rho."""
+    p = W.stress()
+    N, more = 120, 200
+    kw = dict(eps_primal=1e-12, eps_dual=1e-12, adaptive_rho=True)
+    sN, iN, _ = oracle.run(p, max_iter=N, **kw)
+    assert tuple(iN["rho"]) != tuple(p.rho)                  # adapted before N
+    a, ia, _ = oracle.run(p, max_iter=N + more, adapt_until=N, **kw)
+    b, ib, _ = oracle.run(p, max_iter=more, state=sN, rho=tuple(iN["rho"]), eps_primal=1e-12, eps_dual=1e-12)
+    u, iu, _ = oracle.run(p, max_iter=N + more, **kw)
+    assert tuple(ia["rho"]) == tuple(iN["rho"])
+    assert tuple(iu["rho"]) != tuple(iN["rho"])              # unfrozen: still changing
+    for k in ("x", "z", "s", "h", "mu", "lam", "p"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_rho2_scaled_by_horizon_converges_fast():
     """With the capacity penalty rho_2 = rho_1 / n the iteration count stays
     near a hundred at any horizon, and the optimum is unchanged."""
