@@ -235,7 +235,17 @@ def run_large(args):
             "iters_per_s": args.large_steps / dt, "launch": prof["launch"],
             "kernel_us": {"sweep": prof["sweep_us"], "finalize": prof["finalize_us"],
                           "graph_iteration": prof["graph_iter_us"]},
-            "sweep_bytes": byts, "sweep_gbs": ach, "sweep_hbm_frac": ach / HBM_PEAK_GBS}
+            "sweep_bytes": byts, "sweep_gbs": ach, "sweep_hbm_frac": ach / HBM_PEAK_GBS,
+            "sweep_traffic": _sweep_traffic(prof["launch"], args.precision, p.m, p.n)}
+
+
+def _sweep_traffic(launch, precision, m, n):
+    """Counter-measured HBM bytes per sweep launch of the large leg, when a
+    record for the current kernel sources exists (split launch only)."""
+    if launch != "split":
+        return None
+    t, src = traffic_record("k_sweep", precision, m, n)
+    return None if t is None else {"bytes_per_launch": t, "from": src}
 
 
 def run_quartic(args):

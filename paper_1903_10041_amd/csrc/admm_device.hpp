@@ -517,12 +517,29 @@ __device__ inline void finalize_body(const SolveParams &P) {
     const bool check = CK < 0 ? (t1 % P.check_every) == 0 : CK != 0;
     FinPair a;
     fin_pair_load(P, gid, gl, G, check, a);
+    // on a check, the first four strides of the tiles' residual maxima,
+    // issued with the pair reads and folded at once into two values (the
+    // wait for them is the wait for the pair reads), so that only two
+    // registers stay live; entries past the end repeat the stride's first,
+    // which leaves the maximum alone
+    const int nres = q * nblk;
+    double r0 = 0.0, c0 = 0.0;
+    if (check && tid < nres) {
+        double ra[4], rc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int bb = tid + u * NT < nres ? tid + u * NT : tid;
+            ra[u] = ld32(pr, 2 * bb);
+            rc[u] = ld32(pr, 2 * bb + 1);
+        }
+        r0 = fmax(fmax(ra[0], ra[1]), fmax(ra[2], ra[3]));
+        c0 = fmax(fmax(rc[0], rc[1]), fmax(rc[2], rc[3]));
+    }
     // a compiler barrier: the reads above stay issued before the test
     // rather than being moved into the code that uses them
     asm volatile("" ::: "memory");
     if (GUARD && done_in) return;
     bool stopped = done_in != 0;
-    const int nres = q * nblk;
 
     for (int base = 0; base < M; base += ngroups) {
         const int pi = base + gid;
@@ -642,10 +659,11 @@ __device__ inline void finalize_body(const SolveParams &P) {
             r = fmax(r, pair_r[pi]);
             sg = fmax(sg, pair_s[pi]);
         }
-        // the tiles' residual partials, four strides at a time (entries
-        // past the end repeat the stride's first, which leaves the maximum
-        // alone)
-        for (int b0 = tid; b0 < nres; b0 += 4 * NT) {
+        // the tiles' residual partials: the first four strides read above,
+        // the rest four strides at a time
+        r = fmax(r, r0);
+        sg = fmax(sg, P.rho3 * c0);
+        for (int b0 = tid + 4 * NT; b0 < nres; b0 += 4 * NT) {
             double a[4], c[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
