@@ -89,8 +89,8 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
  * AUTO      RESIDENT when the problem fits in a few co-resident blocks,
  *           else CHAINED when it applies (q = 1: while one iteration's
  *           algorithmic traffic fits the 256 MB last-level cache; with the
- *           consensus block: while q ceil(n / 1024) <= twice the compute
- *           units), else SPLIT.
+ *           consensus block: while q ceil(n / 1024) <= the compute
+ *           units), else CHAINED_LOCAL where it applies, else SPLIT.
  * SPLIT     a captured graph of two launches per iteration: the sweep
  *           (7a), (7e), (7f) with block partials, then one block for the
  *           scalar steps (7b)-(7d), (7g)-(7i), residuals and stop flag.
@@ -104,15 +104,17 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
  *           when every block fits on the device at once (else
  *           ADMM_E_UNSUPPORTED).
  * CHAINED_LOCAL  for many scenarios: one launch per iteration, one block
- *           per tile of 256 columns, each completing the previous
+ *           per tile of 256 threads with 4 or 8 columns each (m <= 2;
+ *           8 once the tiles of 1024 columns exceed four per compute
+ *           unit) or 2 (m <= 4), each completing the previous
  *           iteration's scalar steps for its own scenario only (the tile
  *           of the first step also forms the consensus); a check
  *           iteration adds one launch of a block per scenario that finishes
  *           its steps and residuals, and the next launch takes the stop
  *           decision.  q > 1 (or consensus_q1), m <= 4, m q <= 4096, fixed
  *           rho (ADMM_E_UNSUPPORTED otherwise).  CHAINED takes it where
- *           the other chained form does not apply; AUTO never does (it
- *           measures slower than SPLIT where it would be the choice). */
+ *           the other chained form does not apply, AUTO past that form's
+ *           range. */
 typedef enum { ADMM_LAUNCH_AUTO = 0, ADMM_LAUNCH_SPLIT = 1, ADMM_LAUNCH_CHAINED = 2,
                ADMM_LAUNCH_RESIDENT = 3, ADMM_LAUNCH_CHAINED_LOCAL = 4 } admm_launch;
 

@@ -889,15 +889,16 @@ __device__ __forceinline__ void loc_decide(const SolveParams &P, double (*red)[2
 // scalar steps need are issued before the column loads (memory results
 // return in issue order), so the steps are computed while the columns are
 // still arriving.
-template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int NT>
+template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int NT, int CPT>
 __global__ __launch_bounds__(NT) void k_loc(SolveParams P, int rs) {
+    // CPT columns per thread, NT apart
     const int ws = rs ^ 1, m = P.m, nbs = P.nblk;
     __shared__ double red[NT / 64][3 * MAXM + 2];
     const QSlot in = qslot(P, rs);
     const Ctrl *c = in.ctrl;
     const int tile = blockIdx.x, j = tile / nbs, b = tile - j * nbs;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int k = b * NT + tid;
+    const int k0 = b * NT * CPT + tid;
     const int t = c->t, pending = c->pending, done0 = c->done;
     const bool steps = pending == 1 && !done0;
     const double *part = rs ? P.part : P.part1;
@@ -921,9 +922,10 @@ __global__ __launch_bounds__(NT) void k_loc(SolveParams P, int rs) {
         for (int e = tid; e < P.m * P.q; e += NT) xd[e] = in.x1[e] - in.nu[e];
         __syncthreads();
     }
-    // 2. the columns
+    // 2. the first column (the others are loaded one ahead of the sweep,
+    //    so that two columns are live at a time)
     Col<T, MAXM> d;
-    if (k < P.n) col_load<T, MAXM>(P, j, k, d);
+    if (k0 < P.n) col_load<T, MAXM>(P, j, k0, d);
     // 3. the pair's new state (lanes < m), the same arithmetic and order
     //    as loc_pair
     double lam = lam0, zoff = zoff0, h = h0, p = p0, nu = pending == 2 ? nu_f : nu_s;
@@ -1021,9 +1023,16 @@ __global__ __launch_bounds__(NT) void k_loc(SolveParams P, int rs) {
     scal_bounds<MAXM>(P.slo, P.shi, m, sc);
     Acc<MAXM> acc;
     acc.reset();
-    if (k < P.n) {
-        col_update<T, MAXM, MODE, CHECK, FEAT>(Q, j, k, d, sc, acc);
-        col_store<T, MAXM>(Q, j, k, d);
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+        const int k = k0 + cc * NT;
+        Col<T, MAXM> dn;
+        if (cc + 1 < CPT && k + NT < P.n) col_load<T, MAXM>(P, j, k + NT, dn);
+        if (k < P.n) {
+            col_update<T, MAXM, MODE, CHECK, FEAT>(Q, j, k, d, sc, acc);
+            col_store<T, MAXM>(Q, j, k, d);
+        }
+        if (cc + 1 < CPT) d = dn;
     }
     chain_partials<MAXM, NT>(P, rs ? P.part1 : P.part, tile, acc, CHECK, red, (size_t)P.q * nbs * m);
 }
@@ -1637,12 +1646,15 @@ static void launch_loc(const SolveParams &P, int rs, hipStream_t s) {
     const unsigned g = (unsigned)(P.q * P.nblk);
     const size_t lds = P.m * P.q <= kLocLdsPairs ? (size_t)P.m * P.q * sizeof(double) : 0;
     const bool cons_only = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
+    // P.cpt (columns per thread) is 8 or 4 for m <= 2 and 2 for m <= 4
     if (cons_only) {
-        if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
-        else k_loc<T, 4, MODE, CHECK, F_CONS, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+        if (P.m <= 2 && P.cpt == 8) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 4, MODE, CHECK, F_CONS, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
     } else {
-        if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
-        else k_loc<T, 4, MODE, CHECK, F_ALL, kLocBlock><<<g, kLocBlock, lds, s>>>(P, rs);
+        if (P.m <= 2 && P.cpt == 8) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 4, MODE, CHECK, F_ALL, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
     }
     // a check iteration's steps and residuals, for the next launch's decision
     if (CHECK) {
@@ -1655,7 +1667,9 @@ bool chain_loc_fits(int m, int q) { return m <= 4 && (int64_t)m * q <= 4 * kChai
 
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {
     if (P.chain == 2) {
-        if (!P.consensus || !chain_loc_fits(P.m, P.q) || P.nblk != (P.n + kLocBlock - 1) / kLocBlock ||
+        const int cols = kLocBlock * P.cpt;
+        const bool cpt_ok = P.m <= 2 ? (P.cpt == 4 || P.cpt == 8) : P.cpt == 2;
+        if (!P.consensus || !chain_loc_fits(P.m, P.q) || !cpt_ok || P.nblk != (P.n + cols - 1) / cols ||
             P.adaptive || !P.qres || !P.nuN)
             return hipErrorInvalidValue;
         if (dtype == 0) {

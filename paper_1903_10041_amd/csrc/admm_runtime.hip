@@ -383,11 +383,16 @@ static bool chain_loc_applies(const admm_problem *pr, const admm_settings *s) {
 }
 
 // With the consensus block, the launch that completes every pair in every
-// block wins while its tiles number about two per compute unit; past that
-// the split launch does (measured q = 200, n = 3600: split 16.5 us per
-// iteration, this one slower, the scenario-local chained one 17.7 us).
+// block wins while its tiles number at most one per compute unit; past that
+// the scenario-local one does (m = 2, n = 3600: 6.9 against 7.8 us at
+// q = 50, 200 tiles; 10.0 against 9.4 us at q = 100, 400 tiles).
 static bool chain_q_preferred(admm_context *ctx, const admm_problem *pr) {
-    return (int64_t)pr->q * ((pr->n + kChainBlock - 1) / kChainBlock) <= 2 * std::max(1, ctx->num_cu);
+    return (int64_t)pr->q * ((pr->n + kChainBlock - 1) / kChainBlock) <= std::max(1, ctx->num_cu);
+}
+
+int loc_cols(int m, int q, int n, int num_cu) {
+    if (m > 2) return 2;
+    return (int64_t)q * ((n + kChainBlock - 1) / kChainBlock) > 4 * (int64_t)std::max(1, num_cu) ? 8 : 4;
 }
 
 // Chained grid: one block per kChainBlock columns while that fits in
@@ -461,13 +466,17 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         break;
     default:
         R = persist_columns(ctx, dtype, m, n, q, false);
-        // with consensus the chained launch wins while its tiles fit about
-        // two per compute unit (measured: q = 100, n = 3600 faster than
-        // split, q = 200 slower): past that every block's pass over all
-        // m q pairs and its tiles in series cost more than the second
-        // launch, and the scenario-local chained launch, whose first-step
-        // tiles finish the consensus, runs slower than split too
+        // with consensus the chained launch that completes every pair in
+        // every block wins while its tiles fit one per compute unit; past
+        // that the scenario-local one (per-tile steps of the block's own
+        // scenario, several columns per thread), which also beats split
+        // (m = 2, n = 3600: 13.7 against 15.2 us at q = 200, 23.5 against
+        // 30.0 at q = 500)
         chain = R == 0 && (chain_applies(pr, s) || (chain_q_applies(pr, s) && chain_q_preferred(ctx, pr)));
+        if (R == 0 && !chain && chain_loc_applies(pr, s)) {
+            chain = true;
+            local = true;
+        }
         // past the 256 MB last-level cache the split sweep, with many more
         // waves in flight, streams HBM faster than the chained blocks'
         // chunks (measured m = 4, n = 2^22: 97 against 104 us)
@@ -488,7 +497,8 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
         chain_grid(ctx, n, nb, chunks);
         cpt = kChainBlock / kBlock * chunks;
     }
-    if (local) cpt = kLocBlock / kBlock;   // tiles of kLocBlock columns
+    // tiles of kLocBlock threads with loc_cols columns each
+    if (local) cpt = kLocBlock / kBlock * loc_cols(m, q, n, ctx->num_cu);
     const int nblk = (n + kBlock * cpt - 1) / (kBlock * cpt);
     P.persistent = R > 0;
     P.chain = local ? 2 : (chain ? 1 : 0);

@@ -133,3 +133,22 @@ def test_full_size_robust(ctx, c4_oracle, prec, launch):
     say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
     assert info["iters"] == 20
     assert dx <= tol_x and rel <= tol_obj
+
+
+def test_full_size_robust_q500_eight_columns(ctx):
+    """m = 2, q = 500, n = 3600 (3.6 M quartics): past four tiles of 1024
+    columns per compute unit the scenario-local launch gives each thread
+    eight columns; AUTO takes it. 20 FP64 iterations, every element against
+    the oracle (run on the host's cores), and the split launch alongside."""
+    p = W.phev_c4(q=500)
+    st, oi, _ = oracle.run(p, max_iter=20, nthreads=16)
+    for launch in (admm.LAUNCH_AUTO, admm.LAUNCH_SPLIT):
+        say(f"[full-size robust q=500] launch={launch}, 20 iterations")
+        s = admm.Settings(rho=tuple(p.rho), max_iter=20, eps_primal=0.0, eps_dual=0.0, precision=admm.F64,
+                          launch=launch)
+        x, info, _ = ctx.solve(p, s)
+        dx = float(np.abs(x - st["x"]).max())
+        rel = abs(info["objective"] - oi["objective"]) / (1 + abs(oi["objective"]))
+        say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
+        assert info["iters"] == 20
+        assert dx <= 1e-9 and rel <= 1e-10
