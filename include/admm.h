@@ -104,9 +104,9 @@ typedef enum { ADMM_SWEEP_GAUSS_SEIDEL = 0, ADMM_SWEEP_JACOBI = 1 } admm_sweep;
  *           when every block fits on the device at once (else
  *           ADMM_E_UNSUPPORTED).
  * CHAINED_LOCAL  for many scenarios: one launch per iteration, one block
- *           per tile of 256 threads with 4 or 8 columns each (m <= 2;
- *           8 once the tiles of 1024 columns exceed four per compute
- *           unit) or 2 (m <= 4), each completing the previous
+ *           per tile of 256 threads with 3, 4, 6 or 8 columns each (m <= 2:
+ *           3 while the grid fits one round of four waves per SIMD, else
+ *           the fewest that fits) or 2 (m <= 4), each completing the previous
  *           iteration's scalar steps for its own scenario only (the tile
  *           of the first step also forms the consensus); a check
  *           iteration adds one launch of a block per scenario that finishes

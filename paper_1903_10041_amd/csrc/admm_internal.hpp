@@ -15,9 +15,9 @@ constexpr int kChainBlock = 1024;    // threads per block of the chained iterati
 constexpr int kChainMaxBlocks = 512; // largest grid the chained iteration takes
 constexpr int kLocBlock = 256;       // threads per tile of the scenario-local chained launch
 // Columns per thread of that launch (its per-tile scalar steps are spread
-// over kLocBlock times as many columns): 2 for m <= 4; for m <= 2, 4, or 8
-// once the q ceil(n / 1024) tiles of 1024 columns exceed four per compute
-// unit (measured m = 2, n = 3600: 4 wins to q = 200, 8 at q = 500).
+// over kLocBlock times as many columns): 2 for m <= 4; for m <= 2, 3 while
+// the grid fits one round of four waves per SIMD, else the fewest of 4, 6,
+// 8 that fits (measured m = 2, n = 3600: 3 best to q = 200, 8 at q = 500).
 int loc_cols(int m, int q, int n, int num_cu);
 static_assert(kLocBlock == kBlock, "SolveParams::cpt counts the local launch's columns per thread in kBlock units");
 constexpr int kLocLdsPairs = 2048;   // m q up to which that launch stages the consensus terms in LDS

@@ -1646,15 +1646,19 @@ static void launch_loc(const SolveParams &P, int rs, hipStream_t s) {
     const unsigned g = (unsigned)(P.q * P.nblk);
     const size_t lds = P.m * P.q <= kLocLdsPairs ? (size_t)P.m * P.q * sizeof(double) : 0;
     const bool cons_only = !P.g0 && !P.blo && !P.want_codes && !P.jacobi && !P.xstep_project;
-    // P.cpt (columns per thread) is 8 or 4 for m <= 2 and 2 for m <= 4
+    // P.cpt (columns per thread) is 3, 4, 6 or 8 for m <= 2 and 2 for m <= 4
     if (cons_only) {
-        if (P.m <= 2 && P.cpt == 8) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
-        else if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
-        else k_loc<T, 4, MODE, CHECK, F_CONS, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
+        if (P.m > 2) k_loc<T, 4, MODE, CHECK, F_CONS, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 3) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 3><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 4) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 6) k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 6><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 2, MODE, CHECK, F_CONS, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
     } else {
-        if (P.m <= 2 && P.cpt == 8) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
-        else if (P.m <= 2) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
-        else k_loc<T, 4, MODE, CHECK, F_ALL, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
+        if (P.m > 2) k_loc<T, 4, MODE, CHECK, F_ALL, kLocBlock, 2><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 3) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 3><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 4) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 4><<<g, kLocBlock, lds, s>>>(P, rs);
+        else if (P.cpt == 6) k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 6><<<g, kLocBlock, lds, s>>>(P, rs);
+        else k_loc<T, 2, MODE, CHECK, F_ALL, kLocBlock, 8><<<g, kLocBlock, lds, s>>>(P, rs);
     }
     // a check iteration's steps and residuals, for the next launch's decision
     if (CHECK) {
@@ -1668,7 +1672,7 @@ bool chain_loc_fits(int m, int q) { return m <= 4 && (int64_t)m * q <= 4 * kChai
 hipError_t launch_chain(const SolveParams &P, int dtype, bool check, int rs, hipStream_t s) {
     if (P.chain == 2) {
         const int cols = kLocBlock * P.cpt;
-        const bool cpt_ok = P.m <= 2 ? (P.cpt == 4 || P.cpt == 8) : P.cpt == 2;
+        const bool cpt_ok = P.m <= 2 ? (P.cpt == 3 || P.cpt == 4 || P.cpt == 6 || P.cpt == 8) : P.cpt == 2;
         if (!P.consensus || !chain_loc_fits(P.m, P.q) || !cpt_ok || P.nblk != (P.n + cols - 1) / cols ||
             P.adaptive || !P.qres || !P.nuN)
             return hipErrorInvalidValue;

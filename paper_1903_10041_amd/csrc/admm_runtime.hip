@@ -392,7 +392,15 @@ static bool chain_q_preferred(admm_context *ctx, const admm_problem *pr) {
 
 int loc_cols(int m, int q, int n, int num_cu) {
     if (m > 2) return 2;
-    return (int64_t)q * ((n + kChainBlock - 1) / kChainBlock) > 4 * (int64_t)std::max(1, num_cu) ? 8 : 4;
+    // one round of waves at four per SIMD (the kernels stay under 128
+    // registers): 3 columns while the grid fits it, else the fewest of
+    // 4, 6, 8 that fit, else 8
+    const int64_t slots = 16 * (int64_t)std::max(1, num_cu);
+    for (int c : {3, 4, 6, 8}) {
+        const int64_t blocks = (int64_t)q * ((n + kLocBlock * c - 1) / (kLocBlock * c));
+        if (blocks * (kLocBlock / 64) <= slots) return c;
+    }
+    return 8;
 }
 
 // Chained grid: one block per kChainBlock columns while that fits in

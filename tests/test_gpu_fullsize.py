@@ -152,3 +152,21 @@ def test_full_size_robust_q500_eight_columns(ctx):
         say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
         assert info["iters"] == 20
         assert dx <= 1e-9 and rel <= 1e-10
+
+
+@pytest.mark.parametrize("q,n", [(300, 3000), (300, 3600)])
+def test_scenario_local_column_counts(ctx, q, n):
+    """The scenario-local launch's columns per thread depend on the grid:
+    q = 300 with n = 3000 takes 4, with n = 3600 takes 6 (three would need
+    more than one round of waves). 20 FP64 iterations from AUTO, every
+    element against the oracle."""
+    p = W.phev_c4(seed=21, q=q, n=n)
+    st, oi, _ = oracle.run(p, max_iter=20, nthreads=16)
+    say(f"[local columns] q={q} n={n}, 20 iterations")
+    s = admm.Settings(rho=tuple(p.rho), max_iter=20, eps_primal=0.0, eps_dual=0.0, precision=admm.F64)
+    x, info, _ = ctx.solve(p, s)
+    dx = float(np.abs(x - st["x"]).max())
+    rel = abs(info["objective"] - oi["objective"]) / (1 + abs(oi["objective"]))
+    say(f"   max|dx|={dx:.2e} rel obj={rel:.2e}")
+    assert info["iters"] == 20
+    assert dx <= 1e-9 and rel <= 1e-10
