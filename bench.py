@@ -466,14 +466,17 @@ def run_batch(args):
     ctx.solve_batch(dp, s)
     torch.cuda.synchronize()
     dt_list = time.perf_counter() - t2
-    # plain per-instance path on a sample of the same instances
-    sample = list(range(0, len(dp), max(1, len(dp) // args.plain_sample)))[:args.plain_sample]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for b in sample:
-        ctx.solve(dp[b], s)
-    torch.cuda.synchronize()
-    dt_plain = (time.perf_counter() - t1) / len(sample)
+    # plain per-instance path on a sample of the same instances (skipped
+    # with --plain-sample 0)
+    sample, dt_plain = [], None
+    if args.plain_sample > 0:
+        sample = list(range(0, len(dp), max(1, len(dp) // args.plain_sample)))[:args.plain_sample]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for b in sample:
+            ctx.solve(dp[b], s)
+        torch.cuda.synchronize()
+        dt_plain = (time.perf_counter() - t1) / len(sample)
     ctx.close()
     return {"workload": f"{len(probs)} instances, m ~ U{{2..8}}, n log-uniform [50, 4000], f32 storage, "
                         "residual 1e-4, rho_2 / n",
@@ -488,8 +491,8 @@ def run_batch(args):
                            "tuner_batch_device_ms": {"start": tune_ms0, "tuned": tune_ms1},
                            "ns_per_instance_iteration": {"block": np.round(ns[0], 1).tolist(),
                                                          "wave": np.round(ns[1], 1).tolist()}},
-            "plain_path_solves_per_s": 1.0 / dt_plain, "plain_path_sample": len(sample),
-            "speedup_vs_plain": (conv / dt) * dt_plain}
+            "plain_path_solves_per_s": 1.0 / dt_plain if dt_plain else None, "plain_path_sample": len(sample),
+            "speedup_vs_plain": (conv / dt) * dt_plain if dt_plain else None}
 
 
 def _serve_stream_run(ctx, streams, s, rate, seconds, seed, threads=4):

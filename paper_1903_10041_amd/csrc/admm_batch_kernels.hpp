@@ -185,6 +185,32 @@ __device__ __forceinline__ BInst uniform_inst(const BInst &I) {
     return u;
 }
 
+// The block's sweep over its instance's columns, NT apart.  For up to four
+// sources the next column's loads are issued before the current column's
+// update (two columns live); the m <= 8 class has no registers to spare
+// and loads each column as it starts.  The compiler barrier at the top of
+// each column keeps the per-source scalars read from LDS inside the loop
+// rather than held in registers.
+template <typename T, int MAXM, int MODE, bool CHECK, int NT>
+__device__ __forceinline__ void batch_columns(const SolveParams &P, int n, int tid, const Scal<MAXM> &sc,
+                                              Acc<MAXM> &acc) {
+    constexpr bool AHEAD = MAXM <= 4;
+    Col<T, MAXM> d;
+    if (AHEAD && tid < n) col_load(P, 0, tid, d);
+    for (int k = tid; k < n; k += NT) {
+        asm volatile("" ::: "memory");
+        Col<T, MAXM> dn;
+        if (AHEAD) {
+            if (k + NT < n) col_load(P, 0, k + NT, dn);
+        } else {
+            col_load(P, 0, k, d);
+        }
+        col_update<T, MAXM, MODE, CHECK, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
+        col_store(P, 0, k, d);
+        if (AHEAD) d = dn;
+    }
+}
+
 // Occupancy: with the descriptor uniform and the per-source scalars read
 // from LDS, the classes m <= 2 and m <= 4 fit 3 and 2 waves per SIMD
 // without spills; m <= 8 is held to 2 waves (256 registers).  NT is the
@@ -251,23 +277,8 @@ void k_batch(BatchParams B) {
             const Scal<MAXM> &sc = s_sc;
             Acc<MAXM> acc;
             acc.reset();
-            if (check) {
-                for (int k = tid; k < n; k += NT) {
-                    asm volatile("" ::: "memory");
-                    Col<T, MAXM> d;
-                    col_load(P, 0, k, d);
-                    col_update<T, MAXM, MODE, true, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
-                    col_store(P, 0, k, d);
-                }
-            } else {
-                for (int k = tid; k < n; k += NT) {
-                    asm volatile("" ::: "memory");
-                    Col<T, MAXM> d;
-                    col_load(P, 0, k, d);
-                    col_update<T, MAXM, MODE, false, F_JACOBI | F_PROJECT>(P, 0, k, d, sc, acc);
-                    col_store(P, 0, k, d);
-                }
-            }
+            if (check) batch_columns<T, MAXM, MODE, true, NT>(P, n, tid, sc, acc);
+            else batch_columns<T, MAXM, MODE, false, NT>(P, n, tid, sc, acc);
             block_sum_rows<MAXM, NT>(m, acc.gsum, lds, s_sum);
             if (check) {
                 // rows: dg-max of each source, then the demand and s-x
