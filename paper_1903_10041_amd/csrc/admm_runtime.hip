@@ -1218,7 +1218,16 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
         GraphEntry *gr = graph_find(ctx, P, L.dtype, more_iter, 0, off, true, x_out, xdt);
         if (!gr && (st = graph_build(ctx, P, L.dtype, more_iter, 0, off, true, s, &gr, x_out, xdt)) != ADMM_OK)
             return st;
-        if (hipGraphLaunch(gr->exec, s) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
+        // the run goes on the caller's stream itself, behind the caller's
+        // earlier work, with no wait between the two streams (the library's
+        // stream holds nothing unfinished here: continue_start synchronised
+        // any read it made); the next call on the library's stream orders
+        // itself after it through the join event
+        if (hipGraphLaunch(gr->exec, ctx->user) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
+        L.t += more_iter;      // planned; the device may have stopped earlier
+        L.t_exact = false;
+        ctx->last = L;
+        return ADMM_OK;
     } else {
         // a stop at the old iteration cap runs again; a converged solve stays
         HIPCHK(launch_set_run(P, ctx->lim, 1, s));
