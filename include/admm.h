@@ -252,8 +252,9 @@ admm_status admm_resume(admm_context *ctx, int32_t more_iter, double eps_primal,
  * back, and the device stops on its own at the thresholds or the new
  * iteration cap.  x_out (may be NULL): device memory of the problem's dtype
  * that receives x after those iterations, in stream order (only for a
- * solve of a problem in device memory).  Runs of up to 200 iterations are
- * one cached graph launched on the caller's stream itself.  A later
+ * solve of a problem in device memory).  The run's launches go on the
+ * caller's stream itself (up to 200 iterations as one cached graph, longer
+ * runs as cached chunk graphs).  A later
  * admm_resume (e.g. with more_iter = 0) returns x, the state and info.  A solve stopped at its
  * iteration cap runs on; a converged one stays stopped.  The resident
  * launch path waits for each of its launches.  Errors as admm_resume. */

@@ -135,8 +135,10 @@ admm_status prepare(admm_context *ctx, const admm_problem *pr, const admm_settin
 admm_status stage_problem(admm_context *ctx, const admm_problem *pr, const SolveParams &P, int dtype,
                           hipStream_t s);
 admm_status upload_limits(admm_context *ctx, const SolveParams &P, hipStream_t s);
+// Graphs are captured on `s`; `ls` (when given, only without polling) is
+// the stream the launches go on.
 admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll,
-                    bool graphs = true);
+                    bool graphs = true, hipStream_t ls = nullptr, bool use_ls = false);
 
 void batch_release(admm_context *ctx);
 int batch_class(int m);

@@ -870,12 +870,14 @@ constexpr long kSpanMax = 200;
 // instantiation).  On the chained path the state ends in slot 0 (the flush).
 // Returns with the work queued behind ctx->ev0 .. ctx->ev1 on `s`.
 admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStream_t s, int t0, bool poll,
-                    bool graphs) {
+                    bool graphs, hipStream_t ls, bool use_ls) {
+    // launches (and the events around them) go on `run`; captures on `s`
+    const hipStream_t run = use_ls && !poll ? ls : s;
     const long total = std::max(0L, (long)ctx->lim.max_iter - t0);
-    if (P.persistent) return iterate_persistent(ctx, P, dtype, s, total);
+    if (P.persistent) return iterate_persistent(ctx, P, dtype, s, total);   // callers keep `s` for it
     const int ce = P.check_every;
     const int chunk = chunk_for(ce);
-    HIPCHK(hipEventRecord(ctx->ev0, s));
+    HIPCHK(hipEventRecord(ctx->ev0, run));
     Ctrl *hc = ctx->hctrl;
     long issued = 0, segs = 0;
     int phase = 0, direct_used = 0;
@@ -899,10 +901,10 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
             seg = rem;
         }
         if (g) {
-            if (hipGraphLaunch(g->exec, s) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
+            if (hipGraphLaunch(g->exec, run) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
         } else {
             for (long c = 0; c < seg; ++c) {
-                const hipError_t e = launch_one(P, dtype, t + c + 1, (int)((phase + c) & 1), s);
+                const hipError_t e = launch_one(P, dtype, t + c + 1, (int)((phase + c) & 1), run);
                 if (e != hipSuccess) return fail(ADMM_E_DEVICE, std::string("launch: ") + hipGetErrorString(e));
             }
         }
@@ -924,8 +926,8 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
         }
     }
     // chained: the scalar steps of the last iteration, into slot 0
-    if (P.chain && launch_chain_flush(P, phase, s) != hipSuccess) return fail(ADMM_E_DEVICE, "flush launch failed");
-    HIPCHK(hipEventRecord(ctx->ev1, s));
+    if (P.chain && launch_chain_flush(P, phase, run) != hipSuccess) return fail(ADMM_E_DEVICE, "flush launch failed");
+    HIPCHK(hipEventRecord(ctx->ev1, run));
     return ADMM_OK;
 }
 
@@ -1225,6 +1227,17 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
         // itself after it through the join event
         if (hipGraphLaunch(gr->exec, ctx->user) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
         L.t += more_iter;      // planned; the device may have stopped earlier
+        L.t_exact = false;
+        ctx->last = L;
+        return ADMM_OK;
+    } else if (!P.persistent) {
+        // longer runs: chunk graphs captured on the library's stream and
+        // launched, like everything else of the run, on the caller's
+        // a stop at the old iteration cap runs again; a converged solve stays
+        HIPCHK(launch_set_run(P, ctx->lim, 1, ctx->user));
+        if ((st = iterate(ctx, P, L.dtype, s, L.t, false, true, ctx->user, true)) != ADMM_OK) return st;
+        if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, xdt, ctx->user));
+        L.t += more_iter;
         L.t_exact = false;
         ctx->last = L;
         return ADMM_OK;
