@@ -219,7 +219,10 @@ admm_status admm_create(admm_context **out, int device, size_t hbm_budget_bytes,
                         const admm_settings *defaults);
 
 /* HIP stream (hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on
- * which solve and solve_batch run; NULL = the default stream. */
+ * which solve and solve_batch run; NULL = the default stream.  Switching to
+ * another stream orders everything the context does afterwards after the
+ * work already queued on the old one (which must still exist at the
+ * switch); setting the same stream again does nothing. */
 admm_status admm_set_stream(admm_context *ctx, void *stream);
 
 /* Solve one instance.  settings NULL = the context's defaults; warm NULL =
@@ -254,7 +257,9 @@ admm_status admm_resume(admm_context *ctx, int32_t more_iter, double eps_primal,
  * that receives x after those iterations, in stream order (only for a
  * solve of a problem in device memory).  The run's launches go on the
  * caller's stream itself (up to 200 iterations as one cached graph, longer
- * runs as cached chunk graphs).  A later
+ * runs as cached chunk graphs), ordered after the caller's earlier work and
+ * after any work of this context still in flight (a stream switched with
+ * admm_set_stream included).  A later
  * admm_resume (e.g. with more_iter = 0) returns x, the state and info.  A solve stopped at its
  * iteration cap runs on; a converged one stays stopped.  The resident
  * launch path waits for each of its launches.  Errors as admm_resume. */

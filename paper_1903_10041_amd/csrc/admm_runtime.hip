@@ -251,7 +251,18 @@ extern "C" admm_status admm_create(admm_context **out, int device, size_t budget
 
 extern "C" admm_status admm_set_stream(admm_context *ctx, void *stream) {
     if (!ctx) return fail(ADMM_E_INVALID_ARG, "context is NULL");
-    ctx->user = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    const hipStream_t ns = (hipStream_t)stream;
+    if (ns != ctx->user) {
+        // what this context queued on the old stream comes before anything
+        // it does later: the library's stream waits for the old stream, and
+        // every later call follows the library's stream
+        DeviceGuard g(ctx->device);
+        hipError_t e = hipEventRecord(ctx->join, ctx->user);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ctx->own, ctx->join, 0);
+        if (e != hipSuccess) return fail(ADMM_E_DEVICE, std::string("stream switch: ") + hipGetErrorString(e));
+        ctx->user = ns;
+    }
     return ADMM_OK;
 }
 
@@ -1201,11 +1212,26 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     hipStream_t s = ctx->own;
-    HIPCHK(hipEventRecord(ctx->join, ctx->user));
-    HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    // the library's stream gets work here only to read the iteration count
+    // (when the last call left it unknown) and on the resident path: it
+    // follows the caller's stream then
+    if (ctx->last.valid && !ctx->last.t_exact) {
+        HIPCHK(hipEventRecord(ctx->join, ctx->user));
+        HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
+    }
     LastSolve L;
     admm_status st;
     if ((st = continue_start(ctx, more_iter, s, L)) != ADMM_OK) return st;
+    // the run on the caller's stream follows whatever the library's stream
+    // still holds (a wait only when it holds something: a wait on an idle
+    // stream still costs tens of microseconds)
+    auto follow_own = [&]() -> admm_status {
+        if (hipStreamQuery(s) != hipSuccess) {
+            HIPCHK(hipEventRecord(ctx->join, s));
+            HIPCHK(hipStreamWaitEvent(ctx->user, ctx->join, 0));
+        }
+        return ADMM_OK;
+    };
     if (x_out && L.mem != ADMM_DEVICE)
         return fail(ADMM_E_INVALID_ARG, "x_out of admm_iterate is device memory: the solve's problem was on the host");
     const SolveParams &P = L.P;
@@ -1221,10 +1247,10 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
         if (!gr && (st = graph_build(ctx, P, L.dtype, more_iter, 0, off, true, s, &gr, x_out, xdt)) != ADMM_OK)
             return st;
         // the run goes on the caller's stream itself, behind the caller's
-        // earlier work, with no wait between the two streams (the library's
-        // stream holds nothing unfinished here: continue_start synchronised
-        // any read it made); the next call on the library's stream orders
-        // itself after it through the join event
+        // earlier work and what the library's stream holds; the next call
+        // on the library's stream orders itself after the run through the
+        // join event
+        if ((st = follow_own()) != ADMM_OK) return st;
         if (hipGraphLaunch(gr->exec, ctx->user) != hipSuccess) return fail(ADMM_E_DEVICE, "graph launch failed");
         L.t += more_iter;      // planned; the device may have stopped earlier
         L.t_exact = false;
@@ -1232,8 +1258,10 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
         return ADMM_OK;
     } else if (!P.persistent) {
         // longer runs: chunk graphs captured on the library's stream and
-        // launched, like everything else of the run, on the caller's
-        // a stop at the old iteration cap runs again; a converged solve stays
+        // launched, like everything else of the run, on the caller's (after
+        // what the library's stream holds, as above); a stop at the old
+        // iteration cap runs again, a converged solve stays stopped
+        if ((st = follow_own()) != ADMM_OK) return st;
         HIPCHK(launch_set_run(P, ctx->lim, 1, ctx->user));
         if ((st = iterate(ctx, P, L.dtype, s, L.t, false, true, ctx->user, true)) != ADMM_OK) return st;
         if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, xdt, ctx->user));
@@ -1242,7 +1270,10 @@ extern "C" admm_status admm_iterate(admm_context *ctx, int32_t more_iter, void *
         ctx->last = L;
         return ADMM_OK;
     } else {
+        // the resident path, on the library's stream after the caller's
         // a stop at the old iteration cap runs again; a converged solve stays
+        HIPCHK(hipEventRecord(ctx->join, ctx->user));
+        HIPCHK(hipStreamWaitEvent(s, ctx->join, 0));
         HIPCHK(launch_set_run(P, ctx->lim, 1, s));
         if ((st = iterate(ctx, P, L.dtype, s, L.t, false)) != ADMM_OK) return st;
         if (x_out) HIPCHK(launch_unpack_x(P, L.dtype, x_out, xdt, s));

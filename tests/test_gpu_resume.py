@@ -212,3 +212,46 @@ def test_iterate_long_run_and_repeat(name):
     say(f"[iterate-long] {name}: iters {i['iters']} vs {i_ref['iters']}")
     assert i["iters"] == i_ref["iters"] == 455
     assert np.array_equal(x, x_ref)
+
+
+@pytest.mark.parametrize("name", ["c1-chained", "robust_q5-local", "c1-split"])
+def test_iterate_stream_order_on_a_side_stream(name):
+    """admm_iterate runs on the caller's stream: on a side stream (default
+    priority), a torch op queued right after it on that stream, with no
+    synchronisation between, sees the final x, for a short run (one cached
+    graph) and a long one (chunk graphs).  A resume from the default stream
+    right after, with nothing synchronised, follows the side stream's run
+    (switching streams joins the old one): it reports the full count and
+    the same x."""
+    import torch
+    mk, launch = CASES[name]
+    p = mk()
+    dev = torch.device("cuda:0")
+    t = W.Problem(**{k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) and k != "c" else v)
+                     for k, v in vars(p).items()})
+    t.c = p.c
+    say(f"[iterate-stream] {name}")
+    ctx = admm.Context(0)
+    side = torch.cuda.Stream(device=dev)
+    try:
+        x25, _, _ = ctx.solve(t, fixed(p, 25, launch=launch))
+        x455, _, _ = ctx.solve(t, fixed(p, 455, launch=launch))
+        x25, x455 = x25.clone(), x455.clone()
+        outs = []
+        for more, ref in ((20, x25), (450, x455)):
+            ctx.solve(t, fixed(p, 5, launch=launch))
+            torch.cuda.synchronize()
+            xo = torch.empty_like(ref)
+            with torch.cuda.stream(side):
+                ctx.iterate(more, x_out=xo)
+                y = xo * 2.0            # ordered after the run on the side stream only
+            xr, info, _ = ctx.resume(0)  # default stream, no synchronisation first
+            side.synchronize()
+            torch.cuda.synchronize()
+            outs.append((y, ref, xr, info["iters"], 5 + more))
+    finally:
+        ctx.close()
+    for y, ref, xr, iters, want in outs:
+        assert torch.equal(y, ref * 2.0)
+        assert iters == want
+        assert torch.equal(xr, ref)
