@@ -125,6 +125,25 @@ __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double 
         double x;
         if (qmin_f32_fast(A, B, C, D, (float)lo, (float)hi, x, code)) return x;
     }
+    if (MODE == MODE_MIXED) {
+        // 4A and 2C straight away (exact doublings of the grouping below,
+        // which the FP32 closed form and the Newton step take as they are)
+        const double rg1 = P.rho1 * g1, rg2x2 = (2.0 * P.rho1) * g2;
+        const double A4 = rg2x2 * g2;
+        const double B = rg1 * g2;
+        double C2 = fma(-rg2x2, tg, fma(f2, 2.0 * P.inv_q, fma(rg1, g1, P.rho3)));
+        double D = fma(-rg1, tg, fma(f1, P.inv_q, -P.rho3 * phi));
+        if (first_step) {
+            C2 += P.rho4;
+            D -= P.rho4 * cons;
+        }
+        double x;
+        if (A4 != 0.0 && qmin_mixed_fast(A4, B, C2, D, lo, hi, x, code)) return x;
+        if (A4 == 0.0) return qmin_quadratic(0.5 * C2, D, lo, hi, code);
+        const QRes r = qmin_f64_call(0.25 * A4, B, 0.5 * C2, D, lo, hi, project);
+        code = r.code;
+        return r.x;
+    }
     // the same coefficients, grouped so that rho1 g1 and rho1 g2 are
     // shared and the products fuse (12 operations rather than 15)
     const double rg1 = P.rho1 * g1, rg2 = P.rho1 * g2;
@@ -136,7 +155,6 @@ __device__ __forceinline__ double xstep(const SolveParams &P, double f2, double 
         C += 0.5 * P.rho4;
         D -= P.rho4 * cons;
     }
-    if (MODE == MODE_MIXED) return qmin_mixed(A, B, C, D, lo, hi, project, code);
     if (MODE == MODE_F32) {
         const QRes r = qmin_f64_call(A, B, C, D, lo, hi, project);
         code = r.code;
@@ -309,7 +327,8 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
                 lo = sc.lo[i];
                 hi = sc.hi[i];
             }
-            const double g_old = (g2 * xo[i] + g1) * xo[i] + g0;
+            // g0 = 0 adds nothing (the sign of a zero aside)
+            const double g_old = G0 ? (g2 * xo[i] + g1) * xo[i] + g0 : (g2 * xo[i] + g1) * xo[i];
             const double theta = g_old + sc.toff[i];
             const double others = (jacobi ? sum_old : sum_cur) - xo[i];
             const double phi = sm - others + y;
@@ -321,7 +340,7 @@ __device__ __forceinline__ void col_update(const SolveParams &P, int j, int k, C
             d.x[i] = (T)xn;
             if ((FEAT & F_CODES) && P.want_codes) P.codes[e] = (uint8_t)code;
             if ((FEAT & F_CONS) && k == 0) P.x1[j * m + i] = xn;
-            const double g_new = (g2 * xn + g1) * xn + g0;
+            const double g_new = G0 ? (g2 * xn + g1) * xn + g0 : (g2 * xn + g1) * xn;
             acc.gsum[i] += g_new;
             if (CHECK) {
                 const double dg = g_new - g_old;

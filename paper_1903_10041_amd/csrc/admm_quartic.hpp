@@ -153,37 +153,48 @@ __device__ __noinline__ QRes qmin_f64_call(double A, double B, double C, double 
 // |Q|^3 + R^2 before the FP32 one-real-root path is trusted.
 constexpr float kMixedDeltaMargin = 1e-4f;
 
-__device__ __forceinline__ double qmin_mixed(double A, double B, double C, double D, double lo, double hi,
-                                             int project, int &code) {
-    if (A == 0.0) return qmin_quadratic(C, D, lo, hi, code);
-    const float ia = rcp32((float)A);
-    const float b3 = 0.25f * (float)B * ia;
-    const float c = 0.5f * (float)C * ia;
-    const float d = 0.25f * (float)D * ia;
+// The FP32 one-real-root path and its FP64 Newton polish from the scaled
+// coefficients A4 = 4A > 0 and C2 = 2C (the cubic's b/3 = B/A4, c = C2/A4,
+// d = D/A4 and f' = ((A4 u + 3B) u + C2) u + D take them as they are; the
+// power-of-two scalings are exact, so every rounded value is the one the
+// unscaled form gives).  Returns false, x and code unset, when the case
+// needs the FP64 minimiser.
+__device__ __forceinline__ bool qmin_mixed_fast(double A4, double B, double C2, double D, double lo, double hi,
+                                                double &x, int &code) {
+    const float ia = rcp32((float)A4);
+    const float b3 = (float)B * ia;
+    const float c = (float)C2 * ia;
+    const float d = (float)D * ia;
     const float Q = c * (1.0f / 3.0f) - b3 * b3;
     const float R = 0.5f * (b3 * c - d) - b3 * b3 * b3;
     const float Q3 = Q * Q * Q;
     const float R2 = R * R;
     const float Delta = Q3 + R2;
-    if (Delta > kMixedDeltaMargin * (fabsf(Q3) + R2)) {
-        // Delta > 0 here, so |R| + sqrt(Delta) > 0 and S != 0
-        const float sq = sqrt32(Delta);
-        const float S = cbrt32(R + copysignf(sq, R));
-        const float T = -Q * rcp32(S);
-        double u = (double)(S + T - b3);
-        // one FP64 Newton step on f'(u) = 0
-        // f' = ((4A u + 3B) u + 2C) u + D and f'' = 3 (4A u + 2B) u + 2C,
-        // sharing 4A u and 2C
-        const double a4u = (4.0 * A) * u, c2 = 2.0 * C;
-        const double p1 = fma(fma(fma(3.0, B, a4u), u, c2), u, D);
-        const double p2 = fma(3.0 * fma(2.0, B, a4u), u, c2);
-        const double step = (double)((float)p1 * rcp32((float)p2));
-        if (p2 > 0.0 && fabs(step) <= 1e-3 * (1.0 + fabs(u))) {
-            u -= step;
-            code = 3 * BR_CARDANO + cstate(u, lo, hi);
-            return clampd(u, lo, hi);
-        }
-    }
+    if (!(Delta > kMixedDeltaMargin * (fabsf(Q3) + R2))) return false;
+    // Delta > 0 here, so |R| + sqrt(Delta) > 0 and S != 0
+    const float sq = sqrt32(Delta);
+    const float S = cbrt32(R + copysignf(sq, R));
+    const float T = -Q * rcp32(S);
+    double u = (double)(S + T - b3);
+    // one FP64 Newton step on f'(u) = 0
+    // f' = ((4A u + 3B) u + 2C) u + D and f'' = 3 (4A u + 2B) u + 2C,
+    // sharing 4A u and 2C
+    const double a4u = A4 * u;
+    const double p1 = fma(fma(fma(3.0, B, a4u), u, C2), u, D);
+    const double p2 = fma(3.0 * fma(2.0, B, a4u), u, C2);
+    const double step = (double)((float)p1 * rcp32((float)p2));
+    if (!(p2 > 0.0 && fabs(step) <= 1e-3 * (1.0 + fabs(u)))) return false;
+    u -= step;
+    code = 3 * BR_CARDANO + cstate(u, lo, hi);
+    x = clampd(u, lo, hi);
+    return true;
+}
+
+__device__ __forceinline__ double qmin_mixed(double A, double B, double C, double D, double lo, double hi,
+                                             int project, int &code) {
+    if (A == 0.0) return qmin_quadratic(C, D, lo, hi, code);
+    double x;
+    if (qmin_mixed_fast(4.0 * A, B, 2.0 * C, D, lo, hi, x, code)) return x;
     const QRes r = qmin_f64_call(A, B, C, D, lo, hi, project);
     code = r.code;
     return r.x;
