@@ -138,6 +138,10 @@ bool chain_q_fits(int m, int q, int n);   // the chained launch with consensus a
 bool chain_loc_fits(int m, int q);        // the scenario-local chained launch applies
 hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hipStream_t s);
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s);
+// The chained flush (q = 1, no consensus) and the copy of x into dst as one
+// launch; the same results as launch_chain_flush then launch_unpack_x.
+hipError_t launch_chain_flush_unpack(const SolveParams &P, int rs, int dtype, void *dst, int dst_dtype,
+                                     hipStream_t s);
 hipError_t launch_load_x(const SolveParams &P, int dtype, const void *src, int src_dtype,
                          const void *w_src, hipStream_t s);
 // precision: 0 FP64, 1 FP32 with FP64 polish, 2 FP32; codes may be null;

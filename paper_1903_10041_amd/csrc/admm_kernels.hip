@@ -498,12 +498,36 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
 // Completes a pending iteration of slot rs into slot 0 (one block), after
 // the last launch of a solve, so that the state rests in slot 0.
 template <int MAXM>
-__global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P, int rs) {
+__device__ __forceinline__ void chain_flush_block(const SolveParams &P, int rs) {
     __shared__ ChainShared<MAXM> sh;
     const double wd = (rs ? P.ctrl1 : P.ctrl)->wdiv;
     chain_prologue<MAXM, kChainBlock>(P, rs, sh);
     // a divisor decided here (or left by a launch that stopped) is pending
     chain_store<MAXM>(P, 0, sh, sh.t, 0, sh.bad, sh.f != 1.0 ? sh.f : wd);
+}
+
+template <int MAXM>
+__global__ __launch_bounds__(kChainBlock) void k_chain_flush(SolveParams P, int rs) {
+    chain_flush_block<MAXM>(P, rs);
+}
+
+// The flush and the copy of x out of a queued run in one launch: block 0
+// flushes (pair scalars and control block only), the other blocks copy x,
+// which the flush does not touch, into dst ([q][m][n], dtype D).
+template <int MAXM, typename T, typename D>
+__global__ __launch_bounds__(kChainBlock) void k_chain_flush_unpack(SolveParams P, int rs, D *dst) {
+    if (blockIdx.x == 0) {
+        chain_flush_block<MAXM>(P, rs);
+        return;
+    }
+    const int n = P.n, n_pad = P.n_pad;
+    const size_t E = (size_t)P.q * P.m * n;
+    for (size_t e = (blockIdx.x - 1) * (size_t)kChainBlock + threadIdx.x; e < E;
+         e += (size_t)(gridDim.x - 1) * kChainBlock) {
+        const size_t row = e / n;
+        const int k = (int)(e - row * n);
+        dst[e] = (D)((const T *)P.x)[row * n_pad + k];
+    }
 }
 
 // ---------------------------------------- chained, several scenarios
@@ -1805,6 +1829,28 @@ hipError_t launch_objective(const SolveParams &P, int dtype, double *scratch, hi
     else k_obj_part<float><<<kObjBlocks, kBlock, 0, s>>>(P, scratch);
     k_obj_final<<<1, kBlock, 0, s>>>(P, scratch);
     return hipGetLastError();
+}
+
+template <int MAXM>
+static hipError_t launch_flush_unpack_m(const SolveParams &P, int rs, int dtype, void *dst, int dst_dtype,
+                                        unsigned g, hipStream_t s) {
+    if (dtype == 0 && dst_dtype == 0) k_chain_flush_unpack<MAXM, double, double><<<g, kChainBlock, 0, s>>>(P, rs, (double *)dst);
+    else if (dtype == 0) k_chain_flush_unpack<MAXM, double, float><<<g, kChainBlock, 0, s>>>(P, rs, (float *)dst);
+    else if (dst_dtype == 0) k_chain_flush_unpack<MAXM, float, double><<<g, kChainBlock, 0, s>>>(P, rs, (double *)dst);
+    else k_chain_flush_unpack<MAXM, float, float><<<g, kChainBlock, 0, s>>>(P, rs, (float *)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_flush_unpack(const SolveParams &P, int rs, int dtype, void *dst, int dst_dtype,
+                                     hipStream_t s) {
+    if (P.chain != 1 || P.consensus || P.m > 4 || (rs != 0 && rs != 1)) return hipErrorInvalidValue;
+    const size_t E = (size_t)P.q * P.m * P.n;
+    size_t g = (E + kChainBlock - 1) / kChainBlock;
+    if (g > 1024) g = 1024;
+    if (g < 1) g = 1;
+    // one block more for the flush
+    if (P.m <= 2) return launch_flush_unpack_m<2>(P, rs, dtype, dst, dst_dtype, (unsigned)g + 1, s);
+    return launch_flush_unpack_m<4>(P, rs, dtype, dst, dst_dtype, (unsigned)g + 1, s);
 }
 
 hipError_t launch_unpack_x(const SolveParams &P, int dtype, void *dst, int dst_dtype, hipStream_t s) {

@@ -840,8 +840,12 @@ static admm_status graph_build(admm_context *ctx, const SolveParams &P, int dtyp
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = flush ? launch_set_run_more(P, chunk, s) : hipSuccess;
     for (int c = 0; c < chunk && e == hipSuccess; ++c) e = launch_one(P, dtype, offset + c + 1, (c + phase) & 1, s);
-    if (e == hipSuccess && flush && P.chain) e = launch_chain_flush(P, (chunk + phase) & 1, s);
-    if (e == hipSuccess && flush && xout) e = launch_unpack_x(P, dtype, xout, xdt, s);
+    if (e == hipSuccess && flush && xout && P.chain == 1 && !P.consensus) {
+        e = launch_chain_flush_unpack(P, (chunk + phase) & 1, dtype, xout, xdt, s);
+    } else {
+        if (e == hipSuccess && flush && P.chain) e = launch_chain_flush(P, (chunk + phase) & 1, s);
+        if (e == hipSuccess && flush && xout) e = launch_unpack_x(P, dtype, xout, xdt, s);
+    }
     if (e != hipSuccess) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(s, &junk);
