@@ -761,6 +761,19 @@ static int chunk_for(int check_every) {
     return c;
 }
 
+// Near the stop, segments of about half that: a solve waits for the
+// segment before last, so about two segments of no-op launches drain after
+// the device stops, while each segment boundary costs a few microseconds in
+// the stream; short segments pay only close to the end.
+static int chunk_near_for(int check_every) {
+    int c = check_every;
+    while (c < 20 || (c & 1)) c += check_every;
+    return c;
+}
+// "close to the end": the last polled check within this factor of both
+// thresholds
+constexpr double kNearStop = 3.0;
+
 // Persistent path: cooperative launches of at most kPersistChunk iterations
 // each, until the device stop flag is set.
 constexpr int kPersistChunk = 20000;
@@ -891,24 +904,25 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
     const long total = std::max(0L, (long)ctx->lim.max_iter - t0);
     if (P.persistent) return iterate_persistent(ctx, P, dtype, s, total);   // callers keep `s` for it
     const int ce = P.check_every;
-    const int chunk = chunk_for(ce);
+    const int chunk = chunk_for(ce), chunk_near = chunk_near_for(ce);
     HIPCHK(hipEventRecord(ctx->ev0, run));
     Ctrl *hc = ctx->hctrl;
     long issued = 0, segs = 0;
     int phase = 0, direct_used = 0;
-    bool done = total == 0;
+    bool done = total == 0, near = false;
     while (!done && issued < total) {
         const long t = t0 + issued;     // iterations completed before this segment
         const long rem = total - issued;
+        const int len = near ? chunk_near : chunk;
         long seg;
         GraphEntry *g = nullptr;
         if (t % ce != 0) {
             seg = std::min<long>(rem, ce - t % ce);
-        } else if (rem >= chunk) {
-            seg = chunk;
-            g = graphs ? graph_find(ctx, P, dtype, chunk, phase, 0, false) : nullptr;
+        } else if (rem >= len) {
+            seg = len;
+            g = graphs ? graph_find(ctx, P, dtype, len, phase, 0, false) : nullptr;
             if (!g && graphs && direct_used >= direct_chunks()) {
-                admm_status st = graph_build(ctx, P, dtype, chunk, phase, 0, false, s, &g);
+                admm_status st = graph_build(ctx, P, dtype, len, phase, 0, false, s, &g);
                 if (st != ADMM_OK) return st;
             }
             if (!g) ++direct_used;
@@ -937,7 +951,10 @@ admm_status iterate(admm_context *ctx, const SolveParams &P, int dtype, hipStrea
         else if (segs >= 2) wait_slot = slot ^ 1;         // the previous segment
         if (wait_slot >= 0) {
             if (hipEventSynchronize(ctx->fev[wait_slot]) != hipSuccess) return fail(ADMM_E_DEVICE, "event sync failed");
-            done = hc[wait_slot].done != 0;
+            const Ctrl &cw = hc[wait_slot];
+            done = cw.done != 0;
+            // fixed-count runs (thresholds 0) never count as near
+            near = cw.r < kNearStop * ctx->lim.eps_p && cw.sigma < kNearStop * ctx->lim.eps_d;
         }
     }
     // chained: the scalar steps of the last iteration, into slot 0
