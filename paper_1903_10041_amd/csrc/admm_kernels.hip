@@ -806,6 +806,24 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q_flush(SolveParams P, in
 // x_bar_1 (7c) from every pair's x_1 - nu of slot `in`, into xb[] (waves
 // i < m, result in lane 0's LDS write); callers synchronise after.
 // Loads go out eight at a time before they are added, in the same order.
+// One batch of eight pairs per lane (scenarios j0 + 64 r) of source wv.
+__device__ __forceinline__ void loc_xbar_load(const SolveParams &P, const double *x1, const double *nu, int j0,
+                                              int wv, double (&a)[8], double (&c)[8]) {
+    const int m = P.m, q = P.q;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int jj = j0 + 64 * r;
+        a[r] = jj < q ? x1[jj * m + wv] : 0.0;
+        c[r] = jj < q ? nu[jj * m + wv] : 0.0;
+    }
+}
+__device__ __forceinline__ void loc_xbar_add(const SolveParams &P, int j0, const double (&a)[8], const double (&c)[8],
+                                             double &s) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        if (j0 + 64 * r < P.q) s += a[r] - c[r];
+}
+
 template <int MAXM>
 __device__ __forceinline__ void loc_xbar(const SolveParams &P, const double *x1, const double *nu, double *xb) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = P.m, q = P.q;
@@ -813,15 +831,8 @@ __device__ __forceinline__ void loc_xbar(const SolveParams &P, const double *x1,
         double s = 0.0;
         for (int j0 = lane; j0 < q; j0 += 8 * 64) {
             double a[8], c[8];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int jj = j0 + 64 * r;
-                a[r] = jj < q ? x1[jj * m + wv] : 0.0;
-                c[r] = jj < q ? nu[jj * m + wv] : 0.0;
-            }
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-                if (j0 + 64 * r < q) s += a[r] - c[r];
+            loc_xbar_load(P, x1, nu, j0, wv, a, c);
+            loc_xbar_add(P, j0, a, c, s);
         }
         s = wave_sum(s);
         if (lane == 0) xb[wv] = s * P.inv_q;
@@ -833,28 +844,49 @@ struct LocPair {
     double lam, zoff, h, p;
     double pr, ps;           // residual terms (check)
 };
-__device__ __forceinline__ LocPair loc_pair(const SolveParams &P, const double *part, int j, int i,
-                                            double lam, double zoff, double h, double p, bool chk) {
+// Tiles u0 .. u0 + 15 of pair (j, i): sums, and on a check dg max / min.
+struct LocTiles {
+    double v[16], vx[16], vn[16];
+};
+__device__ __forceinline__ void loc_tiles_load(const SolveParams &P, const double *part, int j, int i, int u0,
+                                               bool chk, LocTiles &L) {
     const int m = P.m, nbs = P.nblk;
     const size_t slab = (size_t)P.q * nbs * m;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const size_t idx = ((size_t)j * nbs + (u0 + r < nbs ? u0 + r : u0)) * m + i;
+        L.v[r] = part[idx];
+        if (chk) { L.vx[r] = part[slab + idx]; L.vn[r] = part[2 * slab + idx]; }
+    }
+}
+__device__ __forceinline__ void loc_tiles_add(const SolveParams &P, int u0, bool chk, const LocTiles &L,
+                                              double &W, double &mx, double &mn) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (u0 + r < P.nblk) {
+            W += L.v[r];
+            if (chk) { mx = fmax(mx, L.vx[r]); mn = fmin(mn, L.vn[r]); }
+        }
+}
+
+__device__ __forceinline__ LocPair loc_pair_finish(const SolveParams &P, int i, double W, double mx, double mn,
+                                                   double lam, double zoff, double h, double p, bool chk);
+
+__device__ __forceinline__ LocPair loc_pair(const SolveParams &P, const double *part, int j, int i,
+                                            double lam, double zoff, double h, double p, bool chk) {
     // the scenario's tile partials, sixteen loads in flight before they
     // are added in tile order
     double W = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
-    for (int u0 = 0; u0 < nbs; u0 += 16) {
-        double v[16], vx[16], vn[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const size_t idx = ((size_t)j * nbs + (u0 + r < nbs ? u0 + r : u0)) * m + i;
-            v[r] = part[idx];
-            if (chk) { vx[r] = part[slab + idx]; vn[r] = part[2 * slab + idx]; }
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (u0 + r < nbs) {
-                W += v[r];
-                if (chk) { mx = fmax(mx, vx[r]); mn = fmin(mn, vn[r]); }
-            }
+    for (int u0 = 0; u0 < P.nblk; u0 += 16) {
+        LocTiles L;
+        loc_tiles_load(P, part, j, i, u0, chk, L);
+        loc_tiles_add(P, u0, chk, L, W, mx, mn);
     }
+    return loc_pair_finish(P, i, W, mx, mn, lam, zoff, h, p, chk);
+}
+
+__device__ __forceinline__ LocPair loc_pair_finish(const SolveParams &P, int i, double W, double mx, double mn,
+                                                   double lam, double zoff, double h, double p, bool chk) {
     const double nd = (double)P.n;
     const double kfac = P.rho2 / (P.rho1 + nd * P.rho2);
     const double Wd = W - nd * lam;                  // 1'(g(x) - lambda)
@@ -1071,13 +1103,66 @@ __global__ __launch_bounds__(kBlock) void k_loc_check(SolveParams P, int s) {
     __shared__ double red[kBlock / 64][2];
     const QSlot sl = qslot(P, s);
     const Ctrl *c = sl.ctrl;
-    if (c->done || c->pending != 1) return;
     const int j = blockIdx.x, m = P.m, nbs = P.nblk, tid = threadIdx.x;
     const double *part = s ? P.part : P.part1;      // what the launch that wrote slot s swept into
     const size_t slab = (size_t)P.q * nbs * m;
+    double pr = 0.0, ps = 0.0;
+    if (P.q <= 8 * 64 && nbs <= 16) {
+        // every read fits one batch (eight scenarios per lane, sixteen
+        // tiles): all go out before the control block is tested, so the
+        // kernel waits for memory once; the arithmetic and its order are
+        // those of the general path below
+        const int lane = tid & 63, wv = tid >> 6;
+        const int cdone = c->done, cpend = c->pending;
+        double a[8], cn[8];
+        if (wv < m) loc_xbar_load(P, sl.x1, sl.nu, lane, wv, a, cn);
+        const int pi = j * m + (tid < m ? tid : 0);
+        LocTiles L;
+        double lam = 0.0, zoff = 0.0, h = 0.0, p = 0.0, x1 = 0.0, nu = 0.0;
+        if (tid < m) {
+            loc_tiles_load(P, part, j, tid, 0, true, L);
+            lam = sl.lam[pi]; zoff = sl.zoff[pi]; h = sl.h[pi]; p = sl.p[pi];
+            x1 = sl.x1[pi]; nu = sl.nu[pi];
+        }
+        double t0 = 0.0, t1 = 0.0;
+        if (tid < nbs) {
+            const size_t tt = (size_t)j * nbs + tid;
+            t0 = part[3 * slab + 2 * tt];
+            t1 = part[3 * slab + 2 * tt + 1];
+        }
+        asm volatile("" ::: "memory");
+        if (cdone || cpend != 1) return;
+        if (wv < m) {
+            double sx = 0.0;
+            loc_xbar_add(P, lane, a, cn, sx);
+            sx = wave_sum(sx);
+            if (lane == 0) xb[wv] = sx * P.inv_q;
+        }
+        __syncthreads();
+        if (tid < m) {
+            double W = 0.0, mx = -DBL_MAX, mn = DBL_MAX;
+            loc_tiles_add(P, 0, true, L, W, mx, mn);
+            const LocPair o = loc_pair_finish(P, tid, W, mx, mn, lam, zoff, h, p, true);
+            const double res = xb[tid] - x1;         // (7h)
+            P.nuN[pi] = nu + res;
+            pr = fmax(o.pr, fabs(res));
+            ps = o.ps;
+            sl.lam[pi] = o.lam; sl.zoff[pi] = o.zoff; sl.h[pi] = o.h; sl.p[pi] = o.p;
+        }
+        if (tid < nbs) {
+            pr = fmax(pr, t0);
+            ps = fmax(ps, P.rho3 * t1);
+        }
+        double r, sg;
+        loc_block_max2<kBlock>(pr, ps, red, r, sg);
+        if (tid == 0) { P.qres[2 * j] = r; P.qres[2 * j + 1] = sg; }
+        if (j == 0 && tid < m) sl.xbar1[tid] = xb[tid];
+        if (j == 0 && tid == 0) sl.ctrl->pending = 2;
+        return;
+    }
+    if (c->done || c->pending != 1) return;
     loc_xbar<MAXM>(P, sl.x1, sl.nu, xb);
     __syncthreads();
-    double pr = 0.0, ps = 0.0;
     if (tid < m) {
         const int pi = j * m + tid;
         const LocPair o = loc_pair(P, part, j, tid, sl.lam[pi], sl.zoff[pi], sl.h[pi], sl.p[pi], true);
