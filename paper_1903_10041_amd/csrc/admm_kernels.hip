@@ -422,6 +422,55 @@ __device__ __forceinline__ void chain_partials(const SolveParams &P, double *par
     }
 }
 
+// As chain_partials, the sums transposed through LDS: every thread writes
+// its m sums, then wave i adds source i's NT values (NT / 64 per lane in
+// thread order, then across the wave), so one wave reduction per source in
+// place of one per source in every wave.  The check maxima and minima go
+// the way of chain_partials.
+template <int MAXM, int NT>
+__device__ __forceinline__ void chain_partials_tr(const SolveParams &P, double *part, int tile, const Acc<MAXM> &acc,
+                                                  bool check, double (*red)[3 * MAXM + 2], double (*tr)[NT],
+                                                  size_t slab) {
+    constexpr int NW = NT / 64;
+    static_assert(NW >= MAXM, "one wave per source");
+    const int m = P.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i)
+        if (i < m) tr[i][tid] = acc.gsum[i];
+    if (check) {
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i) {
+            if (i < m) {
+                const double a = wave_max(acc.dgmax[i]), b = wave_min(acc.dgmin[i]);
+                if (lane == 0) { red[wv][MAXM + i] = a; red[wv][2 * MAXM + i] = b; }
+            }
+        }
+        const double a = wave_max(acc.rdem), b = wave_max(acc.sig3);
+        if (lane == 0) { red[wv][3 * MAXM] = a; red[wv][3 * MAXM + 1] = b; }
+    }
+    __syncthreads();
+    if (wv < m) {
+        double v = tr[wv][lane];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v += tr[wv][w * 64 + lane];
+        v = wave_sum(v);
+        if (lane == 0) part[(size_t)tile * m + wv] = v;
+    }
+    if (check) {
+        if (tid < m) {
+            double a = red[0][MAXM + tid], b = red[0][2 * MAXM + tid];
+            for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][MAXM + tid]); b = fmin(b, red[w][2 * MAXM + tid]); }
+            part[slab + (size_t)tile * m + tid] = a;
+            part[2 * slab + (size_t)tile * m + tid] = b;
+        } else if (tid == 64) {
+            double a = red[0][3 * MAXM], b = red[0][3 * MAXM + 1];
+            for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][3 * MAXM]); b = fmax(b, red[w][3 * MAXM + 1]); }
+            part[3 * slab + 2 * (size_t)tile] = a;
+            part[3 * slab + 2 * (size_t)tile + 1] = b;
+        }
+    }
+}
+
 template <typename T, int MAXM, int MODE, bool CHECK, int FEAT, int ME, bool MULTI>
 __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
     const int ws = rs ^ 1;
@@ -486,8 +535,9 @@ __global__ __launch_bounds__(kChainBlock) void k_chain(SolveParams P, int rs) {
             }
         }
     }
-    chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red,
-                                      (size_t)P.nblk * P.m);
+    __shared__ double tr[MAXM][kChainBlock];
+    chain_partials_tr<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, blockIdx.x, acc, CHECK, red, tr,
+                                         (size_t)P.nblk * P.m);
     if (blockIdx.x == 0) {
         const int t1 = sh.t + 1;
         const int bad = sh.bad | (((t1 % P.check_every) == 0) != CHECK ? 2 : 0);
@@ -1090,7 +1140,8 @@ __global__ __launch_bounds__(NT) void k_loc(SolveParams P, int rs) {
         }
         if (cc + 1 < CPT) d = dn;
     }
-    chain_partials<MAXM, NT>(P, rs ? P.part1 : P.part, tile, acc, CHECK, red, (size_t)P.q * nbs * m);
+    __shared__ double tr[MAXM][NT];
+    chain_partials_tr<MAXM, NT>(P, rs ? P.part1 : P.part, tile, acc, CHECK, red, tr, (size_t)P.q * nbs * m);
 }
 
 // Finishes a check iteration's steps for scenario blockIdx.x in slot s
