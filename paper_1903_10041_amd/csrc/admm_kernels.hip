@@ -769,6 +769,7 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) 
     const int nbs = P.nblk, ntile = P.q * nbs;
     __shared__ ChainQShared<MAXM> sh;
     __shared__ double red[kChainBlock / 64][3 * MAXM + 2];
+    __shared__ double tr[MAXM][kChainBlock];
     const Ctrl *cin = rs ? P.ctrl1 : P.ctrl;
     const bool stopped = cin->done;
     // tiles (scenario j, column block b) are dealt round robin; the first
@@ -810,10 +811,10 @@ __global__ __launch_bounds__(kChainBlock) void k_chain_q(SolveParams P, int rs) 
             col_update<T, MAXM, MODE, CHECK, FEAT>(Q, j, k, d, sc, acc);
             col_store<T, MAXM>(Q, j, k, d);
         }
-        chain_partials<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, tl, acc, CHECK, red, (size_t)ntile * m);
+        chain_partials_tr<MAXM, kChainBlock>(P, rs ? P.part1 : P.part, tl, acc, CHECK, red, tr, (size_t)ntile * m);
         tl += gridDim.x;
         if (tl >= ntile) break;
-        __syncthreads();             // red is reused by the next tile
+        __syncthreads();             // red and tr are reused by the next tile
         j = tl / nbs;
         b = tl - j * nbs;
         k = b * kChainBlock + threadIdx.x;
