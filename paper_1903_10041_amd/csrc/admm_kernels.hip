@@ -380,53 +380,12 @@ __device__ __forceinline__ void chain_store(const SolveParams &P, int ws, const 
     }
 }
 
-// Block sums of one tile's accumulators: wave reductions, then the waves'
-// results in order.  Layout as the split path: g-sum [nblk][m], dg-max,
-// dg-min, then residual maxima [nblk][2].
-template <int MAXM, int NT>
-__device__ __forceinline__ void chain_partials(const SolveParams &P, double *part, int tile, const Acc<MAXM> &acc,
-                                               bool check, double (*red)[3 * MAXM + 2], size_t slab) {
-    constexpr int NW = NT / 64;
-    const int m = P.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-#pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-        if (i < m) {
-            const double v = wave_sum(acc.gsum[i]);
-            if (lane == 0) red[wv][i] = v;
-            if (check) {
-                const double a = wave_max(acc.dgmax[i]), b = wave_min(acc.dgmin[i]);
-                if (lane == 0) { red[wv][MAXM + i] = a; red[wv][2 * MAXM + i] = b; }
-            }
-        }
-    }
-    if (check) {
-        const double a = wave_max(acc.rdem), b = wave_max(acc.sig3);
-        if (lane == 0) { red[wv][3 * MAXM] = a; red[wv][3 * MAXM + 1] = b; }
-    }
-    __syncthreads();
-    if (tid < m) {
-        double s = red[0][tid];
-        for (int w = 1; w < NW; ++w) s += red[w][tid];
-        part[(size_t)tile * m + tid] = s;
-        if (check) {
-            double a = red[0][MAXM + tid], b = red[0][2 * MAXM + tid];
-            for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][MAXM + tid]); b = fmin(b, red[w][2 * MAXM + tid]); }
-            part[slab + (size_t)tile * m + tid] = a;
-            part[2 * slab + (size_t)tile * m + tid] = b;
-        }
-    } else if (check && tid == 64) {
-        double a = red[0][3 * MAXM], b = red[0][3 * MAXM + 1];
-        for (int w = 1; w < NW; ++w) { a = fmax(a, red[w][3 * MAXM]); b = fmax(b, red[w][3 * MAXM + 1]); }
-        part[3 * slab + 2 * (size_t)tile] = a;
-        part[3 * slab + 2 * (size_t)tile + 1] = b;
-    }
-}
-
-// As chain_partials, the sums transposed through LDS: every thread writes
-// its m sums, then wave i adds source i's NT values (NT / 64 per lane in
-// thread order, then across the wave), so one wave reduction per source in
-// place of one per source in every wave.  The check maxima and minima go
-// the way of chain_partials.
+// Block sums of one tile's accumulators (layout as the split path: g-sum
+// [nblk][m], dg-max, dg-min, then residual maxima [nblk][2]).  The sums go
+// through LDS: every thread writes its m sums, then wave i adds source i's
+// NT values (NT / 64 per lane in thread order, then across the wave), one
+// wave reduction per source per block.  The check maxima and minima are
+// reduced in each wave, then over the waves in order.
 template <int MAXM, int NT>
 __device__ __forceinline__ void chain_partials_tr(const SolveParams &P, double *part, int tile, const Acc<MAXM> &acc,
                                                   bool check, double (*red)[3 * MAXM + 2], double (*tr)[NT],
